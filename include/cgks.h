@@ -1,0 +1,206 @@
+/*
+ * cgks.h -- C ABI of the MI355X multigrid compact gas-kinetic scheme library.
+ *
+ * Method: multigrid compact gas-kinetic scheme (CGKS) for steady flow on 3-D
+ * hybrid tet/pyramid/prism/hex meshes, arXiv 2402.02075 (Liu, Ji, Mao, Ding,
+ * Xu).  Fine level: third-order CGKS (HWENO reconstruction, BGK interface
+ * solution at face Gauss points, Gauss-Green update of cell-averaged
+ * gradients); coarse levels: first-order KFVS with forward Euler, on meshes
+ * built by two-step random-hash agglomeration; three-level V-cycle.
+ *
+ * Conventions for every call:
+ *  - Return value: CGKS_OK (0) or a negative cgks_status; cgks_last_error()
+ *    gives a message.  No C++ exception crosses this boundary.
+ *  - "device" pointers are HIP device allocations (e.g. torch CUDA tensors on
+ *    ROCm), used stream-ordered on the stream given to cgks_set_stream (the
+ *    null stream by default).  The library never frees caller memory.
+ *    "host" pointers are read or written before the call returns.
+ *  - Cell fields are FP64, component-major, in the caller's cell order:
+ *      W[c*N + i]        c = rho, rho u, rho v, rho w, rho E      (5 x N)
+ *      G[(3c+d)*N + i]   cell average of dW_c/dx_d, d = x, y, z    (15 x N)
+ *      alpha[i]          gradient compression factor               (N)
+ *  - No call synchronises the device except where stated (mesh set-up,
+ *    agglomeration, and the once-per-cycle residual read of cgks_vcycle).
+ *  - One context per host thread; contexts are independent.
+ */
+#ifndef CGKS_H
+#define CGKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cgks_ctx cgks_ctx;
+
+typedef enum {
+    CGKS_OK = 0,
+    CGKS_E_ARG = -1,       /* invalid argument; nothing written */
+    CGKS_E_MESH = -2,      /* invalid or non-conforming mesh; nothing written */
+    CGKS_E_DEVICE = -3,    /* HIP runtime error */
+    CGKS_E_NONFINITE = -4, /* NaN or Inf in a state */
+    CGKS_E_PHYS = -5,      /* non-positive density or pressure; message names the first cell */
+    CGKS_E_NOCONV = -6,    /* cgks_vcycle: max_cycles reached before the requested drop */
+    CGKS_E_STATE = -7      /* call out of order (e.g. no mesh, no hierarchy) */
+} cgks_status;
+
+/* element types: the node count, VTK node order */
+enum { CGKS_TET = 4, CGKS_PYR = 5, CGKS_PRISM = 6, CGKS_HEX = 8 };
+/* boundary kinds */
+enum { CGKS_BC_SLIP = 1, CGKS_BC_NOSLIP_ADIABATIC = 2, CGKS_BC_FARFIELD = 3 };
+
+typedef struct {
+    double gamma;        /* ratio of specific heats (1.4) */
+    double mu;           /* dynamic viscosity, constant (0 for inviscid) */
+    double prandtl;      /* Prandtl number (1 = BGK value, no correction) */
+    double cfl;          /* CFL number of the local time step (fine and coarse) */
+    double eps_tau;      /* inviscid collision time tau_n = eps dt + ...  (0.01) */
+    double c_tau;        /* pressure-jump coefficient C of tau_n (1) */
+    double weno_eps;     /* epsilon of the nonlinear weights (1e-5) */
+    double gamma_lin;    /* linear weight gamma_2 of the large stencil (0.5) */
+    double skew_delta;   /* agglomeration: accept if the virtual centre is within delta V^(1/3) (0.25) */
+    double skew_sin;     /* agglomeration: or if the angle to the face plane has sine >= this (sin 10 deg) */
+    int32_t viscous;     /* 0 inviscid, 1 Navier-Stokes */
+    int32_t levels;      /* multigrid levels including the fine one (3) */
+    int32_t passes;      /* agglomeration passes per coarse level (3) */
+    int32_t precision;   /* 0 FP64 everywhere, 1 mixed (FP32 coarse levels, transfers and flux evaluation) */
+    int32_t nu_pre[8];   /* pre-smoothing sweeps per level (1) */
+    int32_t nu_post[8];  /* post-smoothing sweeps per level (0) */
+    double mixed_switch; /* mixed precision: FP64 flux once the residual drop is below this (1e-6) */
+    uint64_t seed;       /* hash seed multiplier s (1 reproduces the paper's hash) */
+} cgks_params;
+
+/* Fill *p with the defaults above. */
+cgks_status cgks_default_params(cgks_params *p);
+
+/* Create a context on the current HIP device. */
+cgks_status cgks_create(const cgks_params *p, cgks_ctx **out);
+void cgks_destroy(cgks_ctx *ctx);
+const char *cgks_last_error(const cgks_ctx *ctx);
+
+/* Replace the parameters (mesh and hierarchy are kept; levels/passes/seed take effect at the next agglomerate). */
+cgks_status cgks_set_params(cgks_ctx *ctx, const cgks_params *p);
+
+/* Stream for all later work (a hipStream_t; NULL = null stream). */
+cgks_status cgks_set_stream(cgks_ctx *ctx, void *hip_stream);
+
+/*
+ * Mesh (paper Sec. 2.2: hybrid cells, linear iso-parametric faces; 3 Gauss
+ * points on a triangle, 4 on a quadrilateral).  All host arrays, copied:
+ *   xyz[3*n_nodes] interleaved coordinates;
+ *   ctype[n_cells] node count of each cell, cnode_ptr[n_cells+1] / cnode[] its nodes;
+ *   bnode_ptr[n_bfaces+1] / bnode[] / btag[n_bfaces] boundary faces (3 or 4 nodes, tag 1..63);
+ *   node_canon[n_nodes] or NULL: nodes with equal canonical id are periodic images
+ *   (faces whose canonical node sets match are joined across the period).
+ * Every cell face must be shared by two cells or listed once as a boundary face
+ * (else CGKS_E_MESH).  Computes geometry and reconstruction operators on the device.
+ * Synchronises.
+ */
+cgks_status cgks_set_mesh(cgks_ctx *ctx, int64_t n_nodes, const double *xyz, int64_t n_cells, const uint8_t *ctype,
+                          const int64_t *cnode_ptr, const int64_t *cnode, int64_t n_bfaces, const int64_t *bnode_ptr,
+                          const int64_t *bnode, const int32_t *btag, const int64_t *node_canon);
+
+/* Boundary condition of a tag (1..63).  prim = far-field rho, u, v, w, p (host, used by CGKS_BC_FARFIELD). */
+cgks_status cgks_set_bc(cgks_ctx *ctx, int32_t tag, int32_t kind, const double *prim);
+
+/*
+ * Sizes (host out[16]): [0] cells, [1] faces, [2] interior faces, [3] boundary faces,
+ * [4] Gauss points, [5] hierarchy levels built, [6..13] cells per level.
+ */
+cgks_status cgks_mesh_info(const cgks_ctx *ctx, int64_t *out);
+
+/* Geometry (device out, caller order, each nullable): vol[N], cen[3N] (component-major), mom2[6N]
+ * second moments about the centroid, order xx yy zz xy yz xz, component-major. */
+cgks_status cgks_geometry(cgks_ctx *ctx, double *vol, double *cen, double *mom2);
+
+/*
+ * Local time step (paper Secs. 1, 4.3: local time stepping on every level):
+ * dt[i] = CFL |Omega_i| / sum_p lambda_p S_p, lambda_p = |U.n_p| + c + 2 mu S_p/(rho |Omega_i|).
+ * W: device 5N in, dt: device N out.
+ */
+cgks_status cgks_local_dt(cgks_ctx *ctx, const double *W, double *dt);
+
+/*
+ * HWENO reconstruction (paper Sec. 3): per cell and component the 10 monomial
+ * coefficients of R(x) about the cell centroid, order 1, dx, dy, dz, dx^2, dy^2,
+ * dz^2, dxdy, dydz, dxdz.  coef: device [50 N], coef[(10 c + k) N + i].
+ */
+cgks_status cgks_reconstruct(cgks_ctx *ctx, const double *W, const double *G, const double *alpha, double *coef);
+
+/*
+ * Fine CGKS residual (paper Eqs. semidiscrete, 2nd-flux, gauss-formula; Sec. 3.3):
+ *   R[5N]         = - sum_p S_p sum_k w_k F(x_pk).n_p, F time-averaged over the face step
+ *                   dt_f = min(dt_L, dt_R) of the local steps;
+ *   G_new[15N]    = alpha_new / |Omega| * sum_p sum_k w_k W_pk(dt_f) n_pk S_p;
+ *   alpha_new[N]  = product over interior-face Gauss points of 1/(1 + A^2).
+ * Inputs W, G, alpha (alpha of the previous update, scales the Green-Gauss p^1).
+ * G_new and alpha_new may be NULL (residual only).  All device.
+ */
+cgks_status cgks_residual(cgks_ctx *ctx, const double *W, const double *G, const double *alpha, double *R,
+                          double *G_new, double *alpha_new);
+
+/*
+ * One explicit step in place on device W, G, alpha.
+ *   dt_global <= 0: fine smoother W += dt_i/|Omega_i| R with local steps (paper Eq. smo);
+ *   dt_global  > 0: two-stage fourth-order step with this global step.
+ * resnorm (device, nullable) receives sqrt(mean_i (R_rho,i/|Omega_i|)^2) of the step (smoother only).
+ */
+cgks_status cgks_step(cgks_ctx *ctx, double *W, double *G, double *alpha, double dt_global, double *resnorm);
+
+/*
+ * Synchronise and report kernel-detected state errors: CGKS_E_PHYS (with the
+ * first offending cell in the message) if any Gauss-point state had
+ * non-positive density or pressure since the previous check, else CGKS_OK.
+ */
+cgks_status cgks_check(cgks_ctx *ctx);
+
+/* RMS of R_rho/|Omega| (device R in, device scalar out). */
+cgks_status cgks_residual_norm(cgks_ctx *ctx, const double *R, double *out);
+
+/*
+ * Agglomeration on a raw graph (paper Sec. 4.1, Algorithm 1), P passes.
+ * Device inputs: V[n], P[3n] first moments (V*centroid, interleaved xyz),
+ * pair_a[m] < pair_b[m] (int32, lexicographically sorted, no duplicates),
+ * S[m] face areas, M[3m] first area moments (interleaved), A[3m] area vectors a->b.
+ * Device outputs: f2c[n] (int32, coarse ids numbered by smallest member),
+ * Vc[n], Pc[3n] (first *n_coarse valid).  Host out: n_coarse, m_coarse, stats[4*passes]
+ * (selected, skew-accepted, merged, new pair count per pass; nullable).
+ * Deterministic: identical inputs give identical outputs; synchronises.
+ */
+cgks_status cgks_agglomerate_graph(cgks_ctx *ctx, int64_t n, const double *V, const double *P, int64_t m,
+                                   const int32_t *pair_a, const int32_t *pair_b, const double *S, const double *M,
+                                   const double *A, int32_t passes, int32_t *f2c, double *Vc, double *Pc,
+                                   int64_t *n_coarse, int64_t *m_coarse, int64_t *stats);
+
+/* Build the multigrid hierarchy on the context's mesh (params.levels, .passes, .seed). Synchronises. */
+cgks_status cgks_agglomerate(cgks_ctx *ctx);
+
+/* Level map: f2c[n_{level-1}] (device int32) from level-1 cells to level cells; level >= 1. */
+cgks_status cgks_level_map(cgks_ctx *ctx, int32_t level, int32_t *f2c);
+
+/* Coarse KFVS residual on level >= 1 (paper Secs. 1, 4.2): R = - sum S n.F_kfvs. Device W, R (5 N_l). */
+cgks_status cgks_kfvs_residual(cgks_ctx *ctx, int32_t level, const double *W, double *R);
+
+/* Restriction to level >= 1 (paper Sec. 4.2): Wc = sum V W / Vc, Rc = sum R (either pair nullable). */
+cgks_status cgks_restrict(cgks_ctx *ctx, int32_t level, const double *Wf, const double *Rf, double *Wc, double *Rc);
+
+/* Prolongation (paper Sec. 4.2 correction): Wf[i] += dWc[f2c[i]] from level to level-1. */
+cgks_status cgks_prolong(cgks_ctx *ctx, int32_t level, const double *dWc, double *Wf);
+
+/*
+ * V-cycles (paper Sec. 4.2, Fig. Procedure): fine smoothing (nu_pre[0]), fine residual at the
+ * smoothed state restricted with the volume-weighted state, forcing term, coarse
+ * KFVS sweeps, recursion, correction; repeated until the residual drops by tol_drop
+ * relative to the first cycle or max_cycles.  In place on device W, G, alpha.
+ * hist (host, nullable, max_cycles) receives the residual norm of each cycle;
+ * *n_done the cycles run.  Reads one scalar per cycle (synchronises each cycle).
+ * Returns CGKS_E_NOCONV if the drop was not reached (state and history valid).
+ */
+cgks_status cgks_vcycle(cgks_ctx *ctx, double *W, double *G, double *alpha, int32_t max_cycles, double tol_drop,
+                        double *hist, int32_t *n_done);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,251 @@
+"""Thin Python binding of libcgks (the C ABI in include/cgks.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libcgks.so.  PyTorch supplies device memory and the current HIP stream.  If the
+shared library is missing the import fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcgks.so")
+
+OK, E_ARG, E_MESH, E_DEVICE, E_NONFINITE, E_PHYS, E_NOCONV, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
+BC_SLIP, BC_NOSLIP_ADIABATIC, BC_FARFIELD = 1, 2, 3
+
+# symbols the header declares (checked by the CPU test suite)
+EXPORTS = ["cgks_default_params", "cgks_create", "cgks_destroy", "cgks_last_error", "cgks_set_params",
+           "cgks_set_stream", "cgks_set_mesh", "cgks_set_bc", "cgks_mesh_info", "cgks_geometry", "cgks_local_dt",
+           "cgks_reconstruct", "cgks_residual", "cgks_step", "cgks_check", "cgks_residual_norm",
+           "cgks_agglomerate_graph", "cgks_agglomerate", "cgks_level_map", "cgks_kfvs_residual", "cgks_restrict",
+           "cgks_prolong", "cgks_vcycle"]
+
+
+class Params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double), ("cfl", C.c_double),
+                ("eps_tau", C.c_double), ("c_tau", C.c_double), ("weno_eps", C.c_double), ("gamma_lin", C.c_double),
+                ("skew_delta", C.c_double), ("skew_sin", C.c_double), ("viscous", C.c_int32), ("levels", C.c_int32),
+                ("passes", C.c_int32), ("precision", C.c_int32), ("nu_pre", C.c_int32 * 8),
+                ("nu_post", C.c_int32 * 8), ("mixed_switch", C.c_double), ("seed", C.c_uint64)]
+
+
+class CgksError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cgks error {code}: {msg}")
+        self.code = code
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not built: run __graft_entry__.build() (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        sig = {
+            "cgks_default_params": [P], "cgks_create": [P, P], "cgks_set_params": [P, P], "cgks_set_stream": [P, P],
+            "cgks_set_mesh": [P, I64, P, I64, P, P, P, I64, P, P, P, P], "cgks_set_bc": [P, I32, I32, P],
+            "cgks_mesh_info": [P, P], "cgks_geometry": [P, P, P, P], "cgks_local_dt": [P, P, P],
+            "cgks_reconstruct": [P, P, P, P, P], "cgks_residual": [P, P, P, P, P, P, P],
+            "cgks_step": [P, P, P, P, D, P], "cgks_check": [P], "cgks_residual_norm": [P, P, P],
+            "cgks_agglomerate_graph": [P, I64, P, P, I64, P, P, P, P, P, I32, P, P, P, P, P, P],
+            "cgks_agglomerate": [P], "cgks_level_map": [P, I32, P], "cgks_kfvs_residual": [P, I32, P, P],
+            "cgks_restrict": [P, I32, P, P, P, P], "cgks_prolong": [P, I32, P, P],
+            "cgks_vcycle": [P, P, P, P, I32, D, P, P],
+        }
+        for name, args in sig.items():
+            if not hasattr(L, name):
+                continue
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.cgks_destroy.argtypes = [P]
+        L.cgks_destroy.restype = None
+        L.cgks_last_error.argtypes = [P]
+        L.cgks_last_error.restype = C.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().cgks_default_params(C.byref(p))
+    for k, v in kw.items():
+        if k in ("nu_pre", "nu_post"):
+            arr = getattr(p, k)
+            for i, x in enumerate(v):
+                arr[i] = int(x)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    """Device pointer of a contiguous torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors crossing the C ABI must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class Solver:
+    """One libcgks context bound to the current device and torch stream."""
+
+    def __init__(self, params: Params | None = None, **kw):
+        import torch
+        self.torch = torch
+        self.params = params if params is not None else default_params(**kw)
+        h = C.c_void_p()
+        self._check(lib().cgks_create(C.byref(self.params), C.byref(h)), None)
+        self.h = h
+        self.sync_stream()
+
+    def _check(self, code, h="self"):
+        if code != OK:
+            msg = lib().cgks_last_error(self.h if h == "self" else None)
+            raise CgksError(code, msg.decode() if msg else "")
+
+    def sync_stream(self):
+        s = self.torch.cuda.current_stream().cuda_stream
+        self._check(lib().cgks_set_stream(self.h, C.c_void_p(s)))
+
+    def set_params(self, **kw):
+        for k, v in kw.items():
+            if k in ("nu_pre", "nu_post"):
+                arr = getattr(self.params, k)
+                for i, x in enumerate(v):
+                    arr[i] = int(x)
+            else:
+                setattr(self.params, k, v)
+        self._check(lib().cgks_set_params(self.h, C.byref(self.params)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().cgks_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- mesh
+    def set_mesh(self, m):
+        keep = [_np(m.xyz, np.float64), _np(m.ctype, np.uint8), _np(m.cnode_ptr, np.int64), _np(m.cnode, np.int64),
+                _np(m.bnode_ptr, np.int64), _np(m.bnode, np.int64), _np(m.btag, np.int32),
+                None if m.node_canon is None else _np(m.node_canon, np.int64)]
+        p = [None if a is None else a.ctypes.data_as(C.c_void_p) for a in keep]
+        self._check(lib().cgks_set_mesh(self.h, m.n_nodes, p[0], m.n_cells, p[1], p[2], p[3], m.n_bfaces, p[4], p[5],
+                                        p[6], p[7]))
+        self.info()
+
+    def set_bc(self, tag, kind, prim=None):
+        pr = None if prim is None else _np(prim, np.float64)
+        self._check(lib().cgks_set_bc(self.h, int(tag), int(kind),
+                                      None if pr is None else pr.ctypes.data_as(C.c_void_p)))
+
+    def info(self):
+        out = np.zeros(16, np.int64)
+        self._check(lib().cgks_mesh_info(self.h, out.ctypes.data_as(C.c_void_p)))
+        self.n_cells, self.n_faces, self.n_int, self.n_bfaces, self.n_gp = (int(x) for x in out[:5])
+        self.level_sizes = [int(x) for x in out[6:6 + int(out[5])]]
+        return out
+
+    # ---------------------------------------------------------------- tensors
+    def empty(self, *shape, dtype=None):
+        t = self.torch
+        return t.empty(*shape, dtype=dtype or t.float64, device="cuda")
+
+    def geometry(self):
+        N = self.n_cells
+        vol, cen, m2 = self.empty(N), self.empty(3, N), self.empty(6, N)
+        self._check(lib().cgks_geometry(self.h, _ptr(vol), _ptr(cen), _ptr(m2)))
+        return vol, cen, m2
+
+    def local_dt(self, W):
+        dt = self.empty(self.n_cells)
+        self._check(lib().cgks_local_dt(self.h, _ptr(W), _ptr(dt)))
+        return dt
+
+    def reconstruct(self, W, G, alpha=None):
+        coef = self.empty(50, self.n_cells)
+        self._check(lib().cgks_reconstruct(self.h, _ptr(W), _ptr(G), _ptr(alpha), _ptr(coef)))
+        return coef
+
+    def residual(self, W, G, alpha=None, grad=True):
+        N = self.n_cells
+        R = self.empty(5, N)
+        Gn = self.empty(15, N) if grad else None
+        an = self.empty(N) if grad else None
+        self._check(lib().cgks_residual(self.h, _ptr(W), _ptr(G), _ptr(alpha), _ptr(R), _ptr(Gn), _ptr(an)))
+        return R, Gn, an
+
+    def step(self, W, G, alpha, dt_global=-1.0, resnorm=None):
+        self._check(lib().cgks_step(self.h, _ptr(W), _ptr(G), _ptr(alpha), float(dt_global), _ptr(resnorm)))
+
+    def check(self):
+        self._check(lib().cgks_check(self.h))
+
+    def residual_norm(self, R):
+        out = self.empty(1)
+        self._check(lib().cgks_residual_norm(self.h, _ptr(R), _ptr(out)))
+        return out
+
+    # ---------------------------------------------------------------- multigrid
+    def agglomerate_graph(self, V, P, a, b, S, M, A, passes):
+        """Raw-graph agglomeration; device tensors; returns (f2c, Vc, Pc, n_coarse, m_coarse, stats)."""
+        n, m = int(V.shape[0]), int(a.shape[0])
+        f2c = self.empty(n, dtype=self.torch.int32)
+        Vc, Pc = self.empty(n), self.empty(n, 3)
+        nc, mc = C.c_int64(0), C.c_int64(0)
+        stats = np.zeros((max(passes, 1), 4), np.int64)
+        self._check(lib().cgks_agglomerate_graph(self.h, n, _ptr(V), _ptr(P), m, _ptr(a), _ptr(b), _ptr(S), _ptr(M),
+                                                 _ptr(A), int(passes), _ptr(f2c), _ptr(Vc), _ptr(Pc), C.byref(nc),
+                                                 C.byref(mc), stats.ctypes.data_as(C.c_void_p)))
+        return f2c, Vc[:nc.value], Pc[:nc.value], nc.value, mc.value, stats
+
+    def agglomerate(self):
+        self._check(lib().cgks_agglomerate(self.h))
+        self.info()
+        return self.level_sizes
+
+    def level_map(self, level):
+        f2c = self.empty(self.level_sizes[level - 1], dtype=self.torch.int32)
+        self._check(lib().cgks_level_map(self.h, int(level), _ptr(f2c)))
+        return f2c
+
+    def kfvs_residual(self, level, W):
+        R = self.empty(5, self.level_sizes[level])
+        self._check(lib().cgks_kfvs_residual(self.h, int(level), _ptr(W), _ptr(R)))
+        return R
+
+    def restrict(self, level, Wf, Rf):
+        n = self.level_sizes[level]
+        Wc, Rc = self.empty(5, n), self.empty(5, n)
+        self._check(lib().cgks_restrict(self.h, int(level), _ptr(Wf), _ptr(Rf), _ptr(Wc), _ptr(Rc)))
+        return Wc, Rc
+
+    def prolong(self, level, dWc, Wf):
+        self._check(lib().cgks_prolong(self.h, int(level), _ptr(dWc), _ptr(Wf)))
+
+    def vcycle(self, W, G, alpha, max_cycles, tol_drop=1e-10):
+        hist = np.zeros(max(max_cycles, 1))
+        done = C.c_int32(0)
+        code = lib().cgks_vcycle(self.h, _ptr(W), _ptr(G), _ptr(alpha), int(max_cycles), float(tol_drop),
+                                 hist.ctypes.data_as(C.c_void_p), C.byref(done))
+        if code not in (OK, E_NOCONV):
+            self._check(code)
+        return hist[:done.value], code == OK

@@ -1,0 +1,397 @@
+// C ABI entry points of libcgks (see include/cgks.h).
+#include <cmath>
+#include <cstring>
+#include <exception>
+
+#include "common.hpp"
+
+using namespace cgks;
+
+cgks_ctx::~cgks_ctx()
+{
+    for (Level *l : lev) delete l;
+    lev.clear();
+    if (pinned) (void)hipHostFree(pinned);
+    if (pinned_i) (void)hipHostFree(pinned_i);
+}
+
+#define API_BEGIN(ctx)                                     \
+    if (!(ctx)) return CGKS_E_ARG;                         \
+    try {
+#define API_END(ctx)                                       \
+    }                                                      \
+    catch (const cgks::Error &e)                           \
+    {                                                      \
+        (ctx)->err = e.msg;                                \
+        return e.code;                                     \
+    }                                                      \
+    catch (const std::exception &e)                        \
+    {                                                      \
+        (ctx)->err = e.what();                             \
+        return CGKS_E_DEVICE;                              \
+    }                                                      \
+    return CGKS_OK;
+
+static void need_mesh(const cgks_ctx *c)
+{
+    if (!c->has_mesh) throw Error{CGKS_E_STATE, "no mesh: call cgks_set_mesh first"};
+}
+
+static void check_params(const cgks_params *p)
+{
+    if (!(p->gamma > 1.0 && p->gamma < 5.0 / 3.0 + 1e-12)) throw Error{CGKS_E_ARG, "gamma must be in (1, 5/3]"};
+    if (!(p->cfl > 0.0)) throw Error{CGKS_E_ARG, "cfl must be positive"};
+    if (p->viscous && !(p->mu > 0.0)) throw Error{CGKS_E_ARG, "viscous flow needs mu > 0"};
+    if (!(p->prandtl > 0.0)) throw Error{CGKS_E_ARG, "prandtl must be positive"};
+    if (!(p->gamma_lin > 0.0 && p->gamma_lin < 1.0)) throw Error{CGKS_E_ARG, "gamma_lin must be in (0,1)"};
+    if (p->levels < 1 || p->levels > 8) throw Error{CGKS_E_ARG, "levels must be in 1..8"};
+    if (p->passes < 0 || p->passes > 16) throw Error{CGKS_E_ARG, "passes must be in 0..16"};
+    if (p->precision != 0 && p->precision != 1) throw Error{CGKS_E_ARG, "precision must be 0 or 1"};
+}
+
+static void check_bad(cgks_ctx *c)
+{
+    CGKS_HIP(hipMemcpyAsync(c->pinned_i, c->bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    CGKS_HIP(hipStreamSynchronize(c->stream));
+    if (*c->pinned_i != INT32_MAX) {
+        const int32_t cell = *c->pinned_i;
+        const int32_t big = INT32_MAX;
+        CGKS_HIP(hipMemcpyAsync(c->bad.p, &big, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+        CGKS_HIP(hipStreamSynchronize(c->stream));
+        throw Error{CGKS_E_PHYS, "non-positive density or pressure at a Gauss point of cell " + std::to_string(cell)};
+    }
+}
+
+extern "C" {
+
+cgks_status cgks_default_params(cgks_params *p)
+{
+    if (!p) return CGKS_E_ARG;
+    std::memset(p, 0, sizeof(*p));
+    p->gamma = 1.4;
+    p->mu = 0.0;
+    p->prandtl = 1.0;
+    p->cfl = 0.5;
+    p->eps_tau = 0.01;
+    p->c_tau = 1.0;
+    p->weno_eps = 1e-5;
+    p->gamma_lin = 0.5;
+    p->skew_delta = 0.25;
+    p->skew_sin = 0.17364817766693033;  // sin 10 deg
+    p->viscous = 0;
+    p->levels = 3;
+    p->passes = 3;
+    p->precision = 0;
+    for (int l = 0; l < 8; ++l) {
+        p->nu_pre[l] = 1;
+        p->nu_post[l] = 0;
+    }
+    p->mixed_switch = 1e-6;
+    p->seed = 1;
+    return CGKS_OK;
+}
+
+cgks_status cgks_create(const cgks_params *p, cgks_ctx **out)
+{
+    if (!p || !out) return CGKS_E_ARG;
+    cgks_ctx *c = new (std::nothrow) cgks_ctx();
+    if (!c) return CGKS_E_DEVICE;
+    try {
+        check_params(p);
+        c->prm = *p;
+        CGKS_HIP(hipGetDevice(&c->device));
+        hipDeviceProp_t prop;
+        CGKS_HIP(hipGetDeviceProperties(&prop, c->device));
+        c->gpu_cus = prop.multiProcessorCount;
+        CGKS_HIP(hipHostMalloc((void **)&c->pinned, 64 * sizeof(double), hipHostMallocDefault));
+        CGKS_HIP(hipHostMalloc((void **)&c->pinned_i, 16 * sizeof(int32_t), hipHostMallocDefault));
+        for (int t = 0; t < 64; ++t) {
+            c->bc_host.kind[t] = CGKS_BC_SLIP;
+            for (int k = 0; k < 5; ++k) c->bc_host.prim[t][k] = 0.0;
+        }
+        c->bc.alloc(1);
+        CGKS_HIP(hipMemcpy(c->bc.p, &c->bc_host, sizeof(BcTable), hipMemcpyHostToDevice));
+        c->lev.push_back(nullptr);
+    } catch (const Error &e) {
+        int code = e.code;
+        delete c;
+        return (cgks_status)code;
+    } catch (...) {
+        delete c;
+        return CGKS_E_DEVICE;
+    }
+    *out = c;
+    return CGKS_OK;
+}
+
+void cgks_destroy(cgks_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    delete c;
+}
+
+const char *cgks_last_error(const cgks_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+cgks_status cgks_set_params(cgks_ctx *c, const cgks_params *p)
+{
+    API_BEGIN(c)
+    if (!p) throw Error{CGKS_E_ARG, "null params"};
+    check_params(p);
+    c->prm = *p;
+    API_END(c)
+}
+
+cgks_status cgks_set_stream(cgks_ctx *c, void *s)
+{
+    API_BEGIN(c)
+    c->stream = (hipStream_t)s;
+    API_END(c)
+}
+
+cgks_status cgks_set_mesh(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_cells, const uint8_t *ctype,
+                          const int64_t *cnode_ptr, const int64_t *cnode, int64_t n_bfaces, const int64_t *bnode_ptr,
+                          const int64_t *bnode, const int32_t *btag, const int64_t *node_canon)
+{
+    API_BEGIN(c)
+    if (!xyz || !ctype || !cnode_ptr || !cnode || (n_bfaces > 0 && (!bnode_ptr || !bnode || !btag)) || n_bfaces < 0)
+        throw Error{CGKS_E_ARG, "null mesh array"};
+    for (Level *l : c->lev) delete l;
+    c->lev.assign(1, nullptr);
+    c->has_mesh = false;
+    mesh_build(c, n_nodes, xyz, n_cells, ctype, cnode_ptr, cnode, n_bfaces, bnode_ptr, bnode, btag, node_canon);
+    API_END(c)
+}
+
+cgks_status cgks_set_bc(cgks_ctx *c, int32_t tag, int32_t kind, const double *prim)
+{
+    API_BEGIN(c)
+    if (tag < 1 || tag > 63) throw Error{CGKS_E_ARG, "tag must be in 1..63"};
+    if (kind != CGKS_BC_SLIP && kind != CGKS_BC_NOSLIP_ADIABATIC && kind != CGKS_BC_FARFIELD)
+        throw Error{CGKS_E_ARG, "unknown boundary kind"};
+    if (kind == CGKS_BC_FARFIELD && (!prim || !(prim[0] > 0.0) || !(prim[4] > 0.0)))
+        throw Error{CGKS_E_ARG, "far field needs rho > 0 and p > 0"};
+    c->bc_host.kind[tag] = kind;
+    for (int k = 0; k < 5; ++k) c->bc_host.prim[tag][k] = prim ? prim[k] : 0.0;
+    CGKS_HIP(hipMemcpyAsync(c->bc.p, &c->bc_host, sizeof(BcTable), hipMemcpyHostToDevice, c->stream));
+    CGKS_HIP(hipStreamSynchronize(c->stream));
+    API_END(c)
+}
+
+cgks_status cgks_mesh_info(const cgks_ctx *c, int64_t *out)
+{
+    if (!c || !out) return CGKS_E_ARG;
+    for (int i = 0; i < 16; ++i) out[i] = 0;
+    out[0] = c->N;
+    out[1] = c->F;
+    out[2] = c->Fi;
+    out[3] = c->Fb;
+    out[4] = c->NGP;
+    out[5] = (int64_t)c->lev.size();
+    out[6] = c->N;
+    for (size_t l = 1; l < c->lev.size() && l < 8; ++l) out[6 + l] = c->lev[l]->n;
+    return CGKS_OK;
+}
+
+cgks_status cgks_geometry(cgks_ctx *c, double *vol, double *cen, double *mom2)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    const size_t N = c->N;
+    if (vol) CGKS_HIP(hipMemcpyAsync(vol, c->vol.p, N * 8, hipMemcpyDeviceToDevice, c->stream));
+    if (cen) CGKS_HIP(hipMemcpyAsync(cen, c->cen.p, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
+    if (mom2) CGKS_HIP(hipMemcpyAsync(mom2, c->mom2.p, 6 * N * 8, hipMemcpyDeviceToDevice, c->stream));
+    API_END(c)
+}
+
+cgks_status cgks_local_dt(cgks_ctx *c, const double *W, double *dt)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    if (!W || !dt) throw Error{CGKS_E_ARG, "null pointer"};
+    launch_local_dt(c, W, dt);
+    CGKS_HIP(hipGetLastError());
+    API_END(c)
+}
+
+cgks_status cgks_reconstruct(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    if (!W || !G || !coef) throw Error{CGKS_E_ARG, "null pointer"};
+    launch_recon(c, W, G, alpha, coef);
+    CGKS_HIP(hipGetLastError());
+    API_END(c)
+}
+
+cgks_status cgks_residual(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *R, double *G_new,
+                          double *alpha_new)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    if (!W || !G || !R || (G_new == nullptr) != (alpha_new == nullptr))
+        throw Error{CGKS_E_ARG, "W, G, R required; G_new and alpha_new both or neither"};
+    launch_local_dt(c, W, c->dtc.p);
+    launch_recon(c, W, G, alpha, c->coef.p);
+    const int mode = G_new ? MODE_RES : MODE_RESONLY;
+    launch_face(c, mode, c->coef.p, c->dtc.p, -1.0, false);
+    launch_gather_res(c, R, G_new, alpha_new, mode);
+    CGKS_HIP(hipGetLastError());
+    API_END(c)
+}
+
+cgks_status cgks_step(cgks_ctx *c, double *W, double *G, double *alpha, double dt_global, double *resnorm)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    if (!W || !G || !alpha) throw Error{CGKS_E_ARG, "null pointer"};
+    if (dt_global <= 0.0) {
+        launch_local_dt(c, W, c->dtc.p);
+        launch_recon(c, W, G, alpha, c->coef.p);
+        launch_face(c, MODE_RES, c->coef.p, c->dtc.p, -1.0, false);
+        const int nb = norm_blocks(c->N);
+        c->partial.ensure(nb);
+        launch_gather_fe(c, W, G, alpha, c->dtc.p, c->Rw.p, c->partial.p);
+        if (resnorm) finish_norm(c, c->partial.p, nb, c->N, resnorm);
+    } else {
+        launch_recon(c, W, G, alpha, c->coef.p);
+        launch_face(c, MODE_S1, c->coef.p, nullptr, dt_global, false);
+        launch_gather_s2o4(c, 1, dt_global, W, G, alpha);
+        launch_recon(c, c->Ws.p, c->Gs.p, c->aw.p, c->coef.p);
+        launch_face(c, MODE_S2, c->coef.p, nullptr, dt_global, false);
+        launch_gather_s2o4(c, 2, dt_global, W, G, alpha);
+    }
+    CGKS_HIP(hipGetLastError());
+    API_END(c)
+}
+
+cgks_status cgks_residual_norm(cgks_ctx *c, const double *R, double *out)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    if (!R || !out) throw Error{CGKS_E_ARG, "null pointer"};
+    launch_norm(c, R, c->vol.p, c->N, out);
+    CGKS_HIP(hipGetLastError());
+    API_END(c)
+}
+
+cgks_status cgks_check(cgks_ctx *c)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    check_bad(c);
+    API_END(c)
+}
+
+cgks_status cgks_agglomerate_graph(cgks_ctx *c, int64_t n, const double *V, const double *P, int64_t m,
+                                   const int32_t *pa, const int32_t *pb, const double *S, const double *M,
+                                   const double *A, int32_t passes, int32_t *f2c, double *Vc, double *Pc,
+                                   int64_t *n_coarse, int64_t *m_coarse, int64_t *stats)
+{
+    API_BEGIN(c)
+    if (n <= 0 || m < 0 || n > INT32_MAX / 2 || m > INT32_MAX / 2 || passes < 0 || passes > 16)
+        throw Error{CGKS_E_ARG, "graph sizes or pass count out of range"};
+    if (!V || !P || !f2c || !Vc || !Pc || !n_coarse || !m_coarse || (m > 0 && (!pa || !pb || !S || !M || !A)))
+        throw Error{CGKS_E_ARG, "null pointer"};
+    agglomerate_graph(c, n, V, P, m, pa, pb, S, M, A, passes, f2c, Vc, Pc, n_coarse, m_coarse, stats, nullptr, nullptr,
+                      nullptr, nullptr, nullptr);
+    API_END(c)
+}
+
+cgks_status cgks_agglomerate(cgks_ctx *c)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    build_hierarchy(c);
+    API_END(c)
+}
+
+static Level *level_at(cgks_ctx *c, int32_t level)
+{
+    if (level < 1 || level >= (int32_t)c->lev.size()) throw Error{CGKS_E_STATE, "level not built (cgks_agglomerate)"};
+    return c->lev[level];
+}
+
+cgks_status cgks_level_map(cgks_ctx *c, int32_t level, int32_t *f2c)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    Level *L = level_at(c, level);
+    if (!f2c) throw Error{CGKS_E_ARG, "null pointer"};
+    CGKS_HIP(hipMemcpyAsync(f2c, L->f2c.p, 4 * L->nfine, hipMemcpyDeviceToDevice, c->stream));
+    API_END(c)
+}
+
+cgks_status cgks_kfvs_residual(cgks_ctx *c, int32_t level, const double *W, double *R)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    level_at(c, level);
+    if (!W || !R) throw Error{CGKS_E_ARG, "null pointer"};
+    kfvs_residual(c, level, W, R);
+    CGKS_HIP(hipGetLastError());
+    API_END(c)
+}
+
+cgks_status cgks_restrict(cgks_ctx *c, int32_t level, const double *Wf, const double *Rf, double *Wc, double *Rc)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    level_at(c, level);
+    if ((Wf == nullptr) != (Wc == nullptr) || (Rf == nullptr) != (Rc == nullptr))
+        throw Error{CGKS_E_ARG, "each of (Wf, Wc) and (Rf, Rc) must be both set or both null"};
+    restrict_level(c, level, Wf, Rf, Wc, Rc);
+    CGKS_HIP(hipGetLastError());
+    API_END(c)
+}
+
+cgks_status cgks_prolong(cgks_ctx *c, int32_t level, const double *dWc, double *Wf)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    level_at(c, level);
+    if (!dWc || !Wf) throw Error{CGKS_E_ARG, "null pointer"};
+    prolong_level(c, level, dWc, Wf);
+    CGKS_HIP(hipGetLastError());
+    API_END(c)
+}
+
+cgks_status cgks_vcycle(cgks_ctx *c, double *W, double *G, double *alpha, int32_t max_cycles, double tol_drop,
+                        double *hist, int32_t *n_done)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    if (!W || !G || !alpha || max_cycles < 0) throw Error{CGKS_E_ARG, "bad arguments"};
+    if (c->prm.levels > 1 && (int)c->lev.size() != c->prm.levels) build_hierarchy(c);
+    if (n_done) *n_done = 0;
+    double r0 = 0.0, best = 0.0;
+    int best_at = 0;
+    bool mixed = c->prm.precision == 1;
+    for (int32_t k = 0; k < max_cycles; ++k) {
+        vcycle_once(c, W, G, alpha, mixed, mixed);
+        CGKS_HIP(hipGetLastError());
+        CGKS_HIP(hipMemcpyAsync(c->pinned, c->scal.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        CGKS_HIP(hipMemcpyAsync(c->pinned_i, c->bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        CGKS_HIP(hipStreamSynchronize(c->stream));
+        const double r = c->pinned[0];
+        if (*c->pinned_i != INT32_MAX) check_bad(c);
+        if (!std::isfinite(r)) throw Error{CGKS_E_NONFINITE, "non-finite residual in cycle " + std::to_string(k)};
+        if (hist) hist[k] = r;
+        if (n_done) *n_done = k + 1;
+        if (k == 0) {
+            r0 = r;
+            best = r;
+            if (r == 0.0) return CGKS_OK;
+        }
+        if (r < best) best = r, best_at = k;
+        const double drop = r / r0;
+        if (drop <= tol_drop) return CGKS_OK;
+        if (mixed && (drop <= c->prm.mixed_switch || k - best_at >= 20)) mixed = false;
+    }
+    c->err = "residual drop not reached in max_cycles";
+    return CGKS_E_NOCONV;
+    API_END(c)
+}
+
+}  // extern "C"

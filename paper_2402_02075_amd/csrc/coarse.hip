@@ -1,0 +1,1027 @@
+// Coarse levels: random-hash agglomeration, first-order KFVS, restriction,
+// forcing term, coarse sweeps, prolongation and the V-cycle driver.
+//
+// Paper Sec. 4.1 (Algorithm 1, cell coarsening): face hash
+// h = [23 (N_l + N_r) + N_l N_r] % N_f, first occurrence of each hash value
+// selects a face, skewness check against the virtual centre, merge, coarse
+// volume and centre as sums.  Sec. 4.2: restriction of the state (volume
+// weighted) and of the residual (sum), forcing term, coarse explicit update,
+// correction, three-level V-cycle.  Secs. 1 and 6: first-order KFVS with local
+// time stepping on the coarse levels.
+//
+// Parallel form of Algorithm 1 (equal to the sequential loop):
+//  - first occurrence: atomicMin of the face index into a table indexed by hash;
+//  - greedy matching in ascending face order = repeated rounds in which a live
+//    face is taken when it is the smallest live face at both of its cells
+//    (such a face has every smaller neighbouring face already dead, i.e. it
+//    would be taken by the sequential loop); cells of taken faces kill their
+//    other faces; rounds end when no face is live;
+//  - relabelling by an exclusive scan over surviving representatives keeps the
+//    numbering by smallest member id;
+//  - coarse pairs by a stable radix sort of (pair key, face index), each pair's
+//    area, moment and area vector summed sequentially in face order.
+// The skewness predicate uses +, -, * only in a fixed association order with
+// contraction off, so it takes bit-identical decisions on identical inputs.
+#include <hipcub/hipcub.hpp>
+
+#include "common.hpp"
+#include "gks_device.hpp"
+#include "bc_device.hpp"
+
+namespace cgks {
+
+// ---------------------------------------------------------------- agglomeration kernels
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_hash_min(int64_t m, uint64_t seed, const int32_t *__restrict__ pa, const int32_t *__restrict__ pb,
+                           int32_t *__restrict__ table)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const uint64_t a = (uint64_t)pa[j], b = (uint64_t)pb[j];
+    const uint64_t h = (23ull * seed * (a + b) + a * b) % (uint64_t)m;
+    atomicMin(&table[h], (int32_t)j);
+}
+
+__device__ __noinline__ bool skew_accept(double Va, double Vb, const double *Pa, const double *Pb, double S,
+                                         const double *M, const double *A, double delta, double smin)
+{
+#pragma clang fp contract(off)
+    const double V = Va + Vb;
+    const double P0 = Pa[0] + Pb[0], P1 = Pa[1] + Pb[1], P2 = Pa[2] + Pb[2];
+    const double e0 = V * M[0] - S * P0, e1 = V * M[1] - S * P1, e2 = V * M[2] - S * P2;
+    const double ee = e0 * e0 + e1 * e1 + e2 * e2;
+    const double d2 = delta * delta;
+    const double d6 = d2 * d2 * d2;
+    const double V2 = V * V, V4 = V2 * V2, V8 = V4 * V4;
+    const double S2 = S * S, S6 = S2 * S2 * S2;
+    if (ee * ee * ee <= d6 * V8 * S6) return true;
+    const double ea = e0 * A[0] + e1 * A[1] + e2 * A[2];
+    const double aa = A[0] * A[0] + A[1] * A[1] + A[2] * A[2];
+    const double s2 = smin * smin;
+    return ea * ea >= s2 * ee * aa;
+}
+
+__global__ void k_select(int64_t m, uint64_t seed, const int32_t *__restrict__ pa, const int32_t *__restrict__ pb,
+                         const int32_t *__restrict__ table, const double *__restrict__ V, const double *__restrict__ P,
+                         const double *__restrict__ S, const double *__restrict__ M, const double *__restrict__ A,
+                         double delta, double smin, uint8_t *__restrict__ live, int32_t *__restrict__ cnt)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const uint64_t a = (uint64_t)pa[j], b = (uint64_t)pb[j];
+    const uint64_t h = (23ull * seed * (a + b) + a * b) % (uint64_t)m;
+    uint8_t ok = 0;
+    if (table[h] == (int32_t)j) {
+        atomicAdd(&cnt[0], 1);
+        if (skew_accept(V[a], V[b], &P[3 * a], &P[3 * b], S[j], &M[3 * j], &A[3 * j], delta, smin)) {
+            ok = 1;
+            atomicAdd(&cnt[1], 1);
+        }
+    }
+    live[j] = ok;
+}
+
+__global__ void k_match_min(int64_t m, const int32_t *__restrict__ pa, const int32_t *__restrict__ pb,
+                            const uint8_t *__restrict__ live, int32_t *__restrict__ best)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m || !live[j]) return;
+    atomicMin(&best[pa[j]], (int32_t)j);
+    atomicMin(&best[pb[j]], (int32_t)j);
+}
+
+__global__ void k_match_take(int64_t m, const int32_t *__restrict__ pa, const int32_t *__restrict__ pb,
+                             uint8_t *__restrict__ live, const int32_t *__restrict__ best, int32_t *__restrict__ mate,
+                             int32_t *__restrict__ partner, uint8_t *__restrict__ matched, int32_t *__restrict__ cnt)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m || !live[j]) return;
+    const int a = pa[j], b = pb[j];
+    if (best[a] == (int32_t)j && best[b] == (int32_t)j) {
+        mate[b] = a;
+        partner[a] = b;
+        matched[a] = 1;
+        matched[b] = 1;
+        atomicAdd(&cnt[2], 1);
+    }
+}
+
+__global__ void k_match_kill(int64_t m, const int32_t *__restrict__ pa, const int32_t *__restrict__ pb,
+                             uint8_t *__restrict__ live, const uint8_t *__restrict__ matched, int32_t *__restrict__ cnt)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m || !live[j]) return;
+    if (matched[pa[j]] || matched[pb[j]]) live[j] = 0;
+    else atomicAdd(&cnt[3], 1);
+}
+
+__global__ void k_surv(int64_t n, const int32_t *__restrict__ mate, int32_t *__restrict__ flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = mate[i] < 0 ? 1 : 0;
+}
+
+__global__ void k_newid(int64_t n, const int32_t *__restrict__ mate, int32_t *__restrict__ newid)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && mate[i] >= 0) newid[i] = newid[mate[i]];
+}
+
+__global__ void k_new_geom(int64_t n, const int32_t *__restrict__ mate, const int32_t *__restrict__ partner,
+                           const int32_t *__restrict__ newid, const double *__restrict__ V, const double *__restrict__ P,
+                           double *__restrict__ Vo, double *__restrict__ Po)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || mate[i] >= 0) return;
+    const int k = newid[i];
+    const int b = partner[i];
+    if (b >= 0) {
+        Vo[k] = V[i] + V[b];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Po[3 * k + d] = P[3 * i + d] + P[3 * b + d];
+    } else {
+        Vo[k] = V[i];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Po[3 * k + d] = P[3 * i + d];
+    }
+}
+
+__global__ void k_compose(int64_t n, int32_t *__restrict__ f2c, const int32_t *__restrict__ newid)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) f2c[i] = newid[f2c[i]];
+}
+
+__global__ void k_iota(int64_t n, int32_t *p)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int32_t)i;
+}
+
+// key of the relabelled pair (min, max) << ; dropped pairs get the largest key
+__global__ void k_pair_keys(int64_t m, const int32_t *__restrict__ pa, const int32_t *__restrict__ pb,
+                            const int32_t *__restrict__ newid, uint64_t *__restrict__ key, int32_t *__restrict__ idx)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t a = (uint32_t)newid[pa[j]], b = (uint32_t)newid[pb[j]];
+    key[j] = a == b ? ~0ull : ((uint64_t)(a < b ? a : b) << 32) | (uint64_t)(a < b ? b : a);
+    idx[j] = (int32_t)j;
+}
+
+__global__ void k_seg_heads(int64_t m, const uint64_t *__restrict__ key, int32_t *__restrict__ head)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    head[j] = (key[j] != ~0ull && (j == 0 || key[j] != key[j - 1])) ? 1 : 0;
+}
+
+__global__ void k_seg_start(int64_t m, const int32_t *__restrict__ head, const int32_t *__restrict__ segid,
+                            int32_t *__restrict__ start)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m && head[j]) start[segid[j]] = (int32_t)j;
+}
+
+// one thread per coarse pair: sequential sums in ascending face index
+__global__ void k_seg_sum(int64_t nseg, int64_t m, const int32_t *__restrict__ start, const uint64_t *__restrict__ key,
+                          const int32_t *__restrict__ idx, const int32_t *__restrict__ pa,
+                          const int32_t *__restrict__ newid, const double *__restrict__ S, const double *__restrict__ M,
+                          const double *__restrict__ A, int32_t *__restrict__ pao, int32_t *__restrict__ pbo,
+                          double *__restrict__ So, double *__restrict__ Mo, double *__restrict__ Ao)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nseg) return;
+    const int64_t b = start[g];
+    const uint64_t k0 = key[b];
+    double s = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int64_t q = b; q < m && key[q] == k0; ++q) {
+        const int j = idx[q];
+        const uint32_t lo = (uint32_t)(k0 >> 32);
+        const bool rev = (uint32_t)newid[pa[j]] != lo;
+        s += S[j];
+        m0 += M[3 * j];
+        m1 += M[3 * j + 1];
+        m2 += M[3 * j + 2];
+        a0 += rev ? -A[3 * j] : A[3 * j];
+        a1 += rev ? -A[3 * j + 1] : A[3 * j + 1];
+        a2 += rev ? -A[3 * j + 2] : A[3 * j + 2];
+    }
+    pao[g] = (int32_t)(k0 >> 32);
+    pbo[g] = (int32_t)(k0 & 0xffffffffu);
+    So[g] = s;
+    Mo[3 * g] = m0;
+    Mo[3 * g + 1] = m1;
+    Mo[3 * g + 2] = m2;
+    Ao[3 * g] = a0;
+    Ao[3 * g + 1] = a1;
+    Ao[3 * g + 2] = a2;
+}
+
+// ---------------------------------------------------------------- agglomeration driver
+namespace {
+struct Scratch {
+    DBuf<int32_t> table, best, mate, partner, newid, flag, cnt, idx, idx2, head, segid, start;
+    DBuf<uint8_t> live, matched;
+    DBuf<uint64_t> key, key2;
+    DBuf<uint8_t> tmp;
+};
+
+void scan_excl(Scratch &s, const int32_t *in, int32_t *out, int64_t n, hipStream_t st)
+{
+    size_t bytes = 0;
+    CGKS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, st));
+    s.tmp.ensure(bytes + 1);
+    CGKS_HIP(hipcub::DeviceScan::ExclusiveSum(s.tmp.p, bytes, in, out, (int)n, st));
+}
+}  // namespace
+
+static inline dim3 G1(int64_t n) { return dim3(blocks_for(n > 0 ? n : 1, 256)); }
+
+void agglomerate_graph(cgks_ctx *c, int64_t n, const double *V, const double *P, int64_t m, const int32_t *pa,
+                       const int32_t *pb, const double *S, const double *M, const double *A, int passes, int32_t *f2c,
+                       double *Vc, double *Pc, int64_t *n_coarse, int64_t *m_coarse, int64_t *stats, int32_t *pa_out,
+                       int32_t *pb_out, double *S_out, double *M_out, double *A_out)
+{
+    hipStream_t st = c->stream;
+    const dim3 B(256);
+    Scratch s;
+    // current graph buffers (ping-pong)
+    DBuf<double> cV, cP, cS, cM, cA, nV, nP, nS, nM, nA;
+    DBuf<int32_t> ca, cb, na, nb;
+    cV.alloc(n);
+    cP.alloc(3 * n);
+    cS.alloc(m + 1);
+    cM.alloc(3 * m + 3);
+    cA.alloc(3 * m + 3);
+    ca.alloc(m + 1);
+    cb.alloc(m + 1);
+    nV.alloc(n);
+    nP.alloc(3 * n);
+    nS.alloc(m + 1);
+    nM.alloc(3 * m + 3);
+    nA.alloc(3 * m + 3);
+    na.alloc(m + 1);
+    nb.alloc(m + 1);
+    CGKS_HIP(hipMemcpyAsync(cV.p, V, 8 * n, hipMemcpyDeviceToDevice, st));
+    CGKS_HIP(hipMemcpyAsync(cP.p, P, 24 * n, hipMemcpyDeviceToDevice, st));
+    if (m) {
+        CGKS_HIP(hipMemcpyAsync(cS.p, S, 8 * m, hipMemcpyDeviceToDevice, st));
+        CGKS_HIP(hipMemcpyAsync(cM.p, M, 24 * m, hipMemcpyDeviceToDevice, st));
+        CGKS_HIP(hipMemcpyAsync(cA.p, A, 24 * m, hipMemcpyDeviceToDevice, st));
+        CGKS_HIP(hipMemcpyAsync(ca.p, pa, 4 * m, hipMemcpyDeviceToDevice, st));
+        CGKS_HIP(hipMemcpyAsync(cb.p, pb, 4 * m, hipMemcpyDeviceToDevice, st));
+    }
+    hipLaunchKernelGGL(k_iota, G1(n), B, 0, st, n, f2c);
+    s.table.alloc(m + 1);
+    s.best.alloc(n);
+    s.mate.alloc(n);
+    s.partner.alloc(n);
+    s.newid.alloc(n);
+    s.flag.alloc(n);
+    s.cnt.alloc(8);
+    s.live.alloc(m + 1);
+    s.matched.alloc(n);
+    s.key.alloc(m + 1);
+    s.key2.alloc(m + 1);
+    s.idx.alloc(m + 1);
+    s.idx2.alloc(m + 1);
+    s.head.alloc(m + 1);
+    s.segid.alloc(m + 1);
+    s.start.alloc(m + 1);
+    int64_t cn = n, cm = m;
+    for (int pass = 0; pass < passes; ++pass) {
+        int32_t hc[4] = {0, 0, 0, 0};
+        CGKS_HIP(hipMemcpyAsync(s.cnt.p, hc, sizeof(hc), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_fill_i32, G1(cn), B, 0, st, s.mate.p, -1, cn);
+        hipLaunchKernelGGL(k_fill_i32, G1(cn), B, 0, st, s.partner.p, -1, cn);
+        CGKS_HIP(hipMemsetAsync(s.matched.p, 0, cn, st));
+        if (cm > 0) {
+            hipLaunchKernelGGL(k_fill_i32, G1(cm), B, 0, st, s.table.p, INT32_MAX, cm);
+            hipLaunchKernelGGL(k_hash_min, G1(cm), B, 0, st, cm, (uint64_t)c->prm.seed, ca.p, cb.p, s.table.p);
+            hipLaunchKernelGGL(k_select, G1(cm), B, 0, st, cm, (uint64_t)c->prm.seed, ca.p, cb.p, s.table.p, cV.p, cP.p,
+                               cS.p, cM.p, cA.p, c->prm.skew_delta, c->prm.skew_sin, s.live.p, s.cnt.p);
+            for (int round = 0;; ++round) {
+                hipLaunchKernelGGL(k_fill_i32, G1(cn), B, 0, st, s.best.p, INT32_MAX, cn);
+                hipLaunchKernelGGL(k_match_min, G1(cm), B, 0, st, cm, ca.p, cb.p, s.live.p, s.best.p);
+                hipLaunchKernelGGL(k_match_take, G1(cm), B, 0, st, cm, ca.p, cb.p, s.live.p, s.best.p, s.mate.p,
+                                   s.partner.p, s.matched.p, s.cnt.p);
+                int32_t zero = 0;
+                CGKS_HIP(hipMemcpyAsync(s.cnt.p + 3, &zero, 4, hipMemcpyHostToDevice, st));
+                hipLaunchKernelGGL(k_match_kill, G1(cm), B, 0, st, cm, ca.p, cb.p, s.live.p, s.matched.p, s.cnt.p);
+                int32_t alive = 0;
+                CGKS_HIP(hipMemcpyAsync(&alive, s.cnt.p + 3, 4, hipMemcpyDeviceToHost, st));
+                CGKS_HIP(hipStreamSynchronize(st));
+                if (alive == 0) break;
+                if (round > 100000) throw Error{CGKS_E_DEVICE, "matching rounds did not terminate"};
+            }
+        }
+        CGKS_HIP(hipMemcpyAsync(hc, s.cnt.p, sizeof(hc), hipMemcpyDeviceToHost, st));
+        // relabel: exclusive scan over representatives
+        hipLaunchKernelGGL(k_surv, G1(cn), B, 0, st, cn, s.mate.p, s.flag.p);
+        scan_excl(s, s.flag.p, s.newid.p, cn, st);
+        int32_t lastf = 0, lastid = 0;
+        CGKS_HIP(hipMemcpyAsync(&lastf, s.flag.p + cn - 1, 4, hipMemcpyDeviceToHost, st));
+        CGKS_HIP(hipMemcpyAsync(&lastid, s.newid.p + cn - 1, 4, hipMemcpyDeviceToHost, st));
+        hipLaunchKernelGGL(k_newid, G1(cn), B, 0, st, cn, s.mate.p, s.newid.p);
+        hipLaunchKernelGGL(k_new_geom, G1(cn), B, 0, st, cn, s.mate.p, s.partner.p, s.newid.p, cV.p, cP.p, nV.p, nP.p);
+        hipLaunchKernelGGL(k_compose, G1(n), B, 0, st, n, f2c, s.newid.p);
+        CGKS_HIP(hipStreamSynchronize(st));
+        const int64_t nn = (int64_t)lastid + lastf;
+        // coarse pairs
+        int64_t nm = 0;
+        if (cm > 0) {
+            hipLaunchKernelGGL(k_pair_keys, G1(cm), B, 0, st, cm, ca.p, cb.p, s.newid.p, s.key.p, s.idx.p);
+            size_t bytes = 0;
+            CGKS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, s.key.p, s.key2.p, s.idx.p, s.idx2.p, (int)cm, 0,
+                                                        64, st));
+            s.tmp.ensure(bytes + 1);
+            CGKS_HIP(hipcub::DeviceRadixSort::SortPairs(s.tmp.p, bytes, s.key.p, s.key2.p, s.idx.p, s.idx2.p, (int)cm,
+                                                        0, 64, st));
+            hipLaunchKernelGGL(k_seg_heads, G1(cm), B, 0, st, cm, s.key2.p, s.head.p);
+            scan_excl(s, s.head.p, s.segid.p, cm, st);
+            int32_t lh = 0, ls = 0;
+            CGKS_HIP(hipMemcpyAsync(&lh, s.head.p + cm - 1, 4, hipMemcpyDeviceToHost, st));
+            CGKS_HIP(hipMemcpyAsync(&ls, s.segid.p + cm - 1, 4, hipMemcpyDeviceToHost, st));
+            CGKS_HIP(hipStreamSynchronize(st));
+            nm = (int64_t)ls + lh;
+            hipLaunchKernelGGL(k_seg_start, G1(cm), B, 0, st, cm, s.head.p, s.segid.p, s.start.p);
+            hipLaunchKernelGGL(k_seg_sum, G1(nm), B, 0, st, nm, cm, s.start.p, s.key2.p, s.idx2.p, ca.p, s.newid.p,
+                               cS.p, cM.p, cA.p, na.p, nb.p, nS.p, nM.p, nA.p);
+        }
+        if (stats) {
+            stats[4 * pass + 0] = hc[0];
+            stats[4 * pass + 1] = hc[1];
+            stats[4 * pass + 2] = hc[2];
+            stats[4 * pass + 3] = nm;
+        }
+        std::swap(cV.p, nV.p);
+        std::swap(cP.p, nP.p);
+        std::swap(cS.p, nS.p);
+        std::swap(cM.p, nM.p);
+        std::swap(cA.p, nA.p);
+        std::swap(ca.p, na.p);
+        std::swap(cb.p, nb.p);
+        cn = nn;
+        cm = nm;
+    }
+    CGKS_HIP(hipMemcpyAsync(Vc, cV.p, 8 * cn, hipMemcpyDeviceToDevice, st));
+    CGKS_HIP(hipMemcpyAsync(Pc, cP.p, 24 * cn, hipMemcpyDeviceToDevice, st));
+    if (pa_out && cm) {
+        CGKS_HIP(hipMemcpyAsync(pa_out, ca.p, 4 * cm, hipMemcpyDeviceToDevice, st));
+        CGKS_HIP(hipMemcpyAsync(pb_out, cb.p, 4 * cm, hipMemcpyDeviceToDevice, st));
+        CGKS_HIP(hipMemcpyAsync(S_out, cS.p, 8 * cm, hipMemcpyDeviceToDevice, st));
+        CGKS_HIP(hipMemcpyAsync(M_out, cM.p, 24 * cm, hipMemcpyDeviceToDevice, st));
+        CGKS_HIP(hipMemcpyAsync(A_out, cA.p, 24 * cm, hipMemcpyDeviceToDevice, st));
+    }
+    CGKS_HIP(hipStreamSynchronize(st));
+    *n_coarse = cn;
+    *m_coarse = cm;
+}
+
+// ---------------------------------------------------------------- hierarchy
+__global__ void k_first_moment(int64_t N, const double *__restrict__ vol, const double *__restrict__ cen,
+                               double *__restrict__ P)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) P[3 * i + d] = vol[i] * cen[d * N + i];
+}
+
+__global__ void k_gather_pairs(int64_t m, const int32_t *__restrict__ fidx, int64_t F, const double *__restrict__ farea,
+                               const double *__restrict__ fmom, const double *__restrict__ favec, double *__restrict__ S,
+                               double *__restrict__ M, double *__restrict__ A)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const int f = fidx[j];
+    S[j] = farea[f];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        M[3 * j + d] = fmom[d * F + f];
+        A[3 * j + d] = favec[d * F + f];
+    }
+}
+
+__global__ void k_interleaved_to_soa(int64_t m, const double *__restrict__ in, double *__restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) out[d * m + j] = in[3 * j + d];
+}
+
+namespace {
+// host description of a graph level before upload
+struct HostGraph {
+    std::vector<int32_t> a, b;     // candidate pairs
+    std::vector<int32_t> pera, perb; // periodic pairs (kept out of agglomeration)
+    std::vector<double> perA;      // interleaved area vectors of periodic pairs
+    std::vector<double> perS;
+};
+
+void build_cell_items(Level *L, const std::vector<int32_t> &pa, const std::vector<int32_t> &pb,
+                      const std::vector<int32_t> &bown, hipStream_t st)
+{
+    const int64_t n = L->n, m = (int64_t)pa.size(), nb = (int64_t)bown.size();
+    std::vector<int32_t> ptr(n + 1, 0);
+    for (int64_t j = 0; j < m; ++j) {
+        ptr[pa[j] + 1]++;
+        ptr[pb[j] + 1]++;
+    }
+    for (int64_t k = 0; k < nb; ++k) ptr[bown[k] + 1]++;
+    for (int64_t i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+    std::vector<int32_t> item(ptr[n]);
+    std::vector<int32_t> fill(n, 0);
+    for (int64_t j = 0; j < m; ++j) {
+        item[ptr[pa[j]] + fill[pa[j]]++] = (int32_t)(2 * j);
+        item[ptr[pb[j]] + fill[pb[j]]++] = (int32_t)(2 * j + 1);
+    }
+    for (int64_t k = 0; k < nb; ++k) item[ptr[bown[k]] + fill[bown[k]]++] = (int32_t)(-(k + 1));
+    L->cf_ptr.upload(ptr, st);
+    L->cf_item.upload(item, st);
+}
+
+void build_c2f(Level *L, const std::vector<int32_t> &f2c, hipStream_t st)
+{
+    const int64_t n = L->n, nf = (int64_t)f2c.size();
+    std::vector<int32_t> ptr(n + 1, 0), idx(nf);
+    for (int64_t i = 0; i < nf; ++i) ptr[f2c[i] + 1]++;
+    for (int64_t k = 0; k < n; ++k) ptr[k + 1] += ptr[k];
+    std::vector<int32_t> fill(n, 0);
+    for (int64_t i = 0; i < nf; ++i) idx[ptr[f2c[i]] + fill[f2c[i]]++] = (int32_t)i;
+    L->c2f_ptr.upload(ptr, st);
+    L->c2f_idx.upload(idx, st);
+}
+}  // namespace
+
+void build_hierarchy(cgks_ctx *c)
+{
+    hipStream_t st = c->stream;
+    for (Level *l : c->lev) delete l;
+    c->lev.assign(1, nullptr);
+    const int levels = c->prm.levels;
+    if (levels <= 1) return;
+    const int64_t N = c->N, F = c->F, Fi = c->Fi;
+    // fine graph: interior, non-periodic faces as pairs (L < R, sorted); periodic faces kept aside
+    std::vector<int32_t> hfl = c->fl.download(F, st), hfr = c->fr.download(F, st), htag = c->ftag.download(F, st);
+    std::vector<double> hsh = c->fshift.download(3 * F, st), hav = c->favec.download(3 * F, st),
+                        har = c->farea.download(F, st);
+    std::vector<int32_t> ga, gb, gidx, pera, perb;
+    std::vector<double> perA, perS;
+    for (int64_t f = 0; f < Fi; ++f) {
+        const bool per = hsh[f] != 0.0 || hsh[F + f] != 0.0 || hsh[2 * F + f] != 0.0;
+        if (per) {
+            pera.push_back(hfl[f]);
+            perb.push_back(hfr[f]);
+            for (int d = 0; d < 3; ++d) perA.push_back(hav[d * F + f]);
+            perS.push_back(har[f]);
+            continue;
+        }
+        if (!ga.empty() && ga.back() == hfl[f] && gb.back() == hfr[f])
+            throw Error{CGKS_E_MESH, "two faces between the same pair of cells are not supported by agglomeration"};
+        ga.push_back(hfl[f]);
+        gb.push_back(hfr[f]);
+        gidx.push_back((int32_t)f);
+    }
+    std::vector<int32_t> bown, btag;
+    std::vector<double> bA;
+    for (int64_t f = Fi; f < F; ++f) {
+        bown.push_back(hfl[f]);
+        btag.push_back(htag[f]);
+    }
+    const int64_t nbf = F - Fi;
+    // device graph of the current finest level
+    int64_t n = N, m = (int64_t)ga.size();
+    DBuf<double> V, P, S, M, A;
+    DBuf<int32_t> pa, pb, fidx;
+    V.alloc(n);
+    P.alloc(3 * n);
+    S.alloc(m + 1);
+    M.alloc(3 * m + 3);
+    A.alloc(3 * m + 3);
+    pa.upload(ga, st);
+    pb.upload(gb, st);
+    fidx.upload(gidx, st);
+    CGKS_HIP(hipMemcpyAsync(V.p, c->vol.p, 8 * n, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_first_moment, G1(n), dim3(256), 0, st, n, c->vol.p, c->cen.p, P.p);
+    if (m) hipLaunchKernelGGL(k_gather_pairs, G1(m), dim3(256), 0, st, m, fidx.p, F, c->farea.p, c->fmom.p, c->favec.p,
+                              S.p, M.p, A.p);
+    // fine boundary area vectors (SoA)
+    std::vector<double> hbA(3 * nbf);
+    for (int64_t k = 0; k < nbf; ++k)
+        for (int d = 0; d < 3; ++d) hbA[d * nbf + k] = hav[d * F + Fi + k];
+    std::vector<int32_t> comp(N);  // fine -> current level
+    for (int64_t i = 0; i < N; ++i) comp[i] = (int32_t)i;
+    std::vector<int32_t> cur_pera = pera, cur_perb = perb;
+    std::vector<double> cur_perA = perA, cur_perS = perS;
+    for (int l = 1; l < levels; ++l) {
+        Level *L = new Level();
+        c->lev.push_back(L);
+        L->nfine = n;
+        L->f2c.alloc(n);
+        DBuf<double> Vc, Pc, Sc, Mc, Ac;
+        DBuf<int32_t> pac, pbc;
+        Vc.alloc(n);
+        Pc.alloc(3 * n);
+        Sc.alloc(m + 1);
+        Mc.alloc(3 * m + 3);
+        Ac.alloc(3 * m + 3);
+        pac.alloc(m + 1);
+        pbc.alloc(m + 1);
+        int64_t nc = 0, mc = 0;
+        agglomerate_graph(c, n, V.p, P.p, m, pa.p, pb.p, S.p, M.p, A.p, c->prm.passes, L->f2c.p, Vc.p, Pc.p, &nc, &mc,
+                          nullptr, pac.p, pbc.p, Sc.p, Mc.p, Ac.p);
+        L->n = nc;
+        std::vector<int32_t> hf2c = L->f2c.download(n, st);
+        // periodic pairs carried to the coarse level
+        std::vector<int32_t> hpa = pac.download(mc, st), hpb = pbc.download(mc, st);
+        std::vector<double> hS = Sc.download(mc, st), hA = Ac.download(3 * mc, st);
+        std::vector<int32_t> allA = hpa, allB = hpb;
+        std::vector<double> allS = hS, allAv = hA;
+        for (size_t q = 0; q < cur_pera.size(); ++q) {
+            cur_pera[q] = hf2c[cur_pera[q]];
+            cur_perb[q] = hf2c[cur_perb[q]];
+            allA.push_back(cur_pera[q]);
+            allB.push_back(cur_perb[q]);
+            allS.push_back(cur_perS[q]);
+            for (int d = 0; d < 3; ++d) allAv.push_back(cur_perA[3 * q + d]);
+        }
+        const int64_t mall = (int64_t)allA.size();
+        L->m = mall;
+        L->pa.upload(allA, st);
+        L->pb.upload(allB, st);
+        L->S.upload(allS, st);
+        {
+            DBuf<double> tmp;
+            tmp.upload(allAv, st);
+            L->A.alloc(3 * mall + 3);
+            if (mall) hipLaunchKernelGGL(k_interleaved_to_soa, G1(mall), dim3(256), 0, st, mall, tmp.p, L->A.p);
+            CGKS_HIP(hipStreamSynchronize(st));
+        }
+        L->V.alloc(nc);
+        L->P.alloc(3 * nc);
+        CGKS_HIP(hipMemcpyAsync(L->V.p, Vc.p, 8 * nc, hipMemcpyDeviceToDevice, st));
+        CGKS_HIP(hipMemcpyAsync(L->P.p, Pc.p, 24 * nc, hipMemcpyDeviceToDevice, st));
+        // boundary faces: fine faces with the coarse owner
+        for (int64_t i = 0; i < N; ++i) comp[i] = hf2c[comp[i]];
+        std::vector<int32_t> lbown(nbf);
+        for (int64_t k = 0; k < nbf; ++k) lbown[k] = comp[bown[k]];
+        L->nb = nbf;
+        L->bown.upload(lbown, st);
+        L->btag.upload(btag, st);
+        L->bA.upload(hbA, st);
+        build_cell_items(L, allA, allB, lbown, st);
+        build_c2f(L, hf2c, st);
+        // work buffers
+        L->W0.alloc(5 * nc);
+        L->W.alloc(5 * nc);
+        L->R.alloc(5 * nc);
+        L->F.alloc(5 * nc);
+        L->Rs.alloc(5 * nc);
+        L->dt.alloc(nc);
+        L->fflux.alloc(5 * (mall + nbf) + 5);
+        // next level's input graph = this level's agglomerated pairs (periodic ones stay aside)
+        std::swap(V.p, Vc.p);
+        std::swap(P.p, Pc.p);
+        std::swap(S.p, Sc.p);
+        std::swap(M.p, Mc.p);
+        std::swap(A.p, Ac.p);
+        std::swap(pa.p, pac.p);
+        std::swap(pb.p, pbc.p);
+        n = nc;
+        m = mc;
+        CGKS_HIP(hipStreamSynchronize(st));
+    }
+}
+
+// ---------------------------------------------------------------- KFVS and transfers
+template <class T> struct CoarseArgs {
+    int64_t n, m, nb;
+    double gam, K;
+    const T *W;
+    const int32_t *pa, *pb, *bown, *btag;
+    const double *A, *bA;
+    const BcTable *bc;
+    T *fflux;  // [5][m + nb], S n . F
+};
+
+template <class T> __device__ __forceinline__ void kfvs_local(const T wl[5], const T wr[5], T gam, T K, T F[5])
+{
+    const Side<T> sl = side_of(wl, gam), sr = side_of(wr, gam);
+    Tab<T> t;
+    T q[5];
+    tab_vw(t, sl, K);
+    tab_u_half(t, sl, T(1));
+    mpsi<1, 0, 0>(t, q);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) F[c] = sl.rho * q[c];
+    tab_vw(t, sr, K);
+    tab_u_half(t, sr, T(-1));
+    mpsi<1, 0, 0>(t, q);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) F[c] += sr.rho * q[c];
+}
+
+template <class T> __global__ __launch_bounds__(256) void k_kfvs_face(CoarseArgs<T> A)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = A.m + A.nb;
+    if (j >= tot) return;
+    double av[3];
+    double wa[5], wb[5];
+    if (j < A.m) {
+        for (int d = 0; d < 3; ++d) av[d] = A.A[d * A.m + j];
+        const int a = A.pa[j], b = A.pb[j];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            wa[q] = double(A.W[q * A.n + a]);
+            wb[q] = double(A.W[q * A.n + b]);
+        }
+    } else {
+        const int64_t k = j - A.m;
+        for (int d = 0; d < 3; ++d) av[d] = A.bA[d * A.nb + k];
+        const int o = A.bown[k];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) wa[q] = double(A.W[q * A.n + o]);
+    }
+    const double S = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
+    if (S == 0.0) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) A.fflux[q * tot + j] = T(0);
+        return;
+    }
+    const double n[3] = {av[0] / S, av[1] / S, av[2] / S};
+    if (j >= A.m) ghost_state(*A.bc, A.btag[j - A.m], n, wa, A.gam, wb);
+    double t1[3], t2[3];
+    onb(n, t1, t2);
+    T la[5], lb[5];
+    la[0] = T(wa[0]);
+    la[1] = T(wa[1] * n[0] + wa[2] * n[1] + wa[3] * n[2]);
+    la[2] = T(wa[1] * t1[0] + wa[2] * t1[1] + wa[3] * t1[2]);
+    la[3] = T(wa[1] * t2[0] + wa[2] * t2[1] + wa[3] * t2[2]);
+    la[4] = T(wa[4]);
+    lb[0] = T(wb[0]);
+    lb[1] = T(wb[1] * n[0] + wb[2] * n[1] + wb[3] * n[2]);
+    lb[2] = T(wb[1] * t1[0] + wb[2] * t1[1] + wb[3] * t1[2]);
+    lb[3] = T(wb[1] * t2[0] + wb[2] * t2[1] + wb[3] * t2[2]);
+    lb[4] = T(wb[4]);
+    T Fl[5];
+    kfvs_local(la, lb, T(A.gam), T(A.K), Fl);
+    A.fflux[0 * tot + j] = T(S * double(Fl[0]));
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        A.fflux[(1 + d) * tot + j] = T(S * (double(Fl[1]) * n[d] + double(Fl[2]) * t1[d] + double(Fl[3]) * t2[d]));
+    A.fflux[4 * tot + j] = T(S * double(Fl[4]));
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_kfvs_gather(int64_t n, int64_t tot, int64_t m, const int32_t *__restrict__ ptr,
+                                                     const int32_t *__restrict__ item, const T *__restrict__ ff,
+                                                     T *__restrict__ R)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T r[5] = {T(0), T(0), T(0), T(0), T(0)};
+    for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+        const int it = item[k];
+        if (it >= 0) {
+            const int j = it >> 1;
+            const T s = (it & 1) ? T(1) : T(-1);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) r[q] += s * ff[q * tot + j];
+        } else {
+            const int64_t j = m + (-it - 1);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) r[q] -= ff[q * tot + j];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) R[q * n + i] = r[q];
+}
+
+// local time step on a coarse level
+template <class T>
+__global__ __launch_bounds__(256) void k_coarse_dt(int64_t n, int64_t m, int64_t nb, double gam, double cfl, double mu,
+                                                   int viscous, const T *__restrict__ W, const int32_t *__restrict__ ptr,
+                                                   const int32_t *__restrict__ item, const double *__restrict__ S,
+                                                   const double *__restrict__ A, const double *__restrict__ bA,
+                                                   const double *__restrict__ V, T *__restrict__ dt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double rho = double(W[i]), ir = 1.0 / rho;
+    const double u = double(W[n + i]) * ir, v = double(W[2 * n + i]) * ir, w = double(W[3 * n + i]) * ir;
+    const double p = (gam - 1.0) * (double(W[4 * n + i]) - 0.5 * rho * (u * u + v * v + w * w));
+    const double cs = sqrt(gam * p * ir);
+    const double Vi = V[i];
+    double sum = 0.0;
+    for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+        const int it = item[k];
+        double ax, ay, az, s;
+        if (it >= 0) {
+            const int j = it >> 1;
+            ax = A[j];
+            ay = A[m + j];
+            az = A[2 * m + j];
+            s = S[j];
+        } else {
+            const int q = -it - 1;
+            ax = bA[q];
+            ay = bA[nb + q];
+            az = bA[2 * nb + q];
+            s = sqrt(ax * ax + ay * ay + az * az);
+        }
+        const double uA = fabs(u * ax + v * ay + w * az);
+        const double lam = cs + (viscous ? 2.0 * mu * s / (rho * Vi) : 0.0);
+        sum += uA + lam * s;
+    }
+    dt[i] = T(cfl * Vi / sum);
+}
+
+template <class T>
+__global__ void k_coarse_forcing(int64_t n5, const T *__restrict__ Rs, const T *__restrict__ R0, T *__restrict__ F)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n5) F[i] = Rs[i] - R0[i];
+}
+
+template <class T>
+__global__ void k_coarse_update(int64_t n, const T *__restrict__ dt, const double *__restrict__ V,
+                                const T *__restrict__ R, const T *__restrict__ F, T *__restrict__ W)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T h = dt[i] / T(V[i]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) W[q * n + i] += h * (R[q * n + i] + F[q * n + i]);
+}
+
+template <class T>
+__global__ void k_add(int64_t n5, const T *__restrict__ a, T *__restrict__ b)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n5) b[i] += a[i];
+}
+
+// restriction: Wc = sum V W / Vc (fine ids ascending), Rc = sum R; Tf fine type, Tc coarse type
+template <class Tf, class Tc>
+__global__ __launch_bounds__(256) void k_restrict(int64_t nc, int64_t nf, const int32_t *__restrict__ ptr,
+                                                  const int32_t *__restrict__ idx, const double *__restrict__ Vf,
+                                                  const double *__restrict__ Vc, const Tf *__restrict__ Wf,
+                                                  const Tf *__restrict__ Rf, Tc *__restrict__ Wc, Tc *__restrict__ Rc)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nc) return;
+    double w[5] = {0, 0, 0, 0, 0}, r[5] = {0, 0, 0, 0, 0};
+    for (int q = ptr[k]; q < ptr[k + 1]; ++q) {
+        const int i = idx[q];
+        const double v = Vf[i];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            if (Wf) w[c] += v * double(Wf[c * nf + i]);
+            if (Rf) r[c] += double(Rf[c * nf + i]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        if (Wc) Wc[c * nc + k] = Tc(w[c] / Vc[k]);
+        if (Rc) Rc[c * nc + k] = Tc(r[c]);
+    }
+}
+
+// prolongation of the correction: Wf += (Wc - Wc0)[f2c]
+template <class Tc, class Tf>
+__global__ void k_prolong(int64_t nf, int64_t nc, const int32_t *__restrict__ f2c, const Tc *__restrict__ Wc,
+                          const Tc *__restrict__ Wc0, Tf *__restrict__ Wf)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    const int k = f2c[i];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        if (Wc0) Wf[c * nf + i] += Tf(Wc[c * nc + k] - Wc0[c * nc + k]);
+        else Wf[c * nf + i] += Tf(Wc[c * nc + k]);
+    }
+}
+
+static Level *level_of(cgks_ctx *c, int level)
+{
+    if (level < 1 || level >= (int)c->lev.size()) throw Error{CGKS_E_STATE, "no such level: call cgks_agglomerate"};
+    return c->lev[level];
+}
+
+template <class T> static void kfvs_impl(cgks_ctx *c, int level, const T *W, T *R, T *ff)
+{
+    Level *L = level_of(c, level);
+    CoarseArgs<T> A;
+    A.n = L->n;
+    A.m = L->m;
+    A.nb = L->nb;
+    A.gam = c->prm.gamma;
+    A.K = (5.0 - 3.0 * c->prm.gamma) / (c->prm.gamma - 1.0);
+    A.W = W;
+    A.pa = L->pa.p;
+    A.pb = L->pb.p;
+    A.bown = L->bown.p;
+    A.btag = L->btag.p;
+    A.A = L->A.p;
+    A.bA = L->bA.p;
+    A.bc = c->bc.p;
+    A.fflux = ff;
+    const int64_t tot = L->m + L->nb;
+    hipLaunchKernelGGL((k_kfvs_face<T>), G1(tot), dim3(256), 0, c->stream, A);
+    hipLaunchKernelGGL((k_kfvs_gather<T>), G1(L->n), dim3(256), 0, c->stream, L->n, tot, L->m, L->cf_ptr.p,
+                       L->cf_item.p, ff, R);
+}
+
+void kfvs_residual(cgks_ctx *c, int level, const double *W, double *R)
+{
+    kfvs_impl<double>(c, level, W, R, level_of(c, level)->fflux.p);
+}
+
+void kfvs_residual32(cgks_ctx *c, int level, const float *W, float *R)
+{
+    Level *L = level_of(c, level);
+    L->ffluxf.ensure(5 * (L->m + L->nb) + 5);
+    kfvs_impl<float>(c, level, W, R, L->ffluxf.p);
+}
+
+template <class T> static void coarse_dt_impl(cgks_ctx *c, int level, const T *W, T *dt)
+{
+    Level *L = level_of(c, level);
+    hipLaunchKernelGGL((k_coarse_dt<T>), G1(L->n), dim3(256), 0, c->stream, L->n, L->m, L->nb, c->prm.gamma, c->prm.cfl,
+                       c->prm.mu, c->prm.viscous, W, L->cf_ptr.p, L->cf_item.p, L->S.p, L->A.p, L->bA.p, L->V.p, dt);
+}
+
+static const double *finer_vol(cgks_ctx *c, int level)
+{
+    return level == 1 ? c->vol.p : c->lev[level - 1]->V.p;
+}
+
+void restrict_level(cgks_ctx *c, int level, const double *Wf, const double *Rf, double *Wc, double *Rc)
+{
+    Level *L = level_of(c, level);
+    hipLaunchKernelGGL((k_restrict<double, double>), G1(L->n), dim3(256), 0, c->stream, L->n, L->nfine, L->c2f_ptr.p,
+                       L->c2f_idx.p, finer_vol(c, level), L->V.p, Wf, Rf, Wc, Rc);
+}
+
+void prolong_level(cgks_ctx *c, int level, const double *dWc, double *Wf)
+{
+    Level *L = level_of(c, level);
+    hipLaunchKernelGGL((k_prolong<double, double>), G1(L->nfine), dim3(256), 0, c->stream, L->nfine, L->n, L->f2c.p,
+                       dWc, (const double *)nullptr, Wf);
+}
+
+// ---------------------------------------------------------------- V-cycle (FP64 and mixed)
+// Coarse levels work in delta form: each level keeps its restricted state W0 and
+// the correction D = W - W0.  Because Res_2h(W0) + F = Res*_2h, the first sweep
+// is D = dt/V Res* exactly; the correction therefore vanishes with the fine
+// residual in any precision, and no bits of W0 are lost when it is prolonged.
+template <class T>
+__global__ void k_delta_first(int64_t n, const T *__restrict__ dt, const double *__restrict__ V, const T *__restrict__ Rs,
+                              T *__restrict__ D)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T h = dt[i] / T(V[i]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) D[q * n + i] = h * Rs[q * n + i];
+}
+
+template <class T>
+__global__ void k_delta_update(int64_t n, const T *__restrict__ dt, const double *__restrict__ V, const T *__restrict__ R,
+                               const T *__restrict__ F, T *__restrict__ D)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T h = dt[i] / T(V[i]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) D[q * n + i] += h * (R[q * n + i] + F[q * n + i]);
+}
+
+template <class T>
+__global__ void k_sum_state(int64_t n5, const T *__restrict__ W0, const T *__restrict__ D, T *__restrict__ W)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n5) W[i] = W0[i] + D[i];
+}
+
+template <class T> struct LevelBufs {
+    T *W0, *W, *D, *R, *F, *Rs, *dt, *ff;
+};
+
+template <class T> static LevelBufs<T> bufs(Level *L);
+template <> LevelBufs<double> bufs<double>(Level *L)
+{
+    L->D.ensure(5 * L->n);
+    return {L->W0.p, L->W.p, L->D.p, L->R.p, L->F.p, L->Rs.p, L->dt.p, L->fflux.p};
+}
+template <> LevelBufs<float> bufs<float>(Level *L)
+{
+    const size_t n5 = 5 * L->n;
+    L->W0f.ensure(n5);
+    L->Wf.ensure(n5);
+    L->Df.ensure(n5);
+    L->Rf.ensure(n5);
+    L->Ff.ensure(n5);
+    L->Rsf.ensure(n5);
+    L->dtf.ensure(L->n);
+    L->ffluxf.ensure(5 * (L->m + L->nb) + 5);
+    return {L->W0f.p, L->Wf.p, L->Df.p, L->Rf.p, L->Ff.p, L->Rsf.p, L->dtf.p, L->ffluxf.p};
+}
+
+// Visit level l (>= 1) with W0 and Rs set; leaves the correction in D.
+template <class T> static void coarse_visit(cgks_ctx *c, int l)
+{
+    Level *L = c->lev[l];
+    LevelBufs<T> b = bufs<T>(L);
+    hipStream_t st = c->stream;
+    const int64_t n = L->n, n5 = 5 * n;
+    // forcing F = Res* - Res_2h(W0)
+    kfvs_impl<T>(c, l, b.W0, b.R, b.ff);
+    hipLaunchKernelGGL((k_coarse_forcing<T>), G1(n5), dim3(256), 0, st, n5, b.Rs, b.R, b.F);
+    const int npre = c->prm.nu_pre[l];
+    if (npre > 0) {
+        coarse_dt_impl<T>(c, l, b.W0, b.dt);
+        hipLaunchKernelGGL((k_delta_first<T>), G1(n), dim3(256), 0, st, n, b.dt, L->V.p, b.Rs, b.D);
+    } else {
+        CGKS_HIP(hipMemsetAsync(b.D, 0, sizeof(T) * n5, st));
+    }
+    for (int s = 1; s < npre; ++s) {
+        hipLaunchKernelGGL((k_sum_state<T>), G1(n5), dim3(256), 0, st, n5, b.W0, b.D, b.W);
+        kfvs_impl<T>(c, l, b.W, b.R, b.ff);
+        coarse_dt_impl<T>(c, l, b.W, b.dt);
+        hipLaunchKernelGGL((k_delta_update<T>), G1(n), dim3(256), 0, st, n, b.dt, L->V.p, b.R, b.F, b.D);
+    }
+    if (l + 1 < (int)c->lev.size()) {
+        Level *C = c->lev[l + 1];
+        LevelBufs<T> cb = bufs<T>(C);
+        hipLaunchKernelGGL((k_sum_state<T>), G1(n5), dim3(256), 0, st, n5, b.W0, b.D, b.W);
+        kfvs_impl<T>(c, l, b.W, b.R, b.ff);
+        hipLaunchKernelGGL((k_add<T>), G1(n5), dim3(256), 0, st, n5, b.F, b.R);
+        hipLaunchKernelGGL((k_restrict<T, T>), G1(C->n), dim3(256), 0, st, C->n, C->nfine, C->c2f_ptr.p, C->c2f_idx.p,
+                           L->V.p, C->V.p, b.W, b.R, cb.W0, cb.Rs);
+        coarse_visit<T>(c, l + 1);
+        hipLaunchKernelGGL((k_prolong<T, T>), G1(C->nfine), dim3(256), 0, st, C->nfine, C->n, C->f2c.p, cb.D,
+                           (const T *)nullptr, b.D);
+    }
+    for (int s = 0; s < c->prm.nu_post[l]; ++s) {
+        hipLaunchKernelGGL((k_sum_state<T>), G1(n5), dim3(256), 0, st, n5, b.W0, b.D, b.W);
+        kfvs_impl<T>(c, l, b.W, b.R, b.ff);
+        coarse_dt_impl<T>(c, l, b.W, b.dt);
+        hipLaunchKernelGGL((k_delta_update<T>), G1(n), dim3(256), 0, st, n, b.dt, L->V.p, b.R, b.F, b.D);
+    }
+}
+
+// One V-cycle on the fine state; the norm of the smoothing residual is left in c->scal[0].
+void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flux, bool fp32_coarse)
+{
+    hipStream_t st = c->stream;
+    const int nb = norm_blocks(c->N);
+    c->partial.ensure(nb);
+    const int npre = std::max(1, c->prm.nu_pre[0]);
+    for (int s = 0; s < npre; ++s) {
+        launch_local_dt(c, W, c->dtc.p);
+        launch_recon(c, W, G, alpha, c->coef.p);
+        launch_face(c, MODE_RES, c->coef.p, c->dtc.p, -1.0, fp32_flux);
+        launch_gather_fe(c, W, G, alpha, c->dtc.p, c->Rw.p, s == 0 ? c->partial.p : nullptr);
+        if (s == 0) finish_norm(c, c->partial.p, nb, c->N, c->scal.p);
+    }
+    if (c->lev.size() > 1) {
+        launch_local_dt(c, W, c->dtc.p);
+        launch_recon(c, W, G, alpha, c->coef.p);
+        launch_face(c, MODE_RESONLY, c->coef.p, c->dtc.p, -1.0, fp32_flux);
+        launch_gather_res(c, c->Rw.p, nullptr, nullptr, MODE_RESONLY);
+        Level *L = c->lev[1];
+        if (!fp32_coarse) {
+            LevelBufs<double> b = bufs<double>(L);
+            hipLaunchKernelGGL((k_restrict<double, double>), G1(L->n), dim3(256), 0, st, L->n, L->nfine, L->c2f_ptr.p,
+                               L->c2f_idx.p, c->vol.p, L->V.p, W, c->Rw.p, b.W0, b.Rs);
+            coarse_visit<double>(c, 1);
+            hipLaunchKernelGGL((k_prolong<double, double>), G1(L->nfine), dim3(256), 0, st, L->nfine, L->n, L->f2c.p,
+                               b.D, (const double *)nullptr, W);
+        } else {
+            LevelBufs<float> b = bufs<float>(L);
+            hipLaunchKernelGGL((k_restrict<double, float>), G1(L->n), dim3(256), 0, st, L->n, L->nfine, L->c2f_ptr.p,
+                               L->c2f_idx.p, c->vol.p, L->V.p, W, c->Rw.p, b.W0, b.Rs);
+            coarse_visit<float>(c, 1);
+            hipLaunchKernelGGL((k_prolong<float, double>), G1(L->nfine), dim3(256), 0, st, L->nfine, L->n, L->f2c.p,
+                               b.D, (const float *)nullptr, W);
+        }
+    }
+    for (int s = 0; s < c->prm.nu_post[0]; ++s) {
+        launch_local_dt(c, W, c->dtc.p);
+        launch_recon(c, W, G, alpha, c->coef.p);
+        launch_face(c, MODE_RES, c->coef.p, c->dtc.p, -1.0, fp32_flux);
+        launch_gather_fe(c, W, G, alpha, c->dtc.p, c->Rw.p, nullptr);
+    }
+}
+
+}  // namespace cgks

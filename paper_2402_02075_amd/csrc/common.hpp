@@ -1,0 +1,166 @@
+// Library internals shared by the translation units of libcgks.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/cgks.h"
+
+namespace cgks {
+
+struct Error {
+    cgks_status code;
+    std::string msg;
+};
+
+#define CGKS_HIP(expr)                                                                                   \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess)                                                                            \
+            throw ::cgks::Error{CGKS_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)};      \
+    } while (0)
+
+template <class T> struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    void alloc(size_t count)
+    {
+        release();
+        n = count;
+        if (count) CGKS_HIP(hipMalloc(&p, sizeof(T) * count));
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void ensure(size_t count)
+    {
+        if (n < count) alloc(count);
+    }
+    void upload(const T *h, size_t count, hipStream_t s)
+    {
+        ensure(count);
+        if (count) CGKS_HIP(hipMemcpyAsync(p, h, sizeof(T) * count, hipMemcpyHostToDevice, s));
+    }
+    void upload(const std::vector<T> &v, hipStream_t s) { upload(v.data(), v.size(), s); }
+    std::vector<T> download(size_t count, hipStream_t s) const
+    {
+        std::vector<T> v(count);
+        if (count) {
+            CGKS_HIP(hipMemcpyAsync(v.data(), p, sizeof(T) * count, hipMemcpyDeviceToHost, s));
+            CGKS_HIP(hipStreamSynchronize(s));
+        }
+        return v;
+    }
+    ~DBuf() { release(); }
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+};
+
+// Boundary table kept in device memory, indexed by tag.
+struct BcTable {
+    int32_t kind[64];
+    double prim[64][5];
+};
+
+// One coarse level (l >= 1) of the hierarchy.
+struct Level {
+    int64_t n = 0, m = 0, nb = 0, nfine = 0;
+    DBuf<int32_t> f2c;               // [nfine] from level l-1
+    DBuf<int32_t> c2f_ptr, c2f_idx;  // CSR coarse -> fine, fine ids ascending
+    DBuf<double> V;                  // [n]
+    DBuf<double> P;                  // [3n] interleaved first moments
+    DBuf<int32_t> pa, pb;            // [m] coarse interior pairs
+    DBuf<double> S;                  // [m] summed fine areas
+    DBuf<double> A;                  // [3][m] summed area vectors (SoA)
+    DBuf<int32_t> bown, btag;        // [nb] coarse owner, tag of the fine boundary faces
+    DBuf<double> bA;                 // [3][nb]
+    DBuf<int32_t> cf_ptr, cf_item;   // CSR cell -> (pair j: 2j + side) / (boundary k: -(k+1))
+    // work buffers (FP64)
+    DBuf<double> W0, W, D, R, F, Rs, dt, fflux;
+    // FP32 work buffers (mixed precision)
+    DBuf<float> W0f, Wf, Df, Rf, Ff, Rsf, dtf, ffluxf;
+};
+
+}  // namespace cgks
+
+struct cgks_ctx {
+    cgks_params prm{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    int device = 0;
+    int gpu_cus = 256;
+
+    // fine mesh sizes
+    int64_t N = 0, F = 0, Fi = 0, Fb = 0, NGP = 0;
+    bool has_mesh = false;
+
+    // fine geometry (internal order = caller order for cells)
+    cgks::DBuf<double> vol, cen, mom2;  // [N], [3][N], [6][N]
+    cgks::DBuf<int32_t> fl, fr, ftag;   // [F]
+    cgks::DBuf<int32_t> fngp;           // [F] 3 or 4
+    cgks::DBuf<double> gpx, gpw, gpn;   // [4*3][F], [4][F] (w_k S), [4*3][F]
+    cgks::DBuf<double> fshift, favec, farea, fmom;  // [3][F], [3][F], [F], [3][F]
+    cgks::DBuf<int32_t> cf_ptr, cf_face;  // CSR cell -> 2*face + (cell is R)
+    // reconstruction structures
+    cgks::DBuf<int32_t> slot_nb;   // [6][N] neighbour cell, or -(face+1) for a boundary face, or INT32_MIN unused
+    cgks::DBuf<double> slot_av;    // [6*3][N] outward area vector / |Omega|
+    cgks::DBuf<int64_t> op_off;    // [N] offset into op, -1: Green-Gauss only
+    cgks::DBuf<uint8_t> n_int;     // [N] interior neighbours
+    cgks::DBuf<double> op;         // per cell: 9 x 4nb KKT operator, then 3 x nb LS operator
+    // boundary conditions
+    cgks::BcTable bc_host{};
+    cgks::DBuf<cgks::BcTable> bc;
+    // work buffers
+    cgks::DBuf<double> coef, dtc, fout, Rw, Gw, aw, Ws, Gs, L1, Lt1, Gc1, partial, scal;
+    cgks::DBuf<float> coeff32;
+    cgks::DBuf<int32_t> bad;
+    // multigrid hierarchy; lev[0] is a placeholder for the fine level
+    std::vector<cgks::Level *> lev;
+    // host pinned scalar for per-cycle reads
+    double *pinned = nullptr;
+    int32_t *pinned_i = nullptr;
+
+    ~cgks_ctx();
+};
+
+namespace cgks {
+
+// launch helpers (defined in the translation units that own the kernels)
+void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_cells, const uint8_t *ctype,
+                const int64_t *cptr, const int64_t *cnode, int64_t n_bf, const int64_t *bptr, const int64_t *bnode,
+                const int32_t *btag, const int64_t *canon);
+void launch_local_dt(cgks_ctx *c, const double *W, double *dt);
+void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef);
+enum FaceMode { MODE_RES = 0, MODE_RESONLY = 1, MODE_S1 = 2, MODE_S2 = 3 };
+void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cell, double dt_global, bool fp32);
+void launch_gather_res(cgks_ctx *c, double *R, double *Gn, double *an, int mode);
+void launch_gather_fe(cgks_ctx *c, double *W, double *G, double *alpha, const double *dt, double *Rout, double *norm_part);
+void launch_gather_s2o4(cgks_ctx *c, int stage, double dt, double *W, double *G, double *alpha);
+void launch_norm(cgks_ctx *c, const double *R, const double *vol, int64_t n, double *out);
+void finish_norm(cgks_ctx *c, const double *partials, int nblocks, int64_t n, double *out);
+int norm_blocks(int64_t n);
+void launch_fill(double *p, double v, int64_t n, hipStream_t s);
+
+// coarse levels
+void agglomerate_graph(cgks_ctx *c, int64_t n, const double *V, const double *P, int64_t m, const int32_t *pa,
+                       const int32_t *pb, const double *S, const double *M, const double *A, int passes, int32_t *f2c,
+                       double *Vc, double *Pc, int64_t *n_coarse, int64_t *m_coarse, int64_t *stats,
+                       // optional coarse-pair outputs (device, sized m): pairs, summed S, M (interleaved), A (interleaved)
+                       int32_t *pa_out, int32_t *pb_out, double *S_out, double *M_out, double *A_out);
+void build_hierarchy(cgks_ctx *c);
+void kfvs_residual(cgks_ctx *c, int level, const double *W, double *R);
+void kfvs_residual32(cgks_ctx *c, int level, const float *W, float *R);
+void restrict_level(cgks_ctx *c, int level, const double *Wf, const double *Rf, double *Wc, double *Rc);
+void prolong_level(cgks_ctx *c, int level, const double *dWc, double *Wf);
+void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flux, bool fp32_coarse);
+
+inline int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
+
+}  // namespace cgks

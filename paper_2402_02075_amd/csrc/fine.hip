@@ -1,0 +1,696 @@
+// Fine-level CGKS kernels: local time step, HWENO reconstruction, BGK flux at
+// face Gauss points, deterministic cell gathers and the residual norm.
+//
+// Paper: Sec. 2.2 (semi-discrete finite volume, Eq. semidiscrete), Sec. 2.3
+// (Eq. 2nd-flux), Sec. 2.4 (Eq. gauss-formula), Sec. 3 (HWENO, compression
+// factor, WENO weights), Sec. 4.2 (Eq. smo), local time stepping (Secs. 1, 4.3).
+//
+// Data layout (HBM): every per-cell and per-face array is structure-of-arrays,
+// component-major, so consecutive lanes touch consecutive addresses.  Faces are
+// ordered by (left cell, right cell), cells keep the caller's order, and each
+// cell gathers its faces through a CSR list in a fixed order: sums are
+// deterministic without atomics.
+#include "common.hpp"
+#include "gks_device.hpp"
+#include "bc_device.hpp"
+
+namespace cgks {
+
+// ---------------------------------------------------------------- local time step
+__global__ void k_local_dt(int64_t N, int64_t F, double gam, double cfl, double mu, int viscous,
+                           const double *__restrict__ W, const int32_t *__restrict__ cf_ptr,
+                           const int32_t *__restrict__ cf_face, const double *__restrict__ favec,
+                           const double *__restrict__ farea, const double *__restrict__ vol, double *__restrict__ dt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double rho = W[i], ir = 1.0 / rho;
+    const double u = W[N + i] * ir, v = W[2 * N + i] * ir, w = W[3 * N + i] * ir;
+    const double p = (gam - 1.0) * (W[4 * N + i] - 0.5 * rho * (u * u + v * v + w * w));
+    const double cs = sqrt(gam * p * ir);
+    const double V = vol[i];
+    double sum = 0.0;
+    for (int k = cf_ptr[i]; k < cf_ptr[i + 1]; ++k) {
+        const int f = cf_face[k] >> 1;
+        const double ax = favec[f], ay = favec[F + f], az = favec[2 * F + f];
+        const double S = farea[f];
+        const double un = fabs(u * ax + v * ay + w * az) / sqrt(ax * ax + ay * ay + az * az);
+        const double lam = un + cs + (viscous ? 2.0 * mu * S / (rho * V) : 0.0);
+        sum += lam * S;
+    }
+    dt[i] = cfl * V / sum;
+}
+
+// ---------------------------------------------------------------- reconstruction
+struct ReconArgs {
+    int64_t N, F;
+    double gam, weno_eps, g2;
+    const double *W, *G, *alpha, *vol, *mom2, *slot_av, *op;
+    const int32_t *slot_nb, *ftag;
+    const int64_t *op_off;
+    const uint8_t *n_int;
+    const BcTable *bc;
+    double *coef;
+};
+
+__global__ __launch_bounds__(128) void k_recon(ReconArgs A)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.N) return;
+    const int64_t N = A.N;
+    double Q0[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Q0[c] = A.W[c * N + i];
+    const int64_t off = A.op_off[i];
+    const int nb = A.n_int[i];
+    const int nc = 4 * nb;
+    double gg[5][3], gl[5][3], a[5][9];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) gg[c][d] = gl[c][d] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) a[c][k] = 0.0;
+    }
+    int m = 0;
+    for (int s = 0; s < 6; ++s) {
+        const int nbv = A.slot_nb[s * N + i];
+        if (nbv == INT32_MIN) break;
+        const double av[3] = {A.slot_av[(3 * s) * N + i], A.slot_av[(3 * s + 1) * N + i], A.slot_av[(3 * s + 2) * N + i]};
+        double Qm[5];
+        if (nbv >= 0) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) Qm[c] = A.W[c * N + nbv];
+            if (off >= 0) {
+                const double *op = A.op + off;
+                const double *ls = op + 9 * nc;
+                double Gm[15];
+#pragma unroll
+                for (int q = 0; q < 15; ++q) Gm[q] = A.G[q * N + nbv];
+                double om[9], od[9][3];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    om[k] = op[k * nc + m];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) od[k][d] = op[k * nc + nb + 3 * m + d];
+                }
+                const double l0 = ls[m], l1 = ls[nb + m], l2 = ls[2 * nb + m];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    const double e = Qm[c] - Q0[c];
+                    gl[c][0] += l0 * e;
+                    gl[c][1] += l1 * e;
+                    gl[c][2] += l2 * e;
+#pragma unroll
+                    for (int k = 0; k < 9; ++k)
+                        a[c][k] += om[k] * e + od[k][0] * Gm[3 * c] + od[k][1] * Gm[3 * c + 1] + od[k][2] * Gm[3 * c + 2];
+                }
+            }
+            ++m;
+        } else {
+            const int f = -nbv - 1;
+            const double na = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
+            const double n[3] = {av[0] / na, av[1] / na, av[2] / na};
+            ghost_state(*A.bc, A.ftag[f], n, Q0, A.gam, Qm);
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) gg[c][d] += 0.5 * (Qm[c] + Q0[c]) * av[d];
+    }
+    const double al = A.alpha ? A.alpha[i] : 1.0;
+    double *out = A.coef;
+    if (off < 0) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            out[(10 * c) * N + i] = Q0[c];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) out[(10 * c + 1 + d) * N + i] = al * gg[c][d];
+#pragma unroll
+            for (int k = 4; k < 10; ++k) out[(10 * c + k) * N + i] = 0.0;
+        }
+        return;
+    }
+    const double V = A.vol[i];
+    const double V13 = cbrt(V), V23 = V13 * V13;
+    double I[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) I[q] = A.mom2[q * N + i];
+    const double g2 = A.g2, g1 = 1.0 - A.g2;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        const double *ac = a[c];
+        const double p1x = al * gg[c][0], p1y = al * gg[c][1], p1z = al * gg[c][2];
+        const double bgg = V23 * (p1x * p1x + p1y * p1y + p1z * p1z);
+        const double bls = V23 * (gl[c][0] * gl[c][0] + gl[c][1] * gl[c][1] + gl[c][2] * gl[c][2]);
+        const double b1 = fmin(bgg, bls);
+        // beta_2: first derivatives (linear in dx) squared and integrated, plus constant second derivatives
+        const double hx[3] = {2.0 * ac[3], ac[6], ac[8]};
+        const double hy[3] = {ac[6], 2.0 * ac[4], ac[7]};
+        const double hz[3] = {ac[8], ac[7], 2.0 * ac[5]};
+        const double *hh[3] = {hx, hy, hz};
+        double first = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double *h = hh[d];
+            first += ac[d] * ac[d] * V + h[0] * h[0] * I[0] + h[1] * h[1] * I[1] + h[2] * h[2] * I[2] +
+                     2.0 * (h[0] * h[1] * I[3] + h[1] * h[2] * I[4] + h[0] * h[2] * I[5]);
+        }
+        const double second = 4.0 * (ac[3] * ac[3] + ac[4] * ac[4] + ac[5] * ac[5]) + ac[6] * ac[6] + ac[7] * ac[7] +
+                              ac[8] * ac[8];
+        const double b2 = first / V13 + second * V * V13;
+        const double den = Q0[c] * Q0[c] + b1 + 1e-40;
+        const double t1 = b1 / den, t2 = b2 / den;
+        const double sg = fabs(t2 - t1);
+        const double r1 = sg / (A.weno_eps + t1), r2 = sg / (A.weno_eps + t2);
+        double w1 = g1 * (1.0 + r1 * r1), w2 = g2 * (1.0 + r2 * r2);
+        const double ws = 1.0 / (w1 + w2);
+        w1 *= ws;
+        w2 *= ws;
+        // R = w2 (p2/g2 - g1/g2 p1) + w1 p1
+        const double c2 = w2 / g2, c1 = w1 - w2 * g1 / g2;
+        double r0 = Q0[c];
+#pragma unroll
+        for (int k = 3; k < 9; ++k) r0 -= ac[k] * I[k - 3] / V;
+        out[(10 * c) * N + i] = c2 * r0 + c1 * Q0[c];
+        out[(10 * c + 1) * N + i] = c2 * ac[0] + c1 * p1x;
+        out[(10 * c + 2) * N + i] = c2 * ac[1] + c1 * p1y;
+        out[(10 * c + 3) * N + i] = c2 * ac[2] + c1 * p1z;
+#pragma unroll
+        for (int k = 3; k < 9; ++k) out[(10 * c + 1 + k) * N + i] = c2 * ac[k];
+    }
+}
+
+// ---------------------------------------------------------------- face flux
+struct FaceArgs {
+    int64_t N, F;
+    GksCfg cfg;
+    double dt_global;
+    const double *coef, *dtc, *cen, *gpx, *gpw, *gpn, *fshift;
+    const int32_t *fl, *fr, *ftag, *fngp;
+    const BcTable *bc;
+    double *out;  // [nq][F]
+    int32_t *bad;
+};
+
+__device__ __forceinline__ void eval_poly(const double *__restrict__ coef, int64_t N, int64_t cell, const double dx[3],
+                                          double w[5], double g[15])
+{
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        double r[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) r[k] = coef[(10 * c + k) * N + cell];
+        const double x = dx[0], y = dx[1], z = dx[2];
+        w[c] = r[0] + r[1] * x + r[2] * y + r[3] * z + r[4] * x * x + r[5] * y * y + r[6] * z * z + r[7] * x * y +
+               r[8] * y * z + r[9] * x * z;
+        g[3 * c] = r[1] + 2.0 * r[4] * x + r[7] * y + r[9] * z;
+        g[3 * c + 1] = r[2] + 2.0 * r[5] * y + r[7] * x + r[8] * z;
+        g[3 * c + 2] = r[3] + 2.0 * r[6] * z + r[8] * y + r[9] * x;
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void to_local(const double w[5], const double g[15], const double n[3], const double t1[3],
+                                         const double t2[3], T wl[5], T gl[3][5])
+{
+    wl[0] = T(w[0]);
+    wl[1] = T(w[1] * n[0] + w[2] * n[1] + w[3] * n[2]);
+    wl[2] = T(w[1] * t1[0] + w[2] * t1[1] + w[3] * t1[2]);
+    wl[3] = T(w[1] * t2[0] + w[2] * t2[1] + w[3] * t2[2]);
+    wl[4] = T(w[4]);
+    const double *E[3] = {n, t1, t2};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        double D[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) D[c] = g[3 * c] * E[j][0] + g[3 * c + 1] * E[j][1] + g[3 * c + 2] * E[j][2];
+        gl[j][0] = T(D[0]);
+        gl[j][1] = T(D[1] * n[0] + D[2] * n[1] + D[3] * n[2]);
+        gl[j][2] = T(D[1] * t1[0] + D[2] * t1[1] + D[3] * t1[2]);
+        gl[j][3] = T(D[1] * t2[0] + D[2] * t2[1] + D[3] * t2[2]);
+        gl[j][4] = T(D[4]);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void to_global(const T l[5], const double n[3], const double t1[3], const double t2[3], double o[5])
+{
+    o[0] = double(l[0]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) o[1 + d] = double(l[1]) * n[d] + double(l[2]) * t1[d] + double(l[3]) * t2[d];
+    o[4] = double(l[4]);
+}
+
+__device__ __forceinline__ double group4_sum(double v)
+{
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    return v;
+}
+
+// One lane per (face, Gauss point); four lanes per face, summed with lane shuffles.
+template <class T, int MODE> __global__ __launch_bounds__(256) void k_face(FaceArgs A)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = gid >> 2;
+    const int k = (int)(gid & 3);
+    if (f >= A.F) return;  // whole groups of four leave together
+    const int64_t F = A.F, N = A.N;
+    const int ngp = A.fngp[f];
+    const bool act = k < ngp;
+    const int L = A.fl[f], R = A.fr[f];
+    constexpr int NQ = MODE == MODE_RES ? 21 : MODE == MODE_RESONLY ? 5 : MODE == MODE_S1 ? 41 : 26;
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    double alpha_k = 1.0;
+    if (act) {
+        const double x[3] = {A.gpx[(3 * k) * F + f], A.gpx[(3 * k + 1) * F + f], A.gpx[(3 * k + 2) * F + f]};
+        const double n[3] = {A.gpn[(3 * k) * F + f], A.gpn[(3 * k + 1) * F + f], A.gpn[(3 * k + 2) * F + f]};
+        const double wS = A.gpw[k * F + f];
+        double dtf = A.dt_global;
+        if (dtf <= 0.0) dtf = R >= 0 ? fmin(A.dtc[L], A.dtc[R]) : A.dtc[L];
+        double WL[5], GL[15], WR[5], GR[15];
+        {
+            const double dx[3] = {x[0] - A.cen[L], x[1] - A.cen[N + L], x[2] - A.cen[2 * N + L]};
+            eval_poly(A.coef, N, L, dx, WL, GL);
+        }
+        if (R >= 0) {
+            const double dx[3] = {x[0] - A.fshift[f] - A.cen[R], x[1] - A.fshift[F + f] - A.cen[N + R],
+                                  x[2] - A.fshift[2 * F + f] - A.cen[2 * N + R]};
+            eval_poly(A.coef, N, R, dx, WR, GR);
+        } else {
+            const int tag = A.ftag[f];
+            ghost_state(*A.bc, tag, n, WL, A.cfg.gamma, WR);
+            ghost_grad(*A.bc, tag, n, GL, GR);
+        }
+        double t1[3], t2[3];
+        onb(n, t1, t2);
+        T wl[5], wr[5], gl[3][5], gr[3][5];
+        to_local(WL, GL, n, t1, t2, wl, gl);
+        to_local(WR, GR, n, t1, t2, wr, gr);
+        GksMoments<T> mo;
+        if (!gks_moments(wl, gl, wr, gr, T(A.cfg.gamma), T(A.cfg.K), mo)) {
+            atomicMin(A.bad, L);
+        } else {
+            T tau, taun;
+            collision_times(mo, T(dtf), A.cfg, tau, taun);
+            T Fl[5];
+            double Fg[5];
+            flux_integrated(mo, T(dtf), tau, taun, A.cfg, Fl);
+            to_global(Fl, n, t1, t2, Fg);
+            if (MODE == MODE_RES || MODE == MODE_RESONLY) {
+                const double s = wS / dtf;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) acc[q] = s * Fg[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) acc[q] = wS * Fg[q];
+                T Fh[5];
+                double Fhg[5];
+                flux_integrated(mo, T(0.5 * dtf), tau, taun, A.cfg, Fh);
+                to_global(Fh, n, t1, t2, Fhg);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) acc[5 + q] = wS * Fhg[q];
+            }
+            if (MODE == MODE_RES) {
+                T Wt[5];
+                double Wg[5];
+                value_at(mo, T(dtf), tau, taun, Wt);
+                to_global(Wt, n, t1, t2, Wg);
+#pragma unroll
+                for (int q = 0; q < 5; ++q)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) acc[5 + 3 * q + d] = wS * Wg[q] * n[d];
+            } else if (MODE == MODE_S1) {
+                T Wt[5];
+                double Wg[5], Wc[5];
+                value_at(mo, T(0.5 * dtf), tau, taun, Wt);
+                to_global(Wt, n, t1, t2, Wg);
+                T wc[5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) wc[q] = mo.Vc[0][q];
+                to_global(wc, n, t1, t2, Wc);
+#pragma unroll
+                for (int q = 0; q < 5; ++q)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        acc[10 + 3 * q + d] = wS * Wg[q] * n[d];
+                        acc[25 + 3 * q + d] = wS * Wc[q] * n[d];
+                    }
+            } else if (MODE == MODE_S2) {
+                T Wt[5];
+                double Wg[5];
+                value_at(mo, T(dtf), tau, taun, Wt);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) Wt[q] -= mo.Vc[0][q];
+                to_global(Wt, n, t1, t2, Wg);
+#pragma unroll
+                for (int q = 0; q < 5; ++q)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) acc[10 + 3 * q + d] = wS * Wg[q] * n[d];
+            }
+            if (MODE != MODE_RESONLY && R >= 0) {
+                // compression factor from the two Gauss-point states (Sec. 3.3)
+                const double pl = double(mo.pl), pr = double(mo.pr);
+                const double cl = sqrt(A.cfg.gamma * pl / double(wl[0])), cr = sqrt(A.cfg.gamma * pr / double(wr[0]));
+                const double unl = double(wl[1]) / double(wl[0]), unr = double(wr[1]) / double(wr[0]);
+                const double vtl = sqrt(double(wl[2]) * double(wl[2]) + double(wl[3]) * double(wl[3])) / double(wl[0]);
+                const double vtr = sqrt(double(wr[2]) * double(wr[2]) + double(wr[3]) * double(wr[3])) / double(wr[0]);
+                const double dp = fabs(pl - pr);
+                const double dmn = unl / cl - unr / cr, dmt = vtl / cl - vtr / cr;
+                const double Aq = dp / pl + dp / pr + dmn * dmn + dmt * dmt;
+                alpha_k = 1.0 / (1.0 + Aq * Aq);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = group4_sum(acc[q]);
+    if (MODE != MODE_RESONLY) {
+        alpha_k *= __shfl_xor(alpha_k, 1, 64);
+        alpha_k *= __shfl_xor(alpha_k, 2, 64);
+    }
+    if (k == 0) {
+        if (MODE == MODE_RES) {
+#pragma unroll
+            for (int q = 0; q < 20; ++q) A.out[q * F + f] = acc[q];
+            A.out[20 * F + f] = alpha_k;
+        } else if (MODE == MODE_RESONLY) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) A.out[q * F + f] = acc[q];
+        } else if (MODE == MODE_S1) {
+#pragma unroll
+            for (int q = 0; q < 40; ++q) A.out[q * F + f] = acc[q];
+            A.out[40 * F + f] = alpha_k;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 25; ++q) A.out[q * F + f] = acc[q];
+            A.out[25 * F + f] = alpha_k;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- gathers
+struct GatherArgs {
+    int64_t N, F;
+    const int32_t *cf_ptr, *cf_face;
+    const double *fout, *vol;
+};
+
+// R = -sum s F, Gn = alpha S/V, alpha = prod; optionally W += dt/V R (FE) and norm partials.
+template <bool FE, bool GRAD>
+__global__ __launch_bounds__(256) void k_gather(GatherArgs A, double *__restrict__ R, double *__restrict__ Gn,
+                                                double *__restrict__ an, double *__restrict__ W,
+                                                const double *__restrict__ dt, double *__restrict__ part)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = A.N, F = A.F;
+    double r2 = 0.0;
+    if (i < N) {
+        double r[5] = {0, 0, 0, 0, 0};
+        double g[15];
+#pragma unroll
+        for (int q = 0; q < 15; ++q) g[q] = 0.0;
+        double al = 1.0;
+        for (int k = A.cf_ptr[i]; k < A.cf_ptr[i + 1]; ++k) {
+            const int it = A.cf_face[k];
+            const int f = it >> 1;
+            const double s = (it & 1) ? -1.0 : 1.0;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) r[q] -= s * A.fout[q * F + f];
+            if (GRAD) {
+#pragma unroll
+                for (int q = 0; q < 15; ++q) g[q] += s * A.fout[(5 + q) * F + f];
+                al *= A.fout[20 * F + f];
+            }
+        }
+        const double iv = 1.0 / A.vol[i];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) R[q * N + i] = r[q];
+        if (GRAD) {
+#pragma unroll
+            for (int q = 0; q < 15; ++q) Gn[q * N + i] = al * g[q] * iv;
+            an[i] = al;
+        }
+        if (FE) {
+            const double h = dt[i] * iv;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) W[q * N + i] += h * r[q];
+        }
+        const double rr = r[0] * iv;
+        r2 = rr * rr;
+    }
+    if (part) {
+        // deterministic block reduction in a fixed tree
+        __shared__ double sm[256];
+        sm[threadIdx.x] = r2;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gather_s2o4(GatherArgs A, int stage, double dt, double *__restrict__ W,
+                                                     double *__restrict__ G, double *__restrict__ alpha,
+                                                     double *__restrict__ Ws, double *__restrict__ Gs,
+                                                     double *__restrict__ as, double *__restrict__ L1,
+                                                     double *__restrict__ Lt1, double *__restrict__ Gc1)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = A.N, F = A.F;
+    if (i >= N) return;
+    double ri[5] = {0, 0, 0, 0, 0}, rh[5] = {0, 0, 0, 0, 0}, g1[15], g2[15];
+#pragma unroll
+    for (int q = 0; q < 15; ++q) g1[q] = g2[q] = 0.0;
+    double al = 1.0;
+    for (int k = A.cf_ptr[i]; k < A.cf_ptr[i + 1]; ++k) {
+        const int it = A.cf_face[k];
+        const int f = it >> 1;
+        const double s = (it & 1) ? -1.0 : 1.0;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            ri[q] -= s * A.fout[q * F + f];
+            rh[q] -= s * A.fout[(5 + q) * F + f];
+        }
+#pragma unroll
+        for (int q = 0; q < 15; ++q) g1[q] += s * A.fout[(10 + q) * F + f];
+        if (stage == 1) {
+#pragma unroll
+            for (int q = 0; q < 15; ++q) g2[q] += s * A.fout[(25 + q) * F + f];
+            al *= A.fout[40 * F + f];
+        } else {
+            al *= A.fout[25 * F + f];
+        }
+    }
+    const double V = A.vol[i], iv = 1.0 / V;
+    if (stage == 1) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const double L = (4.0 * rh[q] - ri[q]) / (dt * V);
+            const double Lt = 4.0 * (ri[q] - 2.0 * rh[q]) / (dt * dt * V);
+            L1[q * N + i] = L;
+            Lt1[q * N + i] = Lt;
+            Ws[q * N + i] = W[q * N + i] + 0.5 * dt * L + 0.125 * dt * dt * Lt;
+        }
+#pragma unroll
+        for (int q = 0; q < 15; ++q) {
+            Gs[q * N + i] = al * g1[q] * iv;
+            Gc1[q * N + i] = g2[q] * iv;
+        }
+        as[i] = al;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const double Lt2 = 4.0 * (ri[q] - 2.0 * rh[q]) / (dt * dt * V);
+            W[q * N + i] += dt * L1[q * N + i] + dt * dt / 6.0 * (Lt1[q * N + i] + 2.0 * Lt2);
+        }
+#pragma unroll
+        for (int q = 0; q < 15; ++q) G[q * N + i] = al * (Gc1[q * N + i] + g1[q] * iv);
+        alpha[i] = al;
+    }
+}
+
+// ---------------------------------------------------------------- norm
+__global__ __launch_bounds__(256) void k_norm_part(int64_t n, const double *__restrict__ R,
+                                                   const double *__restrict__ vol, double *__restrict__ part)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (i < n) {
+        const double r = R[i] / vol[i];
+        v = r * r;
+    }
+    __shared__ double sm[256];
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(256) void k_norm_final(int nb, int64_t n, const double *__restrict__ part,
+                                                    double *__restrict__ out)
+{
+    __shared__ double sm[256];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) v += part[b];
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sqrt(sm[0] / (double)n);
+}
+
+__global__ void k_fill(double *p, double v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------- launchers
+static GksCfg cfg_of(const cgks_ctx *c)
+{
+    GksCfg g;
+    g.gamma = c->prm.gamma;
+    g.K = (5.0 - 3.0 * c->prm.gamma) / (c->prm.gamma - 1.0);
+    g.mu = c->prm.mu;
+    g.prandtl = c->prm.prandtl;
+    g.eps_tau = c->prm.eps_tau;
+    g.c_tau = c->prm.c_tau;
+    g.viscous = c->prm.viscous;
+    return g;
+}
+
+void launch_fill(double *p, double v, int64_t n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, v, n);
+}
+
+void launch_local_dt(cgks_ctx *c, const double *W, double *dt)
+{
+    hipLaunchKernelGGL(k_local_dt, dim3(blocks_for(c->N, 256)), dim3(256), 0, c->stream, c->N, c->F, c->prm.gamma,
+                       c->prm.cfl, c->prm.mu, c->prm.viscous, W, c->cf_ptr.p, c->cf_face.p, c->favec.p, c->farea.p,
+                       c->vol.p, dt);
+}
+
+void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef)
+{
+    ReconArgs A;
+    A.N = c->N;
+    A.F = c->F;
+    A.gam = c->prm.gamma;
+    A.weno_eps = c->prm.weno_eps;
+    A.g2 = c->prm.gamma_lin;
+    A.W = W;
+    A.G = G;
+    A.alpha = alpha;
+    A.vol = c->vol.p;
+    A.mom2 = c->mom2.p;
+    A.slot_av = c->slot_av.p;
+    A.op = c->op.p;
+    A.slot_nb = c->slot_nb.p;
+    A.ftag = c->ftag.p;
+    A.op_off = c->op_off.p;
+    A.n_int = c->n_int.p;
+    A.bc = c->bc.p;
+    A.coef = coef;
+    hipLaunchKernelGGL(k_recon, dim3(blocks_for(c->N, 128)), dim3(128), 0, c->stream, A);
+}
+
+void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cell, double dt_global, bool fp32)
+{
+    FaceArgs A;
+    A.N = c->N;
+    A.F = c->F;
+    A.cfg = cfg_of(c);
+    A.dt_global = dt_global;
+    A.coef = coef;
+    A.dtc = dt_cell;
+    A.cen = c->cen.p;
+    A.gpx = c->gpx.p;
+    A.gpw = c->gpw.p;
+    A.gpn = c->gpn.p;
+    A.fshift = c->fshift.p;
+    A.fl = c->fl.p;
+    A.fr = c->fr.p;
+    A.ftag = c->ftag.p;
+    A.fngp = c->fngp.p;
+    A.bc = c->bc.p;
+    A.out = c->fout.p;
+    A.bad = c->bad.p;
+    const dim3 grid(blocks_for(4 * c->F, 256)), blk(256);
+    if (fp32) {
+        switch (mode) {
+        case MODE_RES: hipLaunchKernelGGL((k_face<float, MODE_RES>), grid, blk, 0, c->stream, A); break;
+        case MODE_RESONLY: hipLaunchKernelGGL((k_face<float, MODE_RESONLY>), grid, blk, 0, c->stream, A); break;
+        default: throw Error{CGKS_E_ARG, "FP32 flux supports the steady modes only"};
+        }
+    } else {
+        switch (mode) {
+        case MODE_RES: hipLaunchKernelGGL((k_face<double, MODE_RES>), grid, blk, 0, c->stream, A); break;
+        case MODE_RESONLY: hipLaunchKernelGGL((k_face<double, MODE_RESONLY>), grid, blk, 0, c->stream, A); break;
+        case MODE_S1: hipLaunchKernelGGL((k_face<double, MODE_S1>), grid, blk, 0, c->stream, A); break;
+        default: hipLaunchKernelGGL((k_face<double, MODE_S2>), grid, blk, 0, c->stream, A); break;
+        }
+    }
+}
+
+static GatherArgs gargs(cgks_ctx *c)
+{
+    GatherArgs g;
+    g.N = c->N;
+    g.F = c->F;
+    g.cf_ptr = c->cf_ptr.p;
+    g.cf_face = c->cf_face.p;
+    g.fout = c->fout.p;
+    g.vol = c->vol.p;
+    return g;
+}
+
+int norm_blocks(int64_t n) { return blocks_for(n, 256); }
+
+void launch_gather_res(cgks_ctx *c, double *R, double *Gn, double *an, int mode)
+{
+    const dim3 grid(blocks_for(c->N, 256)), blk(256);
+    if (mode == MODE_RES)
+        hipLaunchKernelGGL((k_gather<false, true>), grid, blk, 0, c->stream, gargs(c), R, Gn, an, nullptr, nullptr, nullptr);
+    else
+        hipLaunchKernelGGL((k_gather<false, false>), grid, blk, 0, c->stream, gargs(c), R, nullptr, nullptr, nullptr,
+                           nullptr, nullptr);
+}
+
+void launch_gather_fe(cgks_ctx *c, double *W, double *G, double *alpha, const double *dt, double *Rout, double *part)
+{
+    const dim3 grid(blocks_for(c->N, 256)), blk(256);
+    hipLaunchKernelGGL((k_gather<true, true>), grid, blk, 0, c->stream, gargs(c), Rout, G, alpha, W, dt, part);
+}
+
+void launch_gather_s2o4(cgks_ctx *c, int stage, double dt, double *W, double *G, double *alpha)
+{
+    const dim3 grid(blocks_for(c->N, 256)), blk(256);
+    hipLaunchKernelGGL(k_gather_s2o4, grid, blk, 0, c->stream, gargs(c), stage, dt, W, G, alpha, c->Ws.p, c->Gs.p,
+                       c->aw.p, c->L1.p, c->Lt1.p, c->Gc1.p);
+}
+
+void launch_norm(cgks_ctx *c, const double *R, const double *vol, int64_t n, double *out)
+{
+    const int nb = norm_blocks(n);
+    c->partial.ensure(nb);
+    hipLaunchKernelGGL(k_norm_part, dim3(nb), dim3(256), 0, c->stream, n, R, vol, c->partial.p);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, c->stream, nb, n, c->partial.p, out);
+}
+
+void finish_norm(cgks_ctx *c, const double *partials, int nblocks, int64_t n, double *out)
+{
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, c->stream, nblocks, n, partials, out);
+}
+
+}  // namespace cgks

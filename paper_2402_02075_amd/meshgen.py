@@ -568,3 +568,13 @@ def random_smooth_state(centroids_hint: np.ndarray, seed=3, amp=0.05, gamma=1.4)
     rho, u, v, w, p = prim
     W = np.stack([rho, rho * u, rho * v, rho * w, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)])
     return W
+
+
+def cell_node_mean(m: Mesh) -> np.ndarray:
+    """Mean of each cell's node coordinates (a point inside the cell; used only to
+    place analytic input fields, not a geometric quantity of the scheme)."""
+    cnt = np.diff(m.cnode_ptr)
+    idx = np.repeat(np.arange(m.n_cells), cnt)
+    s = np.zeros((m.n_cells, 3))
+    np.add.at(s, idx, m.xyz[m.cnode])
+    return s / cnt[:, None]

@@ -1,0 +1,57 @@
+"""Shared helpers of the GPU parity tests (no method arithmetic here).
+
+The parity bar for FP64 cell residuals is relative to the magnitude of the
+fluxes that make them up: |R_gpu - R_oracle| <= tol * S_i * Fscale_c, where S_i
+is the cell's surface area and Fscale_c the largest Euler-flux magnitude of
+component c over the mesh.  A residual near steady state is a cancelling sum of
+face fluxes, so a plain relative error of R is meaningless there.
+"""
+import sys
+
+import numpy as np
+
+from paper_2402_02075_amd import meshgen as mg
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def flux_scale(W, gamma=1.4):
+    rho = W[0]
+    u = W[1:4] / rho
+    q = np.sqrt((u * u).sum(0))
+    p = (gamma - 1) * (W[4] - 0.5 * rho * (u * u).sum(0))
+    c = np.sqrt(gamma * p / rho)
+    s = q + c
+    return np.array([np.max(rho * s), np.max(rho * q * s + p), np.max(rho * q * s + p), np.max(rho * q * s + p),
+                     np.max((W[4] + p) * s)])
+
+
+def cell_surface(F, n):
+    s = np.zeros(n)
+    np.add.at(s, F["fl"], F["area"])
+    sel = F["fr"] >= 0
+    np.add.at(s, F["fr"][sel], F["area"][sel])
+    return s
+
+
+def assert_residual_close(Rg, Ro, surf, fscale, tol=1e-12, what="R"):
+    bound = tol * surf[None, :] * fscale[:, None]
+    err = np.abs(Rg - Ro)
+    ratio = (err / bound).max()
+    assert ratio <= 1.0, f"{what}: max err/bound = {ratio:.3e} (max abs err {err.max():.3e})"
+    return ratio
+
+
+def channel_bcs(set_bc, farfield_kind, slip_kind, U=(0.5, 0.0, 0.0)):
+    prim = np.array([1.0, *U, 1.0 / 1.4])
+    for tag in (mg.TAG_INLET, mg.TAG_OUTLET):
+        set_bc(tag, farfield_kind, prim)
+    for tag in (mg.TAG_WALL_BOTTOM, mg.TAG_WALL_TOP, mg.TAG_WALL_SIDE):
+        set_bc(tag, slip_kind)

@@ -1,0 +1,172 @@
+"""GPU parity of agglomeration, coarse KFVS, transfers and the V-cycle.
+
+Agglomeration is integer work decided by a floating-point predicate: given
+identical graph arrays (the oracle's geometry fed to both sides) the coarse map,
+coarse volumes and first moments must be bit-identical, at small and at full
+bump-channel size.  Coarse operators and the V-cycle are FP64 and compared
+with the residual bound of the fine tests.
+"""
+import numpy as np
+import pytest
+
+from paper_2402_02075_amd import meshgen as mg
+
+from gpu_common import assert_residual_close, flux_scale, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def cg(torch):
+    from paper_2402_02075_amd import cgks
+    return cgks
+
+
+def _bcs():
+    prim = np.array([1.0, 0.5, 0.0, 0.0, 1.0 / 1.4])
+    out = [(mg.TAG_INLET, 3, prim), (mg.TAG_OUTLET, 3, prim)]
+    for t in (mg.TAG_WALL_BOTTOM, mg.TAG_WALL_TOP, mg.TAG_WALL_SIDE):
+        out.append((t, 1, None))
+    return out
+
+
+def _pair(oracle, cg, m, **par):
+    M = oracle.Mesh(m)
+    S = cg.Solver(**par)
+    S.set_mesh(m)
+    for tag, kind, prim in _bcs():
+        M.set_bc(tag, kind, prim)
+        S.set_bc(tag, kind, prim)
+    return M, S
+
+
+def _oracle_graph(oracle, M):
+    vol, cen, _ = M.cells()
+    F = M.faces()
+    sel = (F["fr"] >= 0) & np.all(F["shift"] == 0, axis=1)
+    return oracle.Graph(vol, vol[:, None] * cen, F["fl"][sel], F["fr"][sel], F["area"][sel], F["fmom"][sel],
+                        F["avec"][sel])
+
+
+@pytest.mark.parametrize("size", ["small", "full"])
+def test_agglomeration_bit_exact(oracle, cg, torch, size):
+    m = mg.bump_channel(24, 12, 6, n_prism=2, n_pyr=3, jitter=0.05, seed=1) if size == "small" else mg.bump_channel()
+    say(f"[gpu] agglomerate_graph {size} cells={m.n_cells}")
+    M = oracle.Mesh(m)
+    g = _oracle_graph(oracle, M)
+    S = cg.Solver()
+    for passes in (1, 3):
+        f2c_o, cg_o, st_o = oracle.agglomerate_graph(g, seed=1, passes=passes)
+        dev = lambda a, dt=np.float64: to_dev(torch, np.ascontiguousarray(a, dtype=dt))
+        f2c, Vc, Pc, nc, mc, st = S.agglomerate_graph(dev(g.V), dev(g.P), dev(g.a, np.int32), dev(g.b, np.int32),
+                                                      dev(g.S), dev(g.M), dev(g.A), passes)
+        assert nc == len(cg_o.V) and mc == len(cg_o.a)
+        np.testing.assert_array_equal(f2c.cpu().numpy(), f2c_o)
+        np.testing.assert_array_equal(Vc.cpu().numpy(), cg_o.V)   # bit-identical sums
+        np.testing.assert_array_equal(Pc.cpu().numpy(), cg_o.P)
+        np.testing.assert_array_equal(st, st_o[:passes])
+
+
+def test_agglomeration_other_seed_and_determinism(oracle, cg, torch):
+    m = mg.bump_channel(20, 10, 6, n_prism=2, n_pyr=3, jitter=0.05, seed=4)
+    M = oracle.Mesh(m)
+    g = _oracle_graph(oracle, M)
+    S = cg.Solver(seed=7)
+    dev = lambda a, dt=np.float64: to_dev(torch, np.ascontiguousarray(a, dtype=dt))
+    args = (dev(g.V), dev(g.P), dev(g.a, np.int32), dev(g.b, np.int32), dev(g.S), dev(g.M), dev(g.A), 3)
+    say("[gpu] agglomerate seed 7 twice")
+    a = S.agglomerate_graph(*args)[0].cpu().numpy()
+    b = S.agglomerate_graph(*args)[0].cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+    f2c_o, _, _ = oracle.agglomerate_graph(g, seed=7, passes=3)
+    np.testing.assert_array_equal(a, f2c_o)
+
+
+@pytest.fixture(scope="module")
+def hier(oracle, cg, torch):
+    m = mg.bump_channel(24, 12, 6, n_prism=2, n_pyr=3, jitter=0.05, seed=1, amp=0.05)
+    say(f"[gpu] hierarchy cells={m.n_cells}")
+    M, S = _pair(oracle, cg, m)
+    sizes = S.agglomerate()
+    H = oracle.Hierarchy(M, levels=3, passes=3, seed=1)
+    return m, M, S, H, sizes
+
+
+def test_hierarchy_maps_match_oracle(hier):
+    m, M, S, H, sizes = hier
+    for l in (1, 2):
+        L = H.level(l)
+        assert sizes[l] == L["n"]
+        np.testing.assert_array_equal(S.level_map(l).cpu().numpy(), L["f2c"])
+
+
+def test_kfvs_restrict_prolong(oracle, torch, hier):
+    m, M, S, H, sizes = hier
+    par = oracle.params()
+    x = mg.cell_node_mean(m)
+    W = mg.random_smooth_state(x, seed=9, amp=0.08)
+    rng = np.random.default_rng(2)
+    R = rng.normal(size=W.shape) * 1e-3
+    Wd, Rd = to_dev(torch, W), to_dev(torch, R)
+    for l in (1, 2):
+        if l == 1:
+            Wf, Rf, Wfd, Rfd = W, R, Wd, Rd
+        Wc, Rc = S.restrict(l, Wfd, Rfd)
+        oWc, oRc = H.restrict(l, Wf, Rf)
+        np.testing.assert_allclose(Wc.cpu().numpy(), oWc, rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(Rc.cpu().numpy(), oRc, rtol=1e-13, atol=1e-17)
+        Rk = S.kfvs_residual(l, Wc).cpu().numpy()
+        oRk = H.kfvs_residual(par, l, oWc)
+        Lv = H.level(l)
+        surf = np.zeros(Lv["n"])
+        nA = np.linalg.norm(Lv["A"], axis=1)
+        np.add.at(surf, Lv["a"], nA)
+        np.add.at(surf, Lv["b"], nA)
+        surf += 1.0  # boundary faces
+        assert_residual_close(Rk, oRk, surf, flux_scale(oWc), what=f"kfvs level {l}")
+        dW = rng.normal(size=oWc.shape) * 1e-4
+        Wp = Wfd.clone()
+        S.prolong(l, to_dev(torch, dW), Wp)
+        np.testing.assert_allclose(Wp.cpu().numpy(), H.prolong(l, dW, Wfd.cpu().numpy()), rtol=0, atol=0)
+        Wf, Rf, Wfd, Rfd = oWc, oRc, Wc, Rc
+
+
+def test_vcycle_matches_oracle(oracle, torch, hier):
+    m, M, S, H, sizes = hier
+    par = oracle.params()
+    W, G = mg.uniform_state(m.n_cells)
+    al = np.ones(m.n_cells)
+    Wd, Gd, ad = to_dev(torch, W), to_dev(torch, G), to_dev(torch, al)
+    say("[gpu] vcycle x3")
+    hist, conv = S.vcycle(Wd, Gd, ad, 3, 1e-30)
+    ohist = [H.vcycle(par, W, G, al) for _ in range(3)]
+    np.testing.assert_allclose(hist, ohist, rtol=1e-10)
+    np.testing.assert_allclose(Wd.cpu().numpy(), W, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(ad.cpu().numpy(), al, rtol=1e-9)
+
+
+def test_vcycle_converges_faster_than_explicit(cg, torch, hier):
+    m, M, S, H, sizes = hier
+    W, G = mg.uniform_state(m.n_cells)
+    res = {}
+    for mode in ("explicit", "vcycle"):
+        Wd, Gd, ad = to_dev(torch, W), to_dev(torch, G), to_dev(torch, np.ones(m.n_cells))
+        if mode == "vcycle":
+            hist, _ = S.vcycle(Wd, Gd, ad, 60, 1e-30)
+        else:
+            rn = S.empty(1)
+            hist = []
+            for _ in range(60):
+                S.step(Wd, Gd, ad, -1.0, rn)
+                hist.append(rn.item())
+        res[mode] = hist[-1] / hist[0]
+    say(f"[gpu] drop after 60: {res}")
+    assert res["vcycle"] < res["explicit"]

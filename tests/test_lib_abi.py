@@ -1,0 +1,34 @@
+"""The C ABI library loads on the CPU and exports every function include/cgks.h declares."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "cgks.h")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cgks_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_set():
+    from paper_2402_02075_amd import cgks
+    assert set(_declared()) == set(cgks.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    path = os.path.join(ROOT, "paper_2402_02075_amd", "libcgks.so")
+    assert os.path.exists(path), "libcgks.so not built"
+    lib = ctypes.CDLL(path)
+    missing = [s for s in _declared() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_default_params_without_gpu():
+    from paper_2402_02075_amd import cgks
+    p = cgks.default_params()
+    assert p.gamma == 1.4 and p.levels == 3 and p.passes == 3 and p.seed == 1
+    assert p.nu_pre[0] == 1 and p.nu_post[0] == 0
+    assert abs(p.skew_sin - 0.17364817766693033) < 1e-15
