@@ -200,6 +200,16 @@ cgks_status cgks_prolong(cgks_ctx *ctx, int32_t level, const double *dWc, double
 cgks_status cgks_vcycle(cgks_ctx *ctx, double *W, double *G, double *alpha, int32_t max_cycles, double tol_drop,
                         double *hist, int32_t *n_done);
 
+/*
+ * Kernel timing for profiling: with enable = 1 the library brackets every
+ * launch of the fine face-flux kernel (the BGK interface solution at the Gauss
+ * points) with HIP events on its stream.  A call with enable = 0 synchronises,
+ * writes the accumulated kernel time (host *face_ms) and launch count (host
+ * *face_launches, nullable), and stops timing.  Timing adds two event records
+ * per launch and no synchronisation until it is read.
+ */
+cgks_status cgks_timing(cgks_ctx *ctx, int32_t enable, double *face_ms, int64_t *face_launches);
+
 #ifdef __cplusplus
 }
 #endif

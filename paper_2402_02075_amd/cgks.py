@@ -22,7 +22,7 @@ EXPORTS = ["cgks_default_params", "cgks_create", "cgks_destroy", "cgks_last_erro
            "cgks_set_stream", "cgks_set_mesh", "cgks_set_bc", "cgks_mesh_info", "cgks_geometry", "cgks_local_dt",
            "cgks_reconstruct", "cgks_residual", "cgks_step", "cgks_check", "cgks_residual_norm",
            "cgks_agglomerate_graph", "cgks_agglomerate", "cgks_level_map", "cgks_kfvs_residual", "cgks_restrict",
-           "cgks_prolong", "cgks_vcycle"]
+           "cgks_prolong", "cgks_vcycle", "cgks_timing"]
 
 
 class Params(C.Structure):
@@ -58,7 +58,7 @@ def lib():
             "cgks_agglomerate_graph": [P, I64, P, P, I64, P, P, P, P, P, I32, P, P, P, P, P, P],
             "cgks_agglomerate": [P], "cgks_level_map": [P, I32, P], "cgks_kfvs_residual": [P, I32, P, P],
             "cgks_restrict": [P, I32, P, P, P, P], "cgks_prolong": [P, I32, P, P],
-            "cgks_vcycle": [P, P, P, P, I32, D, P, P],
+            "cgks_vcycle": [P, P, P, P, I32, D, P, P], "cgks_timing": [P, I32, P, P],
         }
         for name, args in sig.items():
             if not hasattr(L, name):
@@ -240,6 +240,15 @@ class Solver:
 
     def prolong(self, level, dWc, Wf):
         self._check(lib().cgks_prolong(self.h, int(level), _ptr(dWc), _ptr(Wf)))
+
+    def timing_start(self):
+        self._check(lib().cgks_timing(self.h, 1, None, None))
+
+    def timing_stop(self):
+        """Accumulated face-kernel milliseconds and launch count since timing_start()."""
+        ms, n = C.c_double(0), C.c_int64(0)
+        self._check(lib().cgks_timing(self.h, 0, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def vcycle(self, W, G, alpha, max_cycles, tol_drop=1e-10):
         hist = np.zeros(max(max_cycles, 1))

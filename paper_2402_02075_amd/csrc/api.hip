@@ -9,6 +9,7 @@ using namespace cgks;
 
 cgks_ctx::~cgks_ctx()
 {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (Level *l : lev) delete l;
     lev.clear();
     if (pinned) (void)hipHostFree(pinned);
@@ -391,6 +392,28 @@ cgks_status cgks_vcycle(cgks_ctx *c, double *W, double *G, double *alpha, int32_
     }
     c->err = "residual drop not reached in max_cycles";
     return CGKS_E_NOCONV;
+    API_END(c)
+}
+
+cgks_status cgks_timing(cgks_ctx *c, int32_t enable, double *face_ms, int64_t *face_launches)
+{
+    API_BEGIN(c)
+    if (enable) {
+        c->timing = true;
+        c->ev_used = 0;
+    } else {
+        CGKS_HIP(hipStreamSynchronize(c->stream));
+        double ms = 0.0;
+        for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+            float t = 0.f;
+            CGKS_HIP(hipEventElapsedTime(&t, c->ev_pool[k], c->ev_pool[k + 1]));
+            ms += t;
+        }
+        if (face_ms) *face_ms = ms;
+        if (face_launches) *face_launches = (int64_t)(c->ev_used / 2);
+        c->timing = false;
+        c->ev_used = 0;
+    }
     API_END(c)
 }
 

@@ -123,6 +123,10 @@ struct cgks_ctx {
     cgks::DBuf<int32_t> bad;
     // multigrid hierarchy; lev[0] is a placeholder for the fine level
     std::vector<cgks::Level *> lev;
+    // optional face-kernel timing (events recorded around each launch)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
     // host pinned scalar for per-cycle reads
     double *pinned = nullptr;
     int32_t *pinned_i = nullptr;

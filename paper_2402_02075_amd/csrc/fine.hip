@@ -201,45 +201,8 @@ __device__ __forceinline__ void eval_poly(const double *__restrict__ coef, int64
         double r[10];
 #pragma unroll
         for (int k = 0; k < 10; ++k) r[k] = coef[(10 * c + k) * N + cell];
-        const double x = dx[0], y = dx[1], z = dx[2];
-        w[c] = r[0] + r[1] * x + r[2] * y + r[3] * z + r[4] * x * x + r[5] * y * y + r[6] * z * z + r[7] * x * y +
-               r[8] * y * z + r[9] * x * z;
-        g[3 * c] = r[1] + 2.0 * r[4] * x + r[7] * y + r[9] * z;
-        g[3 * c + 1] = r[2] + 2.0 * r[5] * y + r[7] * x + r[8] * z;
-        g[3 * c + 2] = r[3] + 2.0 * r[6] * z + r[8] * y + r[9] * x;
+        poly_eval(r, dx, w[c], &g[3 * c]);
     }
-}
-
-template <class T>
-__device__ __forceinline__ void to_local(const double w[5], const double g[15], const double n[3], const double t1[3],
-                                         const double t2[3], T wl[5], T gl[3][5])
-{
-    wl[0] = T(w[0]);
-    wl[1] = T(w[1] * n[0] + w[2] * n[1] + w[3] * n[2]);
-    wl[2] = T(w[1] * t1[0] + w[2] * t1[1] + w[3] * t1[2]);
-    wl[3] = T(w[1] * t2[0] + w[2] * t2[1] + w[3] * t2[2]);
-    wl[4] = T(w[4]);
-    const double *E[3] = {n, t1, t2};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        double D[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) D[c] = g[3 * c] * E[j][0] + g[3 * c + 1] * E[j][1] + g[3 * c + 2] * E[j][2];
-        gl[j][0] = T(D[0]);
-        gl[j][1] = T(D[1] * n[0] + D[2] * n[1] + D[3] * n[2]);
-        gl[j][2] = T(D[1] * t1[0] + D[2] * t1[1] + D[3] * t1[2]);
-        gl[j][3] = T(D[1] * t2[0] + D[2] * t2[1] + D[3] * t2[2]);
-        gl[j][4] = T(D[4]);
-    }
-}
-
-template <class T>
-__device__ __forceinline__ void to_global(const T l[5], const double n[3], const double t1[3], const double t2[3], double o[5])
-{
-    o[0] = double(l[0]);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) o[1 + d] = double(l[1]) * n[d] + double(l[2]) * t1[d] + double(l[3]) * t2[d];
-    o[4] = double(l[4]);
 }
 
 __device__ __forceinline__ double group4_sum(double v)
@@ -351,18 +314,8 @@ template <class T, int MODE> __global__ __launch_bounds__(256) void k_face(FaceA
 #pragma unroll
                     for (int d = 0; d < 3; ++d) acc[10 + 3 * q + d] = wS * Wg[q] * n[d];
             }
-            if (MODE != MODE_RESONLY && R >= 0) {
-                // compression factor from the two Gauss-point states (Sec. 3.3)
-                const double pl = double(mo.pl), pr = double(mo.pr);
-                const double cl = sqrt(A.cfg.gamma * pl / double(wl[0])), cr = sqrt(A.cfg.gamma * pr / double(wr[0]));
-                const double unl = double(wl[1]) / double(wl[0]), unr = double(wr[1]) / double(wr[0]);
-                const double vtl = sqrt(double(wl[2]) * double(wl[2]) + double(wl[3]) * double(wl[3])) / double(wl[0]);
-                const double vtr = sqrt(double(wr[2]) * double(wr[2]) + double(wr[3]) * double(wr[3])) / double(wr[0]);
-                const double dp = fabs(pl - pr);
-                const double dmn = unl / cl - unr / cr, dmt = vtl / cl - vtr / cr;
-                const double Aq = dp / pl + dp / pr + dmn * dmn + dmt * dmt;
-                alpha_k = 1.0 / (1.0 + Aq * Aq);
-            }
+            if (MODE != MODE_RESONLY && R >= 0)
+                alpha_k = cf_factor(wl, wr, double(mo.pl), double(mo.pr), A.cfg.gamma);
         }
     }
 #pragma unroll
@@ -627,6 +580,17 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
     A.out = c->fout.p;
     A.bad = c->bad.p;
     const dim3 grid(blocks_for(4 * c->F, 256)), blk(256);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        while (c->ev_pool.size() < c->ev_used + 2) {
+            hipEvent_t e;
+            CGKS_HIP(hipEventCreate(&e));
+            c->ev_pool.push_back(e);
+        }
+        e0 = c->ev_pool[c->ev_used++];
+        e1 = c->ev_pool[c->ev_used++];
+        CGKS_HIP(hipEventRecord(e0, c->stream));
+    }
     if (fp32) {
         switch (mode) {
         case MODE_RES: hipLaunchKernelGGL((k_face<float, MODE_RES>), grid, blk, 0, c->stream, A); break;
@@ -641,6 +605,7 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
         default: hipLaunchKernelGGL((k_face<double, MODE_S2>), grid, blk, 0, c->stream, A); break;
         }
     }
+    if (c->timing) CGKS_HIP(hipEventRecord(e1, c->stream));
 }
 
 static GatherArgs gargs(cgks_ctx *c)

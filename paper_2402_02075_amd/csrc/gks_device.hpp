@@ -15,23 +15,32 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+// Host-and-device so the same source can be instantiated with a counting scalar
+// on the host to tally the arithmetic per Gauss point.
+#ifndef CGKS_HD
+#define CGKS_HD __host__ __device__ __forceinline__
+#endif
+
 namespace cgks {
 
 template <class T> struct Fp;
 template <> struct Fp<double> {
-    __device__ static double erfc_(double x) { return ::erfc(x); }
-    __device__ static double exp_(double x) { return ::exp(x); }
-    __device__ static double expm1_(double x) { return ::expm1(x); }
-    __device__ static double sqrt_(double x) { return ::sqrt(x); }
-    __device__ static double rsqrt_(double x) { return ::rsqrt(x); }
+    CGKS_HD static double erfc_(double x) { return ::erfc(x); }
+    CGKS_HD static double exp_(double x) { return ::exp(x); }
+    CGKS_HD static double expm1_(double x) { return ::expm1(x); }
+    CGKS_HD static double sqrt_(double x) { return ::sqrt(x); }
 };
 template <> struct Fp<float> {
-    __device__ static float erfc_(float x) { return ::erfcf(x); }
-    __device__ static float exp_(float x) { return ::expf(x); }
-    __device__ static float expm1_(float x) { return ::expm1f(x); }
-    __device__ static float sqrt_(float x) { return ::sqrtf(x); }
-    __device__ static float rsqrt_(float x) { return ::rsqrtf(x); }
+    CGKS_HD static float erfc_(float x) { return ::erfcf(x); }
+    CGKS_HD static float exp_(float x) { return ::expf(x); }
+    CGKS_HD static float expm1_(float x) { return ::expm1f(x); }
+    CGKS_HD static float sqrt_(float x) { return ::sqrtf(x); }
 };
+
+CGKS_HD double abs_(double x) { return fabs(x); }
+CGKS_HD float abs_(float x) { return fabsf(x); }
+CGKS_HD double sign_(double x) { return copysign(1.0, x); }
+CGKS_HD float sign_(float x) { return copysignf(1.0f, x); }
 
 // 1/sqrt(pi)
 #define CGKS_RSQRT_PI 0.56418958354775628694807945156077
@@ -40,7 +49,7 @@ template <class T> struct Side {
     T rho, U, V, W, lam;
 };
 
-template <class T> __device__ __forceinline__ Side<T> side_of(const T w[5], T gam)
+template <class T> CGKS_HD Side<T> side_of(const T w[5], T gam)
 {
     Side<T> s;
     s.rho = w[0];
@@ -58,14 +67,14 @@ template <class T> struct Tab {
     T u[7], v[7], w[7], x[3];
 };
 
-template <class T> __device__ __forceinline__ void recur(T *m, T U, T h)
+template <class T> CGKS_HD void recur(T *m, T U, T h)
 {
     // m[n+2] = U m[n+1] + (n+1) h m[n], h = 1/(2 lambda)
 #pragma unroll
     for (int n = 0; n < 5; ++n) m[n + 2] = U * m[n + 1] + T(n + 1) * h * m[n];
 }
 
-template <class T> __device__ __forceinline__ void tab_vw(Tab<T> &t, const Side<T> &s, T K)
+template <class T> CGKS_HD void tab_vw(Tab<T> &t, const Side<T> &s, T K)
 {
     const T h = T(0.5) / s.lam;
     t.v[0] = T(1);
@@ -79,7 +88,7 @@ template <class T> __device__ __forceinline__ void tab_vw(Tab<T> &t, const Side<
     t.x[2] = K * (K + T(2)) * h * h;
 }
 
-template <class T> __device__ __forceinline__ void tab_u_full(Tab<T> &t, const Side<T> &s)
+template <class T> CGKS_HD void tab_u_full(Tab<T> &t, const Side<T> &s)
 {
     t.u[0] = T(1);
     t.u[1] = s.U;
@@ -87,7 +96,7 @@ template <class T> __device__ __forceinline__ void tab_u_full(Tab<T> &t, const S
 }
 
 // half space: sgn = +1 for u > 0, -1 for u < 0
-template <class T> __device__ __forceinline__ void tab_u_half(Tab<T> &t, const Side<T> &s, T sgn)
+template <class T> CGKS_HD void tab_u_half(Tab<T> &t, const Side<T> &s, T sgn)
 {
     const T sl = Fp<T>::sqrt_(s.lam);
     t.u[0] = T(0.5) * Fp<T>::erfc_(-sgn * sl * s.U);
@@ -96,7 +105,7 @@ template <class T> __device__ __forceinline__ void tab_u_half(Tab<T> &t, const S
 }
 
 // <u^n v^m w^k psi_a>, a = 0..4
-template <int n, int m, int k, class T> __device__ __forceinline__ void mpsi(const Tab<T> &t, T o[5])
+template <int n, int m, int k, class T> CGKS_HD void mpsi(const Tab<T> &t, T o[5])
 {
     const T vw = t.v[m] * t.w[k];
     const T uvw = t.u[n] * vw;
@@ -108,7 +117,7 @@ template <int n, int m, int k, class T> __device__ __forceinline__ void mpsi(con
 }
 
 // <xi^2 u^n v^m w^k psi_a>
-template <int n, int m, int k, class T> __device__ __forceinline__ void mpsi_x2(const Tab<T> &t, T o[5])
+template <int n, int m, int k, class T> CGKS_HD void mpsi_x2(const Tab<T> &t, T o[5])
 {
     const T vw = t.v[m] * t.w[k];
     const T uvw = t.u[n] * vw;
@@ -120,7 +129,7 @@ template <int n, int m, int k, class T> __device__ __forceinline__ void mpsi_x2(
 }
 
 // acc += s * <a u^n v^m w^k psi>, a = a0 + a1 u + a2 v + a3 w + a4 (u^2+v^2+w^2+xi^2)/2
-template <int n, int m, int k, class T> __device__ __forceinline__ void macc(const Tab<T> &t, const T a[5], T s, T acc[5])
+template <int n, int m, int k, class T> CGKS_HD void macc(const Tab<T> &t, const T a[5], T s, T acc[5])
 {
     T q[5], r[5];
     mpsi<n, m, k>(t, q);
@@ -150,7 +159,7 @@ template <int n, int m, int k, class T> __device__ __forceinline__ void macc(con
 }
 
 // acc += s * <(u a_x + v a_y + w a_z) u^n psi>   (n = 0: value moment, n = 1: flux moment)
-template <int n, class T> __device__ __forceinline__ void macc_transport(const Tab<T> &t, const T a[3][5], T s, T acc[5])
+template <int n, class T> CGKS_HD void macc_transport(const Tab<T> &t, const T a[3][5], T s, T acc[5])
 {
     macc<n + 1, 0, 0>(t, a[0], s, acc);
     macc<n, 1, 0>(t, a[1], s, acc);
@@ -158,7 +167,7 @@ template <int n, class T> __device__ __forceinline__ void macc_transport(const T
 }
 
 // Solve M a = b for a micro-slope, M = <psi psi^T> of the normalised Maxwellian (closed form).
-template <class T> __device__ __forceinline__ void slope_solve(const Side<T> &s, T K, const T b[5], T a[5])
+template <class T> CGKS_HD void slope_solve(const Side<T> &s, T K, const T b[5], T a[5])
 {
     const T q2 = s.U * s.U + s.V * s.V + s.W * s.W;
     const T e = q2 + (K + T(3)) / (T(2) * s.lam);
@@ -175,7 +184,7 @@ template <class T> __device__ __forceinline__ void slope_solve(const Side<T> &s,
 
 // Space slopes a_j from local-frame gradients g[j][c] of conservative variables, and the time slope A.
 template <class T>
-__device__ __forceinline__ void slopes(const Side<T> &s, const Tab<T> &full, T K, const T g[3][5], T a[3][5], T A[5])
+CGKS_HD void slopes(const Side<T> &s, const Tab<T> &full, T K, const T g[3][5], T a[3][5], T A[5])
 {
     const T ir = T(1) / s.rho;
 #pragma unroll
@@ -206,7 +215,7 @@ template <class T> struct GksMoments {
 };
 
 template <class T>
-__device__ __forceinline__ bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T gr[3][5], T gam, T K,
+CGKS_HD bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T gr[3][5], T gam, T K,
                                             GksMoments<T> &o)
 {
     const Side<T> sl = side_of(wl, gam), sr = side_of(wr, gam);
@@ -286,7 +295,7 @@ template <class T> struct TimeCoef {
     T c1, c2, c3, e, k1, k2;
 };
 
-template <class T> __device__ __forceinline__ TimeCoef<T> coef_integrated(T Tt, T tau, T taun)
+template <class T> CGKS_HD TimeCoef<T> coef_integrated(T Tt, T tau, T taun)
 {
     const T x = Tt / taun;
     const T E = Fp<T>::exp_(-x);
@@ -303,7 +312,7 @@ template <class T> __device__ __forceinline__ TimeCoef<T> coef_integrated(T Tt, 
     return c;
 }
 
-template <class T> __device__ __forceinline__ TimeCoef<T> coef_at(T t, T tau, T taun)
+template <class T> CGKS_HD TimeCoef<T> coef_at(T t, T tau, T taun)
 {
     const T e = Fp<T>::exp_(-t / taun);
     TimeCoef<T> c;
@@ -316,7 +325,7 @@ template <class T> __device__ __forceinline__ TimeCoef<T> coef_at(T t, T tau, T 
     return c;
 }
 
-template <class T> __device__ __forceinline__ void combine(const TimeCoef<T> &c, const T Mc[3][5], const T Mk[3][5], T out[5])
+template <class T> CGKS_HD void combine(const TimeCoef<T> &c, const T Mc[3][5], const T Mk[3][5], T out[5])
 {
 #pragma unroll
     for (int i = 0; i < 5; ++i)
@@ -324,7 +333,7 @@ template <class T> __device__ __forceinline__ void combine(const TimeCoef<T> &c,
 }
 
 // Heat flux (relative to the g^c velocity) of time-integrated flux F and conserved integral Q.
-template <class T> __device__ __forceinline__ T heat_flux(const T F[5], const T Q[5], const T U[3])
+template <class T> CGKS_HD T heat_flux(const T F[5], const T Q[5], const T U[3])
 {
     const T u2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
     return F[4] - (U[0] * F[1] + U[1] * F[2] + U[2] * F[3]) + T(0.5) * u2 * F[0] - U[0] * Q[4] +
@@ -332,9 +341,9 @@ template <class T> __device__ __forceinline__ T heat_flux(const T F[5], const T 
 }
 
 // Collision times: tau (outside the exponentials) and tau_n.
-template <class T> __device__ __forceinline__ void collision_times(const GksMoments<T> &m, T dt, const GksCfg &cfg, T &tau, T &taun)
+template <class T> CGKS_HD void collision_times(const GksMoments<T> &m, T dt, const GksCfg &cfg, T &tau, T &taun)
 {
-    const T jump = fabs((m.pl - m.pr) / (m.pl + m.pr));
+    const T jump = abs_((m.pl - m.pr) / (m.pl + m.pr));
     if (cfg.viscous) {
         tau = T(cfg.mu) / m.pc;
         taun = tau + T(cfg.c_tau) * jump * dt;
@@ -346,7 +355,7 @@ template <class T> __device__ __forceinline__ void collision_times(const GksMome
 
 // Time-integrated flux over [0, Tt] with the Prandtl correction.
 template <class T>
-__device__ __forceinline__ void flux_integrated(const GksMoments<T> &m, T Tt, T tau, T taun, const GksCfg &cfg, T F[5])
+CGKS_HD void flux_integrated(const GksMoments<T> &m, T Tt, T tau, T taun, const GksCfg &cfg, T F[5])
 {
     const TimeCoef<T> c = coef_integrated(Tt, tau, taun);
     combine(c, m.Mc, m.Mk, F);
@@ -357,7 +366,7 @@ __device__ __forceinline__ void flux_integrated(const GksMoments<T> &m, T Tt, T 
     }
 }
 
-template <class T> __device__ __forceinline__ void value_at(const GksMoments<T> &m, T t, T tau, T taun, T Wt[5])
+template <class T> CGKS_HD void value_at(const GksMoments<T> &m, T t, T tau, T taun, T Wt[5])
 {
     const TimeCoef<T> c = coef_at(t, tau, taun);
     combine(c, m.Vc, m.Vk, Wt);
@@ -365,9 +374,9 @@ template <class T> __device__ __forceinline__ void value_at(const GksMoments<T> 
 
 // ---------------------------------------------------------------- frames
 // Orthonormal basis completing a unit normal (Duff et al. 2017, branchless).
-template <class T> __device__ __forceinline__ void onb(const T n[3], T t1[3], T t2[3])
+template <class T> CGKS_HD void onb(const T n[3], T t1[3], T t2[3])
 {
-    const T s = copysign(T(1), n[2]);
+    const T s = sign_(n[2]);
     const T a = T(-1) / (s + n[2]);
     const T b = n[0] * n[1] * a;
     t1[0] = T(1) + s * n[0] * n[0] * a;
@@ -376,6 +385,66 @@ template <class T> __device__ __forceinline__ void onb(const T n[3], T t1[3], T 
     t2[0] = b;
     t2[1] = s + n[1] * n[1] * a;
     t2[2] = -n[1];
+}
+
+// ---------------------------------------------------------------- per-point helpers
+// value and gradient of R(x) = r0 + r.dx + quadratic terms (order 1, x, y, z, xx, yy, zz, xy, yz, xz)
+template <class S> CGKS_HD void poly_eval(const S r[10], const S dx[3], S &w, S g[3])
+{
+    const S x = dx[0], y = dx[1], z = dx[2];
+    w = r[0] + r[1] * x + r[2] * y + r[3] * z + r[4] * x * x + r[5] * y * y + r[6] * z * z + r[7] * x * y + r[8] * y * z +
+        r[9] * x * z;
+    g[0] = r[1] + S(2) * r[4] * x + r[7] * y + r[9] * z;
+    g[1] = r[2] + S(2) * r[5] * y + r[7] * x + r[8] * z;
+    g[2] = r[3] + S(2) * r[6] * z + r[8] * y + r[9] * x;
+}
+
+// conservative state and gradients G[3c+d] into the frame (n, t1, t2): wl[c'], gl[j][c']
+template <class S, class T>
+CGKS_HD void to_local(const S w[5], const S g[15], const S n[3], const S t1[3], const S t2[3], T wl[5], T gl[3][5])
+{
+    wl[0] = T(w[0]);
+    wl[1] = T(w[1] * n[0] + w[2] * n[1] + w[3] * n[2]);
+    wl[2] = T(w[1] * t1[0] + w[2] * t1[1] + w[3] * t1[2]);
+    wl[3] = T(w[1] * t2[0] + w[2] * t2[1] + w[3] * t2[2]);
+    wl[4] = T(w[4]);
+    const S *E[3] = {n, t1, t2};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        S D[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) D[c] = g[3 * c] * E[j][0] + g[3 * c + 1] * E[j][1] + g[3 * c + 2] * E[j][2];
+        gl[j][0] = T(D[0]);
+        gl[j][1] = T(D[1] * n[0] + D[2] * n[1] + D[3] * n[2]);
+        gl[j][2] = T(D[1] * t1[0] + D[2] * t1[1] + D[3] * t1[2]);
+        gl[j][3] = T(D[1] * t2[0] + D[2] * t2[1] + D[3] * t2[2]);
+        gl[j][4] = T(D[4]);
+    }
+}
+
+template <class T, class S>
+CGKS_HD void to_global(const T l[5], const S n[3], const S t1[3], const S t2[3], S o[5])
+{
+    o[0] = S(l[0]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) o[1 + d] = S(l[1]) * n[d] + S(l[2]) * t1[d] + S(l[3]) * t2[d];
+    o[4] = S(l[4]);
+}
+
+// gradient compression factor of one Gauss point from the two local-frame states (Sec. 3.3):
+// 1/(1+A^2), A = |dp|/p_l + |dp|/p_r + (Ma_n,l - Ma_n,r)^2 + (Ma_t,l - Ma_t,r)^2
+template <class T, class S>
+CGKS_HD S cf_factor(const T wl[5], const T wr[5], S pl, S pr, S gam)
+{
+    const S rl = S(wl[0]), rr = S(wr[0]);
+    const S cl = Fp<S>::sqrt_(gam * pl / rl), cr = Fp<S>::sqrt_(gam * pr / rr);
+    const S unl = S(wl[1]) / rl, unr = S(wr[1]) / rr;
+    const S vtl = Fp<S>::sqrt_(S(wl[2]) * S(wl[2]) + S(wl[3]) * S(wl[3])) / rl;
+    const S vtr = Fp<S>::sqrt_(S(wr[2]) * S(wr[2]) + S(wr[3]) * S(wr[3])) / rr;
+    const S dp = abs_(pl - pr);
+    const S dmn = unl / cl - unr / cr, dmt = vtl / cl - vtr / cr;
+    const S A = dp / pl + dp / pr + dmn * dmn + dmt * dmt;
+    return S(1) / (S(1) + A * A);
 }
 
 }  // namespace cgks
