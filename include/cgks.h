@@ -202,8 +202,9 @@ cgks_status cgks_vcycle(cgks_ctx *ctx, double *W, double *G, double *alpha, int3
 
 /*
  * Kernel timing for profiling: with enable = 1 the library brackets every
- * launch of the fine face-flux kernel (the BGK interface solution at the Gauss
- * points) with HIP events on its stream.  A call with enable = 0 synchronises,
+ * launch of the fine face-flux kernel in its steady mode with gradient update
+ * (the BGK interface solution at the Gauss points, flux and interface values)
+ * with HIP events on its stream.  A call with enable = 0 synchronises,
  * writes the accumulated kernel time (host *face_ms) and launch count (host
  * *face_launches, nullable), and stops timing.  Timing adds two event records
  * per launch and no synchronisation until it is read.

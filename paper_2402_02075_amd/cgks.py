@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcgks.so")
+LIB_PATH = os.environ.get("CGKS_LIBRARY") or os.path.join(HERE, "libcgks.so")
 
 OK, E_ARG, E_MESH, E_DEVICE, E_NONFINITE, E_PHYS, E_NOCONV, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 BC_SLIP, BC_NOSLIP_ADIABATIC, BC_FARFIELD = 1, 2, 3

@@ -254,7 +254,8 @@ template <class T, int MODE> __global__ __launch_bounds__(256) void k_face(FaceA
         to_local(WL, GL, n, t1, t2, wl, gl);
         to_local(WR, GR, n, t1, t2, wr, gr);
         GksMoments<T> mo;
-        if (!gks_moments(wl, gl, wr, gr, T(A.cfg.gamma), T(A.cfg.K), mo)) {
+        const bool need_val = MODE != MODE_RESONLY || (A.cfg.viscous && A.cfg.prandtl != 1.0);
+        if (!gks_moments<T>(wl, gl, wr, gr, T(A.cfg.gamma), T(A.cfg.K), mo, need_val)) {
             atomicMin(A.bad, L);
         } else {
             T tau, taun;
@@ -581,7 +582,8 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
     A.bad = c->bad.p;
     const dim3 grid(blocks_for(4 * c->F, 256)), blk(256);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
+    const bool timed = c->timing && mode == MODE_RES;
+    if (timed) {
         while (c->ev_pool.size() < c->ev_used + 2) {
             hipEvent_t e;
             CGKS_HIP(hipEventCreate(&e));
@@ -605,7 +607,7 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
         default: hipLaunchKernelGGL((k_face<double, MODE_S2>), grid, blk, 0, c->stream, A); break;
         }
     }
-    if (c->timing) CGKS_HIP(hipEventRecord(e1, c->stream));
+    if (timed) CGKS_HIP(hipEventRecord(e1, c->stream));
 }
 
 static GatherArgs gargs(cgks_ctx *c)

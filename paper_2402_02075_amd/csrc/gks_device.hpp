@@ -116,56 +116,6 @@ template <int n, int m, int k, class T> CGKS_HD void mpsi(const Tab<T> &t, T o[5
     o[4] = T(0.5) * (t.u[n + 2] * vw + t.u[n] * (t.v[m + 2] * t.w[k] + t.v[m] * t.w[k + 2]) + uvw * t.x[1]);
 }
 
-// <xi^2 u^n v^m w^k psi_a>
-template <int n, int m, int k, class T> CGKS_HD void mpsi_x2(const Tab<T> &t, T o[5])
-{
-    const T vw = t.v[m] * t.w[k];
-    const T uvw = t.u[n] * vw;
-    o[0] = t.x[1] * uvw;
-    o[1] = t.x[1] * t.u[n + 1] * vw;
-    o[2] = t.x[1] * t.u[n] * t.v[m + 1] * t.w[k];
-    o[3] = t.x[1] * t.u[n] * t.v[m] * t.w[k + 1];
-    o[4] = T(0.5) * (t.x[1] * (t.u[n + 2] * vw + t.u[n] * (t.v[m + 2] * t.w[k] + t.v[m] * t.w[k + 2])) + uvw * t.x[2]);
-}
-
-// acc += s * <a u^n v^m w^k psi>, a = a0 + a1 u + a2 v + a3 w + a4 (u^2+v^2+w^2+xi^2)/2
-template <int n, int m, int k, class T> CGKS_HD void macc(const Tab<T> &t, const T a[5], T s, T acc[5])
-{
-    T q[5], r[5];
-    mpsi<n, m, k>(t, q);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) r[i] = a[0] * q[i];
-    mpsi<n + 1, m, k>(t, q);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) r[i] += a[1] * q[i];
-    mpsi<n, m + 1, k>(t, q);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) r[i] += a[2] * q[i];
-    mpsi<n, m, k + 1>(t, q);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) r[i] += a[3] * q[i];
-    T e[5];
-    mpsi<n + 2, m, k>(t, e);
-    mpsi<n, m + 2, k>(t, q);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) e[i] += q[i];
-    mpsi<n, m, k + 2>(t, q);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) e[i] += q[i];
-    mpsi_x2<n, m, k>(t, q);
-    const T h4 = T(0.5) * a[4];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) acc[i] += s * (r[i] + h4 * (e[i] + q[i]));
-}
-
-// acc += s * <(u a_x + v a_y + w a_z) u^n psi>   (n = 0: value moment, n = 1: flux moment)
-template <int n, class T> CGKS_HD void macc_transport(const Tab<T> &t, const T a[3][5], T s, T acc[5])
-{
-    macc<n + 1, 0, 0>(t, a[0], s, acc);
-    macc<n, 1, 0>(t, a[1], s, acc);
-    macc<n, 0, 1>(t, a[2], s, acc);
-}
-
 // Solve M a = b for a micro-slope, M = <psi psi^T> of the normalised Maxwellian (closed form).
 template <class T> CGKS_HD void slope_solve(const Side<T> &s, T K, const T b[5], T a[5])
 {
@@ -182,9 +132,60 @@ template <class T> CGKS_HD void slope_solve(const Side<T> &s, T K, const T b[5],
     a[0] = b[0] - s.U * a[1] - s.V * a[2] - s.W * a[3] - T(0.5) * a[4] * e;
 }
 
-// Space slopes a_j from local-frame gradients g[j][c] of conservative variables, and the time slope A.
+// ---------------------------------------------------------------- moment matrices
+// Symmetric 5x5 matrix m_ab = <w psi_a psi_b> for the weight w = u^A v^B w^C, packed as
+// (00 01 02 03 04 11 12 13 14 22 23 24 33 34 44).  psi_4 = (u^2 + v^2 + w^2 + xi^2)/2.
+template <int A, int B, int C, class T> CGKS_HD void mmat(const Tab<T> &t, T m[15])
+{
+#define CGKS_P(i, j, k) (t.u[i] * t.v[j] * t.w[k])
+    const T x1 = t.x[1];
+    const T p000 = CGKS_P(A, B, C);
+    const T p200 = CGKS_P(A + 2, B, C), p020 = CGKS_P(A, B + 2, C), p002 = CGKS_P(A, B, C + 2);
+    const T p100 = CGKS_P(A + 1, B, C), p010 = CGKS_P(A, B + 1, C), p001 = CGKS_P(A, B, C + 1);
+    m[0] = p000;
+    m[1] = p100;
+    m[2] = p010;
+    m[3] = p001;
+    m[4] = T(0.5) * (p200 + p020 + p002 + p000 * x1);
+    m[5] = p200;
+    m[6] = CGKS_P(A + 1, B + 1, C);
+    m[7] = CGKS_P(A + 1, B, C + 1);
+    m[8] = T(0.5) * (CGKS_P(A + 3, B, C) + CGKS_P(A + 1, B + 2, C) + CGKS_P(A + 1, B, C + 2) + p100 * x1);
+    m[9] = p020;
+    m[10] = CGKS_P(A, B + 1, C + 1);
+    m[11] = T(0.5) * (CGKS_P(A + 2, B + 1, C) + CGKS_P(A, B + 3, C) + CGKS_P(A, B + 1, C + 2) + p010 * x1);
+    m[12] = p002;
+    m[13] = T(0.5) * (CGKS_P(A + 2, B, C + 1) + CGKS_P(A, B + 2, C + 1) + CGKS_P(A, B, C + 3) + p001 * x1);
+    m[14] = T(0.25) * (CGKS_P(A + 4, B, C) + CGKS_P(A, B + 4, C) + CGKS_P(A, B, C + 4) +
+                       T(2) * (CGKS_P(A + 2, B + 2, C) + CGKS_P(A + 2, B, C + 2) + CGKS_P(A, B + 2, C + 2)) +
+                       T(2) * (p200 + p020 + p002) * x1 + p000 * t.x[2]);
+#undef CGKS_P
+}
+
+// y += s * m x for a packed symmetric matrix
+template <class T> CGKS_HD void msym_acc(const T m[15], const T x[5], T s, T y[5])
+{
+    y[0] += s * (m[0] * x[0] + m[1] * x[1] + m[2] * x[2] + m[3] * x[3] + m[4] * x[4]);
+    y[1] += s * (m[1] * x[0] + m[5] * x[1] + m[6] * x[2] + m[7] * x[3] + m[8] * x[4]);
+    y[2] += s * (m[2] * x[0] + m[6] * x[1] + m[9] * x[2] + m[10] * x[3] + m[11] * x[4]);
+    y[3] += s * (m[3] * x[0] + m[7] * x[1] + m[10] * x[2] + m[12] * x[3] + m[13] * x[4]);
+    y[4] += s * (m[4] * x[0] + m[8] * x[1] + m[11] * x[2] + m[13] * x[3] + m[14] * x[4]);
+}
+
+// first column of m (the moments <w psi_a>), scaled
+template <class T> CGKS_HD void mcol0_acc(const T m[15], T s, T y[5])
+{
+    y[0] += s * m[0];
+    y[1] += s * m[1];
+    y[2] += s * m[2];
+    y[3] += s * m[3];
+    y[4] += s * m[4];
+}
+
+// Space slopes a_j from local-frame gradients g[j][c], and the full-space transport moment
+// tr = sum_j <u_j a_j psi> (so that the time slope solves M A = -tr).
 template <class T>
-CGKS_HD void slopes(const Side<T> &s, const Tab<T> &full, T K, const T g[3][5], T a[3][5], T A[5])
+CGKS_HD void slopes(const Side<T> &s, const Tab<T> &full, T K, const T g[3][5], T a[3][5], T A[5], T tr[5])
 {
     const T ir = T(1) / s.rho;
 #pragma unroll
@@ -194,8 +195,18 @@ CGKS_HD void slopes(const Side<T> &s, const Tab<T> &full, T K, const T g[3][5], 
         for (int c = 0; c < 5; ++c) b[c] = g[j][c] * ir;
         slope_solve(s, K, b, a[j]);
     }
-    T b[5] = {T(0), T(0), T(0), T(0), T(0)};
-    macc_transport<0>(full, a, T(-1), b);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) tr[c] = T(0);
+    T m[15];
+    mmat<1, 0, 0>(full, m);
+    msym_acc(m, a[0], T(1), tr);
+    mmat<0, 1, 0>(full, m);
+    msym_acc(m, a[1], T(1), tr);
+    mmat<0, 0, 1>(full, m);
+    msym_acc(m, a[2], T(1), tr);
+    T b[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) b[c] = -tr[c];
     slope_solve(s, K, b, A);
 }
 
@@ -214,9 +225,11 @@ template <class T> struct GksMoments {
     T pl, pr, pc;
 };
 
+// VAL = false skips the moments that only the interface value W(t) and the Prandtl
+// correction need (a uniform branch).
 template <class T>
 CGKS_HD bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T gr[3][5], T gam, T K,
-                                            GksMoments<T> &o)
+                         GksMoments<T> &o, bool VAL = true)
 {
     const Side<T> sl = side_of(wl, gam), sr = side_of(wr, gam);
     if (!(sl.rho > T(0) && sr.rho > T(0) && sl.lam > T(0) && sr.lam > T(0))) return false;
@@ -230,7 +243,7 @@ CGKS_HD bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int c = 0; c < 5; ++c) o.Mk[i][c] = o.Vk[i][c] = T(0);
-    // two sides, processed one after the other to bound register live ranges
+    // two sides, one after the other to bound register live ranges
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         const Side<T> &s = side == 0 ? sl : sr;
@@ -238,26 +251,33 @@ CGKS_HD bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T
         Tab<T> t;
         tab_vw(t, s, K);
         tab_u_full(t, s);
-        T a[3][5], A[5];
-        slopes(s, t, K, g, a, A);
+        T a[3][5], A[5], tr[5];
+        slopes(s, t, K, g, a, A, tr);
         tab_u_half(t, s, side == 0 ? T(1) : T(-1));
         const T rho = s.rho;
-        T q[5];
-        mpsi<0, 0, 0>(t, q);
+        T m[15];
+        mmat<0, 0, 0>(t, m);  // <psi psi>_half
+        mcol0_acc(m, rho, Wc);
+        mcol0_acc(m, rho, o.Vk[0]);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            Wc[c] += rho * q[c];
-            o.Vk[0][c] += rho * q[c];
+        for (int j = 0; j < 3; ++j) msym_acc(m, a[j], rho, dWc[j]);
+        if (VAL) msym_acc(m, A, rho, o.Vk[2]);
+        mmat<1, 0, 0>(t, m);  // <u psi psi>_half
+        mcol0_acc(m, rho, o.Mk[0]);
+        msym_acc(m, A, rho, o.Mk[2]);
+        if (VAL) {
+            msym_acc(m, a[0], rho, o.Vk[1]);
+            mmat<0, 1, 0>(t, m);
+            msym_acc(m, a[1], rho, o.Vk[1]);
+            mmat<0, 0, 1>(t, m);
+            msym_acc(m, a[2], rho, o.Vk[1]);
         }
-        mpsi<1, 0, 0>(t, q);
-#pragma unroll
-        for (int c = 0; c < 5; ++c) o.Mk[0][c] += rho * q[c];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) macc<0, 0, 0>(t, a[j], rho, dWc[j]);
-        macc_transport<1>(t, a, rho, o.Mk[1]);
-        macc_transport<0>(t, a, rho, o.Vk[1]);
-        macc<1, 0, 0>(t, A, rho, o.Mk[2]);
-        macc<0, 0, 0>(t, A, rho, o.Vk[2]);
+        mmat<2, 0, 0>(t, m);
+        msym_acc(m, a[0], rho, o.Mk[1]);
+        mmat<1, 1, 0>(t, m);
+        msym_acc(m, a[1], rho, o.Mk[1]);
+        mmat<1, 0, 1>(t, m);
+        msym_acc(m, a[2], rho, o.Mk[1]);
     }
     const Side<T> sc = side_of(Wc, gam);
     if (!(sc.rho > T(0) && sc.lam > T(0))) return false;
@@ -265,21 +285,26 @@ CGKS_HD bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T
         Tab<T> t;
         tab_vw(t, sc, K);
         tab_u_full(t, sc);
-        T a[3][5], A[5];
-        slopes(sc, t, K, dWc, a, A);
+        T a[3][5], A[5], tr[5];
+        slopes(sc, t, K, dWc, a, A, tr);
         const T rho = sc.rho;
-        T q[5];
-        mpsi<1, 0, 0>(t, q);
+        T m[15];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            o.Mc[0][c] = rho * q[c];
-            o.Mc[1][c] = o.Mc[2][c] = o.Vc[1][c] = o.Vc[2][c] = T(0);
             o.Vc[0][c] = Wc[c];
+            o.Vc[1][c] = rho * tr[c];   // rho_c <(a_c.u) psi>
+            o.Vc[2][c] = -rho * tr[c];  // compatibility: <A_c psi> = -<(a_c.u) psi>
+            o.Mc[0][c] = o.Mc[1][c] = o.Mc[2][c] = T(0);
         }
-        macc_transport<1>(t, a, rho, o.Mc[1]);
-        macc<1, 0, 0>(t, A, rho, o.Mc[2]);
-        macc_transport<0>(t, a, rho, o.Vc[1]);
-        macc<0, 0, 0>(t, A, rho, o.Vc[2]);
+        mmat<1, 0, 0>(t, m);
+        mcol0_acc(m, rho, o.Mc[0]);
+        msym_acc(m, A, rho, o.Mc[2]);
+        mmat<2, 0, 0>(t, m);
+        msym_acc(m, a[0], rho, o.Mc[1]);
+        mmat<1, 1, 0>(t, m);
+        msym_acc(m, a[1], rho, o.Mc[1]);
+        mmat<1, 0, 1>(t, m);
+        msym_acc(m, a[2], rho, o.Mc[1]);
     }
     o.Uc[0] = sc.U;
     o.Uc[1] = sc.V;
