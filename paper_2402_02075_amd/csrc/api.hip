@@ -221,7 +221,7 @@ cgks_status cgks_reconstruct(cgks_ctx *c, const double *W, const double *G, cons
     API_BEGIN(c)
     need_mesh(c);
     if (!W || !G || !coef) throw Error{CGKS_E_ARG, "null pointer"};
-    launch_recon(c, W, G, alpha, coef);
+    launch_recon(c, W, G, alpha, coef, false);
     CGKS_HIP(hipGetLastError());
     API_END(c)
 }

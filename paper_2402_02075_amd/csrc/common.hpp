@@ -111,9 +111,9 @@ struct cgks_ctx {
     // reconstruction structures
     cgks::DBuf<int32_t> slot_nb;   // [6][N] neighbour cell, or -(face+1) for a boundary face, or INT32_MIN unused
     cgks::DBuf<double> slot_av;    // [6*3][N] outward area vector / |Omega|
-    cgks::DBuf<int64_t> op_off;    // [N] offset into op, -1: Green-Gauss only
+    cgks::DBuf<int64_t> op_off;    // [N] first entry of the cell's operator (stride 64), -1: Green-Gauss only
     cgks::DBuf<uint8_t> n_int;     // [N] interior neighbours
-    cgks::DBuf<double> op;         // per cell: 9 x 4nb KKT operator, then 3 x nb LS operator
+    cgks::DBuf<double> op;         // per interior neighbour 39 entries (9 x 4 KKT columns, 3 LS), 64-cell interleaved
     // boundary conditions
     cgks::BcTable bc_host{};
     cgks::DBuf<cgks::BcTable> bc;
@@ -141,7 +141,8 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_cells
                 const int64_t *cptr, const int64_t *cnode, int64_t n_bf, const int64_t *bptr, const int64_t *bnode,
                 const int32_t *btag, const int64_t *canon);
 void launch_local_dt(cgks_ctx *c, const double *W, double *dt);
-void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef);
+void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef,
+                  bool cell_major = true);  // cell-major: coef[50 i + 10 c + k], else coef[(10 c + k) N + i]
 enum FaceMode { MODE_RES = 0, MODE_RESONLY = 1, MODE_S1 = 2, MODE_S2 = 3 };
 void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cell, double dt_global, bool fp32);
 void launch_gather_res(cgks_ctx *c, double *R, double *Gn, double *an, int mode);

@@ -48,118 +48,98 @@ struct ReconArgs {
     const double *W, *G, *alpha, *vol, *mom2, *slot_av, *op;
     const int32_t *slot_nb, *ftag;
     const int64_t *op_off;
-    const uint8_t *n_int;
     const BcTable *bc;
     double *coef;
 };
 
-__global__ __launch_bounds__(128) void k_recon(ReconArgs A)
+// Operator entries of one interior neighbour m of a cell, 39 per neighbour: 9 multiply the
+// average difference, 27 the neighbour gradient (row k, direction d at 9 + 3k + d), 3 the
+// linear least-squares gradient (36 + d).  Cells are interleaved in groups of 64, so entry
+// e of cell i sits at op_off[i] + 64 e and a wave reads each entry with one coalesced load.
+constexpr int OP_PER_NB = 39;
+constexpr int OP_GROUP = 64;
+
+// One thread per (cell, conservative component): the reconstruction acts on each
+// component separately, so a block holds 64 consecutive cells and five waves, one per
+// component, all reading the same operator entries.
+template <int C, bool CELL_MAJOR> __device__ __forceinline__ void recon_component(const ReconArgs &A, int64_t i)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.N) return;
     const int64_t N = A.N;
-    double Q0[5];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) Q0[c] = A.W[c * N + i];
+    const double q0 = A.W[C * N + i];
     const int64_t off = A.op_off[i];
-    const int nb = A.n_int[i];
-    const int nc = 4 * nb;
-    double gg[5][3], gl[5][3], a[5][9];
+    double gg[3] = {0.0, 0.0, 0.0}, gl[3] = {0.0, 0.0, 0.0}, a[9];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) gg[c][d] = gl[c][d] = 0.0;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) a[c][k] = 0.0;
-    }
+    for (int k = 0; k < 9; ++k) a[k] = 0.0;
     int m = 0;
     for (int s = 0; s < 6; ++s) {
         const int nbv = A.slot_nb[s * N + i];
         if (nbv == INT32_MIN) break;
         const double av[3] = {A.slot_av[(3 * s) * N + i], A.slot_av[(3 * s + 1) * N + i], A.slot_av[(3 * s + 2) * N + i]};
-        double Qm[5];
+        double qm;
         if (nbv >= 0) {
-#pragma unroll
-            for (int c = 0; c < 5; ++c) Qm[c] = A.W[c * N + nbv];
+            qm = A.W[C * N + nbv];
             if (off >= 0) {
-                const double *op = A.op + off;
-                const double *ls = op + 9 * nc;
-                double Gm[15];
+                const double *op = A.op + off + (int64_t)OP_GROUP * OP_PER_NB * m;
+                const double e = qm - q0;
+                const double gx = A.G[(3 * C) * N + nbv], gy = A.G[(3 * C + 1) * N + nbv],
+                             gz = A.G[(3 * C + 2) * N + nbv];
 #pragma unroll
-                for (int q = 0; q < 15; ++q) Gm[q] = A.G[q * N + nbv];
-                double om[9], od[9][3];
+                for (int k = 0; k < 9; ++k)
+                    a[k] += op[OP_GROUP * k] * e + op[OP_GROUP * (9 + 3 * k)] * gx +
+                            op[OP_GROUP * (10 + 3 * k)] * gy + op[OP_GROUP * (11 + 3 * k)] * gz;
 #pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    om[k] = op[k * nc + m];
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) od[k][d] = op[k * nc + nb + 3 * m + d];
-                }
-                const double l0 = ls[m], l1 = ls[nb + m], l2 = ls[2 * nb + m];
-#pragma unroll
-                for (int c = 0; c < 5; ++c) {
-                    const double e = Qm[c] - Q0[c];
-                    gl[c][0] += l0 * e;
-                    gl[c][1] += l1 * e;
-                    gl[c][2] += l2 * e;
-#pragma unroll
-                    for (int k = 0; k < 9; ++k)
-                        a[c][k] += om[k] * e + od[k][0] * Gm[3 * c] + od[k][1] * Gm[3 * c + 1] + od[k][2] * Gm[3 * c + 2];
-                }
+                for (int d = 0; d < 3; ++d) gl[d] += op[OP_GROUP * (36 + d)] * e;
             }
             ++m;
         } else {
+            // boundary face: Green-Gauss uses the boundary-condition ghost of the own average
             const int f = -nbv - 1;
             const double na = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
             const double n[3] = {av[0] / na, av[1] / na, av[2] / na};
-            ghost_state(*A.bc, A.ftag[f], n, Q0, A.gam, Qm);
+            double Q0[5], Qg[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) Q0[c] = A.W[c * N + i];
+            ghost_state(*A.bc, A.ftag[f], n, Q0, A.gam, Qg);
+            qm = Qg[C];
         }
 #pragma unroll
-        for (int c = 0; c < 5; ++c)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) gg[c][d] += 0.5 * (Qm[c] + Q0[c]) * av[d];
+        for (int d = 0; d < 3; ++d) gg[d] += 0.5 * (qm + q0) * av[d];
     }
     const double al = A.alpha ? A.alpha[i] : 1.0;
-    double *out = A.coef;
+    double r[10];
+    const double p1x = al * gg[0], p1y = al * gg[1], p1z = al * gg[2];
     if (off < 0) {
+        r[0] = q0;
+        r[1] = p1x;
+        r[2] = p1y;
+        r[3] = p1z;
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            out[(10 * c) * N + i] = Q0[c];
+        for (int k = 4; k < 10; ++k) r[k] = 0.0;
+    } else {
+        const double V = A.vol[i];
+        const double V13 = cbrt(V), V23 = V13 * V13;
+        double I[6];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) out[(10 * c + 1 + d) * N + i] = al * gg[c][d];
-#pragma unroll
-            for (int k = 4; k < 10; ++k) out[(10 * c + k) * N + i] = 0.0;
-        }
-        return;
-    }
-    const double V = A.vol[i];
-    const double V13 = cbrt(V), V23 = V13 * V13;
-    double I[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) I[q] = A.mom2[q * N + i];
-    const double g2 = A.g2, g1 = 1.0 - A.g2;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        const double *ac = a[c];
-        const double p1x = al * gg[c][0], p1y = al * gg[c][1], p1z = al * gg[c][2];
+        for (int q = 0; q < 6; ++q) I[q] = A.mom2[q * N + i];
+        const double g2 = A.g2, g1 = 1.0 - A.g2;
         const double bgg = V23 * (p1x * p1x + p1y * p1y + p1z * p1z);
-        const double bls = V23 * (gl[c][0] * gl[c][0] + gl[c][1] * gl[c][1] + gl[c][2] * gl[c][2]);
+        const double bls = V23 * (gl[0] * gl[0] + gl[1] * gl[1] + gl[2] * gl[2]);
         const double b1 = fmin(bgg, bls);
         // beta_2: first derivatives (linear in dx) squared and integrated, plus constant second derivatives
-        const double hx[3] = {2.0 * ac[3], ac[6], ac[8]};
-        const double hy[3] = {ac[6], 2.0 * ac[4], ac[7]};
-        const double hz[3] = {ac[8], ac[7], 2.0 * ac[5]};
+        const double hx[3] = {2.0 * a[3], a[6], a[8]};
+        const double hy[3] = {a[6], 2.0 * a[4], a[7]};
+        const double hz[3] = {a[8], a[7], 2.0 * a[5]};
         const double *hh[3] = {hx, hy, hz};
         double first = 0.0;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const double *h = hh[d];
-            first += ac[d] * ac[d] * V + h[0] * h[0] * I[0] + h[1] * h[1] * I[1] + h[2] * h[2] * I[2] +
+            first += a[d] * a[d] * V + h[0] * h[0] * I[0] + h[1] * h[1] * I[1] + h[2] * h[2] * I[2] +
                      2.0 * (h[0] * h[1] * I[3] + h[1] * h[2] * I[4] + h[0] * h[2] * I[5]);
         }
-        const double second = 4.0 * (ac[3] * ac[3] + ac[4] * ac[4] + ac[5] * ac[5]) + ac[6] * ac[6] + ac[7] * ac[7] +
-                              ac[8] * ac[8];
+        const double second = 4.0 * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5]) + a[6] * a[6] + a[7] * a[7] + a[8] * a[8];
         const double b2 = first / V13 + second * V * V13;
-        const double den = Q0[c] * Q0[c] + b1 + 1e-40;
+        const double den = q0 * q0 + b1 + 1e-40;
         const double t1 = b1 / den, t2 = b2 / den;
         const double sg = fabs(t2 - t1);
         const double r1 = sg / (A.weno_eps + t1), r2 = sg / (A.weno_eps + t2);
@@ -169,15 +149,34 @@ __global__ __launch_bounds__(128) void k_recon(ReconArgs A)
         w2 *= ws;
         // R = w2 (p2/g2 - g1/g2 p1) + w1 p1
         const double c2 = w2 / g2, c1 = w1 - w2 * g1 / g2;
-        double r0 = Q0[c];
+        double r0 = q0;
 #pragma unroll
-        for (int k = 3; k < 9; ++k) r0 -= ac[k] * I[k - 3] / V;
-        out[(10 * c) * N + i] = c2 * r0 + c1 * Q0[c];
-        out[(10 * c + 1) * N + i] = c2 * ac[0] + c1 * p1x;
-        out[(10 * c + 2) * N + i] = c2 * ac[1] + c1 * p1y;
-        out[(10 * c + 3) * N + i] = c2 * ac[2] + c1 * p1z;
+        for (int k = 3; k < 9; ++k) r0 -= a[k] * I[k - 3] / V;
+        r[0] = c2 * r0 + c1 * q0;
+        r[1] = c2 * a[0] + c1 * p1x;
+        r[2] = c2 * a[1] + c1 * p1y;
+        r[3] = c2 * a[2] + c1 * p1z;
 #pragma unroll
-        for (int k = 3; k < 9; ++k) out[(10 * c + 1 + k) * N + i] = c2 * ac[k];
+        for (int k = 3; k < 9; ++k) r[1 + k] = c2 * a[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        if (CELL_MAJOR) A.coef[i * 50 + 10 * C + k] = r[k];
+        else A.coef[(10 * C + k) * N + i] = r[k];
+    }
+}
+
+template <bool CELL_MAJOR> __global__ __launch_bounds__(320) void k_recon(ReconArgs A)
+{
+    const int64_t i = (int64_t)blockIdx.x * OP_GROUP + (threadIdx.x & (OP_GROUP - 1));
+    if (i >= A.N) return;
+    // the component is uniform over a wave
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+    case 0: recon_component<0, CELL_MAJOR>(A, i); break;
+    case 1: recon_component<1, CELL_MAJOR>(A, i); break;
+    case 2: recon_component<2, CELL_MAJOR>(A, i); break;
+    case 3: recon_component<3, CELL_MAJOR>(A, i); break;
+    default: recon_component<4, CELL_MAJOR>(A, i); break;
     }
 }
 
@@ -189,18 +188,19 @@ struct FaceArgs {
     const double *coef, *dtc, *cen, *gpx, *gpw, *gpn, *fshift;
     const int32_t *fl, *fr, *ftag, *fngp;
     const BcTable *bc;
-    double *out;  // [nq][F]
+    double *out;  // [F][nq], face-major
     int32_t *bad;
 };
 
-__device__ __forceinline__ void eval_poly(const double *__restrict__ coef, int64_t N, int64_t cell, const double dx[3],
+__device__ __forceinline__ void eval_poly(const double *__restrict__ coef, int64_t cell, const double dx[3],
                                           double w[5], double g[15])
 {
+    const double *cc = coef + cell * 50;  // cell-major: 10 coefficients per component
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
         double r[10];
 #pragma unroll
-        for (int k = 0; k < 10; ++k) r[k] = coef[(10 * c + k) * N + cell];
+        for (int k = 0; k < 10; ++k) r[k] = cc[10 * c + k];
         poly_eval(r, dx, w[c], &g[3 * c]);
     }
 }
@@ -213,7 +213,7 @@ __device__ __forceinline__ double group4_sum(double v)
 }
 
 // One lane per (face, Gauss point); four lanes per face, summed with lane shuffles.
-template <class T, int MODE> __global__ __launch_bounds__(256) void k_face(FaceArgs A)
+template <class T, int MODE, bool VAL> __global__ __launch_bounds__(256) void k_face(FaceArgs A)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t f = gid >> 2;
@@ -237,12 +237,12 @@ template <class T, int MODE> __global__ __launch_bounds__(256) void k_face(FaceA
         double WL[5], GL[15], WR[5], GR[15];
         {
             const double dx[3] = {x[0] - A.cen[L], x[1] - A.cen[N + L], x[2] - A.cen[2 * N + L]};
-            eval_poly(A.coef, N, L, dx, WL, GL);
+            eval_poly(A.coef, L, dx, WL, GL);
         }
         if (R >= 0) {
             const double dx[3] = {x[0] - A.fshift[f] - A.cen[R], x[1] - A.fshift[F + f] - A.cen[N + R],
                                   x[2] - A.fshift[2 * F + f] - A.cen[2 * N + R]};
-            eval_poly(A.coef, N, R, dx, WR, GR);
+            eval_poly(A.coef, R, dx, WR, GR);
         } else {
             const int tag = A.ftag[f];
             ghost_state(*A.bc, tag, n, WL, A.cfg.gamma, WR);
@@ -254,8 +254,7 @@ template <class T, int MODE> __global__ __launch_bounds__(256) void k_face(FaceA
         to_local(WL, GL, n, t1, t2, wl, gl);
         to_local(WR, GR, n, t1, t2, wr, gr);
         GksMoments<T> mo;
-        const bool need_val = MODE != MODE_RESONLY || (A.cfg.viscous && A.cfg.prandtl != 1.0);
-        if (!gks_moments<T>(wl, gl, wr, gr, T(A.cfg.gamma), T(A.cfg.K), mo, need_val)) {
+        if (!gks_moments<T>(wl, gl, wr, gr, T(A.cfg.gamma), T(A.cfg.K), mo, VAL)) {
             atomicMin(A.bad, L);
         } else {
             T tau, taun;
@@ -325,23 +324,12 @@ template <class T, int MODE> __global__ __launch_bounds__(256) void k_face(FaceA
         alpha_k *= __shfl_xor(alpha_k, 1, 64);
         alpha_k *= __shfl_xor(alpha_k, 2, 64);
     }
+    // face-major record of NQ values (flux sums, interface-value sums, CF product last)
     if (k == 0) {
-        if (MODE == MODE_RES) {
+        double *o = A.out + f * NQ;
 #pragma unroll
-            for (int q = 0; q < 20; ++q) A.out[q * F + f] = acc[q];
-            A.out[20 * F + f] = alpha_k;
-        } else if (MODE == MODE_RESONLY) {
-#pragma unroll
-            for (int q = 0; q < 5; ++q) A.out[q * F + f] = acc[q];
-        } else if (MODE == MODE_S1) {
-#pragma unroll
-            for (int q = 0; q < 40; ++q) A.out[q * F + f] = acc[q];
-            A.out[40 * F + f] = alpha_k;
-        } else {
-#pragma unroll
-            for (int q = 0; q < 25; ++q) A.out[q * F + f] = acc[q];
-            A.out[25 * F + f] = alpha_k;
-        }
+        for (int q = 0; q < NQ; ++q) o[q] = acc[q];
+        if (MODE != MODE_RESONLY) o[NQ - 1] = alpha_k;
     }
 }
 
@@ -367,16 +355,17 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A, double *__restrict
 #pragma unroll
         for (int q = 0; q < 15; ++q) g[q] = 0.0;
         double al = 1.0;
+        constexpr int NQ = GRAD ? 21 : 5;
         for (int k = A.cf_ptr[i]; k < A.cf_ptr[i + 1]; ++k) {
             const int it = A.cf_face[k];
-            const int f = it >> 1;
+            const double *o = A.fout + (int64_t)(it >> 1) * NQ;
             const double s = (it & 1) ? -1.0 : 1.0;
 #pragma unroll
-            for (int q = 0; q < 5; ++q) r[q] -= s * A.fout[q * F + f];
+            for (int q = 0; q < 5; ++q) r[q] -= s * o[q];
             if (GRAD) {
 #pragma unroll
-                for (int q = 0; q < 15; ++q) g[q] += s * A.fout[(5 + q) * F + f];
-                al *= A.fout[20 * F + f];
+                for (int q = 0; q < 15; ++q) g[q] += s * o[5 + q];
+                al *= o[20];
             }
         }
         const double iv = 1.0 / A.vol[i];
@@ -421,23 +410,24 @@ __global__ __launch_bounds__(256) void k_gather_s2o4(GatherArgs A, int stage, do
 #pragma unroll
     for (int q = 0; q < 15; ++q) g1[q] = g2[q] = 0.0;
     double al = 1.0;
+    const int NQ = stage == 1 ? 41 : 26;
     for (int k = A.cf_ptr[i]; k < A.cf_ptr[i + 1]; ++k) {
         const int it = A.cf_face[k];
-        const int f = it >> 1;
+        const double *o = A.fout + (int64_t)(it >> 1) * NQ;
         const double s = (it & 1) ? -1.0 : 1.0;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            ri[q] -= s * A.fout[q * F + f];
-            rh[q] -= s * A.fout[(5 + q) * F + f];
+            ri[q] -= s * o[q];
+            rh[q] -= s * o[5 + q];
         }
 #pragma unroll
-        for (int q = 0; q < 15; ++q) g1[q] += s * A.fout[(10 + q) * F + f];
+        for (int q = 0; q < 15; ++q) g1[q] += s * o[10 + q];
         if (stage == 1) {
 #pragma unroll
-            for (int q = 0; q < 15; ++q) g2[q] += s * A.fout[(25 + q) * F + f];
-            al *= A.fout[40 * F + f];
+            for (int q = 0; q < 15; ++q) g2[q] += s * o[25 + q];
+            al *= o[40];
         } else {
-            al *= A.fout[25 * F + f];
+            al *= o[25];
         }
     }
     const double V = A.vol[i], iv = 1.0 / V;
@@ -535,7 +525,7 @@ void launch_local_dt(cgks_ctx *c, const double *W, double *dt)
                        c->vol.p, dt);
 }
 
-void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef)
+void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef, bool cell_major)
 {
     ReconArgs A;
     A.N = c->N;
@@ -553,10 +543,11 @@ void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *a
     A.slot_nb = c->slot_nb.p;
     A.ftag = c->ftag.p;
     A.op_off = c->op_off.p;
-    A.n_int = c->n_int.p;
     A.bc = c->bc.p;
     A.coef = coef;
-    hipLaunchKernelGGL(k_recon, dim3(blocks_for(c->N, 128)), dim3(128), 0, c->stream, A);
+    const dim3 grid(blocks_for(c->N, OP_GROUP)), blk(5 * OP_GROUP);
+    if (cell_major) hipLaunchKernelGGL((k_recon<true>), grid, blk, 0, c->stream, A);
+    else hipLaunchKernelGGL((k_recon<false>), grid, blk, 0, c->stream, A);
 }
 
 void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cell, double dt_global, bool fp32)
@@ -581,6 +572,7 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
     A.out = c->fout.p;
     A.bad = c->bad.p;
     const dim3 grid(blocks_for(4 * c->F, 256)), blk(256);
+    const bool prfix = c->prm.viscous && c->prm.prandtl != 1.0;  // heat-flux correction needs the value moments
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool timed = c->timing && mode == MODE_RES;
     if (timed) {
@@ -595,16 +587,22 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
     }
     if (fp32) {
         switch (mode) {
-        case MODE_RES: hipLaunchKernelGGL((k_face<float, MODE_RES>), grid, blk, 0, c->stream, A); break;
-        case MODE_RESONLY: hipLaunchKernelGGL((k_face<float, MODE_RESONLY>), grid, blk, 0, c->stream, A); break;
+        case MODE_RES: hipLaunchKernelGGL((k_face<float, MODE_RES, true>), grid, blk, 0, c->stream, A); break;
+        case MODE_RESONLY:
+            if (prfix) hipLaunchKernelGGL((k_face<float, MODE_RESONLY, true>), grid, blk, 0, c->stream, A);
+            else hipLaunchKernelGGL((k_face<float, MODE_RESONLY, false>), grid, blk, 0, c->stream, A);
+            break;
         default: throw Error{CGKS_E_ARG, "FP32 flux supports the steady modes only"};
         }
     } else {
         switch (mode) {
-        case MODE_RES: hipLaunchKernelGGL((k_face<double, MODE_RES>), grid, blk, 0, c->stream, A); break;
-        case MODE_RESONLY: hipLaunchKernelGGL((k_face<double, MODE_RESONLY>), grid, blk, 0, c->stream, A); break;
-        case MODE_S1: hipLaunchKernelGGL((k_face<double, MODE_S1>), grid, blk, 0, c->stream, A); break;
-        default: hipLaunchKernelGGL((k_face<double, MODE_S2>), grid, blk, 0, c->stream, A); break;
+        case MODE_RES: hipLaunchKernelGGL((k_face<double, MODE_RES, true>), grid, blk, 0, c->stream, A); break;
+        case MODE_RESONLY:
+            if (prfix) hipLaunchKernelGGL((k_face<double, MODE_RESONLY, true>), grid, blk, 0, c->stream, A);
+            else hipLaunchKernelGGL((k_face<double, MODE_RESONLY, false>), grid, blk, 0, c->stream, A);
+            break;
+        case MODE_S1: hipLaunchKernelGGL((k_face<double, MODE_S1, true>), grid, blk, 0, c->stream, A); break;
+        default: hipLaunchKernelGGL((k_face<double, MODE_S2, true>), grid, blk, 0, c->stream, A); break;
         }
     }
     if (timed) CGKS_HIP(hipEventRecord(e1, c->stream));

@@ -260,7 +260,8 @@ __global__ void k_slots(int64_t N, int64_t F, const int32_t *__restrict__ cf_ptr
 // linear least-squares operator used by the smoothness indicator beta_1,LS.
 //  unknowns a_1..a_9 of sum_k a_k (phi_k - avg_0 phi_k), phi = dx dy dz dx^2 dy^2 dz^2 dxdy dydz dxdz;
 //  rows: neighbour averages exactly (Lagrange multipliers), h0-scaled gradient averages in LS.
-//  op[k][col]: col < nb multiplies (Q_m - Q_0), col = nb + 3m + d multiplies (dQ/dx_d)_m.
+//  Solution columns: col < nb multiplies (Q_m - Q_0), col = nb + 3m + d multiplies (dQ/dx_d)_m;
+//  stored per interior neighbour m as 39 entries (see the reconstruction kernel), stride 64.
 __global__ void k_op_build(int64_t N, int64_t F, const int32_t *__restrict__ cf_ptr, const int32_t *__restrict__ cf_face,
                            const int32_t *__restrict__ fl, const int32_t *__restrict__ fr,
                            const double *__restrict__ fshift, const double *__restrict__ vol,
@@ -352,8 +353,12 @@ __global__ void k_op_build(int64_t N, int64_t F, const int32_t *__restrict__ cf_
             B[c][q] = s / K[c][c];
         }
     }
-    for (int k = 0; k < 9; ++k)
-        for (int q = 0; q < nc; ++q) op[off + k * nc + q] = B[k][q];
+    // entry m*39 + j of the cell, stride 64 (group-interleaved)
+    for (int m = 0; m < nb; ++m)
+        for (int k = 0; k < 9; ++k) {
+            op[off + 64 * (39 * m + k)] = B[k][m];
+            for (int d = 0; d < 3; ++d) op[off + 64 * (39 * m + 9 + 3 * k + d)] = B[k][nb + 3 * m + d];
+        }
     // linear least squares: (sum D D^T)^-1 D_m
     double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     for (int m = 0; m < nb; ++m)
@@ -375,10 +380,9 @@ __global__ void k_op_build(int64_t N, int64_t F, const int32_t *__restrict__ cf_
     Ai[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / det;
     Ai[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
     Ai[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
-    const int64_t lo = off + 9 * nc;
     for (int d = 0; d < 3; ++d)
         for (int m = 0; m < nb; ++m)
-            op[lo + d * nb + m] = Ai[d][0] * D[m][0] + Ai[d][1] * D[m][1] + Ai[d][2] * D[m][2];
+            op[off + 64 * (39 * m + 36 + d)] = Ai[d][0] * D[m][0] + Ai[d][1] * D[m][1] + Ai[d][2] * D[m][2];
 }
 
 // ------------------------------------------------------------------ host ingest
@@ -523,14 +527,17 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
         nint[hfl[f]]++;
         nint[hfr[f]]++;
     }
+    // Operators are interleaved over groups of 64 consecutive cells: entry e of cell i is
+    // at op_off[i] + 64 e, each group sized for its largest interior-neighbour count.
     std::vector<int64_t> off(N);
     int64_t tot = 0;
-    for (int64_t i = 0; i < N; ++i) {
-        if (nint[i] >= 3) {
-            off[i] = tot;
-            tot += 39 * (int64_t)nint[i];
-        } else
-            off[i] = -1;
+    for (int64_t g0 = 0; g0 < N; g0 += 64) {
+        const int64_t g1 = std::min<int64_t>(N, g0 + 64);
+        int nbmax = 0;
+        for (int64_t i = g0; i < g1; ++i)
+            if (nint[i] >= 3) nbmax = std::max<int>(nbmax, nint[i]);
+        for (int64_t i = g0; i < g1; ++i) off[i] = nint[i] >= 3 ? tot + (i - g0) : -1;
+        tot += 64 * 39 * (int64_t)nbmax;
     }
     // upload and compute geometry
     c->N = N;
