@@ -34,6 +34,10 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_GP = 6270.75
 FP64_PEAK_TFLOPS = 78.6       # MI355X dense FP64 vector
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the same face kernel on this workload, from two rocprofv3 counter passes
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors read off a 1 GiB copy and fill in the same runs).
+# Set to None whenever the face kernel changes until the counters are taken again.
+FACE_HBM_BYTES_PER_LAUNCH = 418.2e6
 
 
 def log(*a):
@@ -165,7 +169,8 @@ def main():
         "cells_evals_per_s": value * N,
         "setup_s": {"mesh_and_geometry": t_mesh, "agglomeration": t_agg},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved_tflops / FP64_PEAK_TFLOPS, "traffic": FACE_HBM_BYTES_PER_LAUNCH,
+                     "traffic_unit": "bytes per launch",
                      "kernel": "k_face<double, steady> (BGK flux at face Gauss points)",
                      "avg_ms": face_avg_ms, "launches": face_n, "flops_per_gp": FLOPS_PER_GP},
     }
