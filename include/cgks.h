@@ -155,6 +155,16 @@ cgks_status cgks_step(cgks_ctx *ctx, double *W, double *G, double *alpha, double
  */
 cgks_status cgks_check(cgks_ctx *ctx);
 
+/*
+ * Force of the gas on the boundary faces carrying `tag` (the integrated surface force behind the
+ * drag coefficients of paper Sec. 5): F[d] = sum over those faces of S_p sum_k w_k F_mom,d(x_pk),
+ * the momentum part of the same time-averaged face flux as cgks_residual, normal pointing out of
+ * the gas.  W, G, alpha (nullable) device in; F: device double[3] out.  Faces are summed in a fixed
+ * order by one work-group: deterministic.  CGKS_E_ARG for a tag outside 1..63.
+ */
+cgks_status cgks_wall_force(cgks_ctx *ctx, const double *W, const double *G, const double *alpha, int32_t tag,
+                            double *F);
+
 /* RMS of R_rho/|Omega| (device R in, device scalar out). */
 cgks_status cgks_residual_norm(cgks_ctx *ctx, const double *R, double *out);
 

@@ -48,6 +48,7 @@ def lib():
         L.om_mesh_faces.argtypes = [P] + [P] * 11
         L.om_mesh_set_bc.argtypes = [P, C.c_int32, C.c_int, P]
         L.om_residual.argtypes = [P, P, P, P, P, P, P, P, P, P, I64, P]
+        L.om_wall_force.argtypes = [P, P, P, P, P, C.c_int32, P, P]
         L.om_residual_norm.restype = D
         L.om_residual_norm.argtypes = [P, P]
         L.om_local_dt.argtypes = [P, P, P, P]
@@ -162,6 +163,17 @@ class Mesh:
 
     def residual_norm(self, R):
         return lib().om_residual_norm(self.h, _p(_f64(R)))
+
+    def wall_force(self, par, W, G, alpha, tag):
+        """Force of the gas on the boundary faces with `tag` (3 components)."""
+        out = np.zeros(3)
+        bad = C.c_int64(-1)
+        al = None if alpha is None else _f64(alpha)
+        e = lib().om_wall_force(self.h, C.byref(par), _p(_f64(W)), _p(_f64(G)), _p(al), int(tag), _p(out),
+                                C.byref(bad))
+        if e:
+            raise OracleError(f"wall force failed ({e}) at cell {bad.value}")
+        return out
 
     def step_fe(self, par, W, G, alpha):
         bad = C.c_int64(-1)

@@ -384,3 +384,45 @@ int om_reconstruct_all(const om_mesh *m, const om_params *p, const double *W, co
         if (om_reconstruct_cell(m, p, W, G, alpha, c, &coef[50 * c])) return (int)c + 1;
     return 0;
 }
+
+/*
+ * Force of the gas on the boundary faces carrying `tag` (the drag/lift integrand of the
+ * sphere and bump results, Sec. 5): the momentum components of the face flux,
+ *   F = sum_{faces with tag} S_p sum_k w_k F_mom(x_pk),
+ * with the same reconstruction, local face step and time-averaged BGK flux as the residual
+ * (Sec. 2.2, Eq. 2nd-flux, Eq. gauss-formula), the normal pointing out of the gas.  Faces are
+ * summed in ascending face order.
+ */
+int om_wall_force(const om_mesh *m, const om_params *p, const double *W, const double *G, const double *alpha,
+                  int32_t tag, double Fout[3], int64_t *bad_cell)
+{
+    const int64_t N = m->n_cells, NF = m->n_faces;
+    *bad_cell = -1;
+    Fout[0] = Fout[1] = Fout[2] = 0.0;
+    double *dtc = (double *)malloc(sizeof(double) * N);
+    if (om_local_dt(m, p, W, dtc)) {
+        free(dtc);
+        return -5;
+    }
+    double *coef = (double *)calloc(50 * N, sizeof(double));
+    int err = 0;
+    for (int64_t f = 0; f < NF && !err; ++f) {
+        if (m->fr[f] >= 0 || m->ftag[f] != tag) continue;
+        const int64_t l = m->fl[f];
+        err = om_reconstruct_cell(m, p, W, G, alpha, l, &coef[50 * l]);
+        if (err) {
+            *bad_cell = l;
+            break;
+        }
+        facesum s;
+        err = face_eval(m, p, coef, f, dtc[l], &s);
+        if (err) {
+            *bad_cell = l;
+            break;
+        }
+        for (int d = 0; d < 3; ++d) Fout[d] += s.F[1 + d];
+    }
+    free(coef);
+    free(dtc);
+    return err;
+}

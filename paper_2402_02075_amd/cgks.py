@@ -22,7 +22,7 @@ EXPORTS = ["cgks_default_params", "cgks_create", "cgks_destroy", "cgks_last_erro
            "cgks_set_stream", "cgks_set_mesh", "cgks_set_bc", "cgks_mesh_info", "cgks_geometry", "cgks_local_dt",
            "cgks_reconstruct", "cgks_residual", "cgks_step", "cgks_check", "cgks_residual_norm",
            "cgks_agglomerate_graph", "cgks_agglomerate", "cgks_level_map", "cgks_kfvs_residual", "cgks_restrict",
-           "cgks_prolong", "cgks_vcycle", "cgks_timing"]
+           "cgks_prolong", "cgks_vcycle", "cgks_timing", "cgks_wall_force"]
 
 
 class Params(C.Structure):
@@ -59,6 +59,7 @@ def lib():
             "cgks_agglomerate": [P], "cgks_level_map": [P, I32, P], "cgks_kfvs_residual": [P, I32, P, P],
             "cgks_restrict": [P, I32, P, P, P, P], "cgks_prolong": [P, I32, P, P],
             "cgks_vcycle": [P, P, P, P, I32, D, P, P], "cgks_timing": [P, I32, P, P],
+            "cgks_wall_force": [P, P, P, P, I32, P],
         }
         for name, args in sig.items():
             if not hasattr(L, name):
@@ -202,6 +203,12 @@ class Solver:
     def residual_norm(self, R):
         out = self.empty(1)
         self._check(lib().cgks_residual_norm(self.h, _ptr(R), _ptr(out)))
+        return out
+
+    def wall_force(self, W, G, alpha, tag):
+        """Force of the gas on the boundary faces with `tag`: device tensor of 3 doubles."""
+        out = self.empty(3)
+        self._check(lib().cgks_wall_force(self.h, _ptr(W), _ptr(G), _ptr(alpha), C.c_int32(int(tag)), _ptr(out)))
         return out
 
     # ---------------------------------------------------------------- multigrid

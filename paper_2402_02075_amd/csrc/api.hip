@@ -242,6 +242,20 @@ cgks_status cgks_residual(cgks_ctx *c, const double *W, const double *G, const d
     API_END(c)
 }
 
+cgks_status cgks_wall_force(cgks_ctx *c, const double *W, const double *G, const double *alpha, int32_t tag, double *F)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    if (!W || !G || !F) throw Error{CGKS_E_ARG, "W, G and F required"};
+    if (tag < 1 || tag > 63) throw Error{CGKS_E_ARG, "tag must be in 1..63"};
+    launch_local_dt(c, W, c->dtc.p);
+    launch_recon(c, W, G, alpha, c->coef.p);
+    launch_face(c, MODE_RESONLY, c->coef.p, c->dtc.p, -1.0, false);
+    launch_wall_force(c, tag, F);
+    CGKS_HIP(hipGetLastError());
+    API_END(c)
+}
+
 cgks_status cgks_step(cgks_ctx *c, double *W, double *G, double *alpha, double dt_global, double *resnorm)
 {
     API_BEGIN(c)

@@ -149,6 +149,7 @@ void launch_gather_res(cgks_ctx *c, double *R, double *Gn, double *an, int mode)
 void launch_gather_fe(cgks_ctx *c, double *W, double *G, double *alpha, const double *dt, double *Rout, double *norm_part);
 void launch_gather_s2o4(cgks_ctx *c, int stage, double dt, double *W, double *G, double *alpha);
 void launch_norm(cgks_ctx *c, const double *R, const double *vol, int64_t n, double *out);
+void launch_wall_force(cgks_ctx *c, int32_t tag, double *out);  // after a MODE_RESONLY face launch
 void finish_norm(cgks_ctx *c, const double *partials, int nblocks, int64_t n, double *out);
 int norm_blocks(int64_t n);
 void launch_fill(double *p, double v, int64_t n, hipStream_t s);

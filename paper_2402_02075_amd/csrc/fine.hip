@@ -458,6 +458,36 @@ __global__ __launch_bounds__(256) void k_gather_s2o4(GatherArgs A, int stage, do
     }
 }
 
+// ---------------------------------------------------------------- wall force
+// One work-group: each thread sums a fixed stride of the boundary faces, then a fixed tree.
+__global__ __launch_bounds__(256) void k_wall_force(int64_t f0, int64_t f1, int32_t tag, int nq,
+                                                     const int32_t *__restrict__ ftag, const double *__restrict__ fout,
+                                                     double *__restrict__ out)
+{
+    __shared__ double sm[3][256];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t f = f0 + threadIdx.x; f < f1; f += 256)
+        if (ftag[f] == tag)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) acc[d] += fout[f * nq + 1 + d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) sm[d][threadIdx.x] = acc[d];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sm[d][threadIdx.x] += sm[d][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[threadIdx.x] = sm[threadIdx.x][0];
+}
+
+void launch_wall_force(cgks_ctx *c, int32_t tag, double *out)
+{
+    // face records of the last residual-only face launch (5 values per face)
+    hipLaunchKernelGGL(k_wall_force, dim3(1), dim3(256), 0, c->stream, c->Fi, c->F, tag, 5, c->ftag.p, c->fout.p, out);
+}
+
 // ---------------------------------------------------------------- norm
 __global__ __launch_bounds__(256) void k_norm_part(int64_t n, const double *__restrict__ R,
                                                    const double *__restrict__ vol, double *__restrict__ part)

@@ -209,3 +209,21 @@ def test_full_size_bump_sampled(oracle, cg, torch):
     surf = cell_surface(F, M.n_cells)
     assert_residual_close(R.cpu().numpy()[:, sub], oR[:, sub], surf[sub], flux_scale(W), what="R sampled")
     np.testing.assert_allclose(an.cpu().numpy()[sub], oan[sub], rtol=1e-10, atol=1e-14)
+
+
+@pytest.mark.parametrize("wall_kind", [1, 2])
+def test_wall_force(oracle, cg, torch, wall_kind):
+    """Force on the lower (bump) wall: summed momentum flux of the wall faces, parity with the
+    oracle to 1e-12 of the summed face-flux magnitude (the two sum faces in different orders)."""
+    m = MESHES["bump"]()
+    say(f"[gpu] wall force bump wall_kind={wall_kind} cells={m.n_cells}")
+    M, S = _pair(oracle, cg, m, _channel_bc_list(wall_kind))
+    W, G, al = _smooth_state(m, seed=21)
+    par = oracle.params()
+    Fo = M.wall_force(par, W, G, al, mg.TAG_WALL_BOTTOM)
+    Fg = S.wall_force(to_dev(torch, W), to_dev(torch, G), to_dev(torch, al), mg.TAG_WALL_BOTTOM).cpu().numpy()
+    scale = flux_scale(W)[1] * 1.5  # largest momentum flux times the wall area
+    np.testing.assert_allclose(Fg, Fo, rtol=0, atol=1e-12 * scale)
+    # a tag without faces gives zero
+    Fz = S.wall_force(to_dev(torch, W), to_dev(torch, G), None, 60).cpu().numpy()
+    assert np.all(Fz == 0.0)

@@ -396,3 +396,53 @@ def test_vcycle_accelerates_convergence(oracle):
                 hist.append(H.vcycle(par, W, G, al))
         res[mode] = hist[-1] / hist[0]
     assert res["vcycle"] < res["explicit"]
+
+
+# ------------------------------------------------------------------ wall force
+def _face_area_vectors(m, tag):
+    """Area vectors of the boundary faces with `tag` from their nodes (exact for a bilinear quad)."""
+    out = []
+    for b in range(m.btag.shape[0]):
+        if m.btag[b] != tag:
+            continue
+        x = m.xyz[m.bnode[m.bnode_ptr[b]:m.bnode_ptr[b + 1]]]
+        if x.shape[0] == 3:
+            a = 0.5 * np.cross(x[1] - x[0], x[2] - x[0])
+        else:
+            a = 0.5 * np.cross(x[2] - x[0], x[3] - x[1])
+        out.append(a)
+    return np.array(out)
+
+
+def test_wall_force_rest_state_is_pressure_times_area(oracle):
+    """Gas at rest: every face flux is p n exactly, so the force on the curved lower wall is
+    p times the sum of its face area vectors (computed here from the nodes)."""
+    m = mg.bump_channel(12, 8, 4, n_prism=2, n_pyr=3, jitter=0.1, seed=5, amp=0.05)
+    M = oracle.Mesh(m)
+    for tag in (mg.TAG_INLET, mg.TAG_OUTLET, mg.TAG_WALL_BOTTOM, mg.TAG_WALL_TOP, mg.TAG_WALL_SIDE):
+        M.set_bc(tag, oracle.BC_SLIP)
+    p0, gam = 0.8, 1.4
+    W = np.zeros((5, m.n_cells))
+    W[0] = 1.0
+    W[4] = p0 / (gam - 1)
+    G = np.zeros((15, m.n_cells))
+    F = M.wall_force(oracle.params(), W, G, None, mg.TAG_WALL_BOTTOM)
+    A = _face_area_vectors(m, mg.TAG_WALL_BOTTOM)
+    A *= -np.sign(A[:, 1])[:, None]  # out of the gas: downwards through the lower wall
+    ref = p0 * A.sum(axis=0)
+    assert ref[1] == pytest.approx(-1.5 * p0, rel=1e-12)  # projected area of the wall
+    np.testing.assert_allclose(F, ref, rtol=0, atol=1e-13 * p0 * 1.5)
+
+
+def test_wall_force_uniform_flow_flat_wall(oracle, channel):
+    """Uniform stream tangent to a flat slip wall: the ghost state equals the interior state, the
+    flux is the Euler flux, and its momentum part through the wall is p n: F = (0, -p A, 0)."""
+    m, M = channel
+    _setup_channel_bc(oracle, M)
+    W, G = mg.uniform_state(m.n_cells)
+    F = M.wall_force(oracle.params(), W, G, None, mg.TAG_WALL_BOTTOM)
+    p = 1 / 1.4
+    np.testing.assert_allclose(F, [0.0, -1.5 * p, 0.0], rtol=0, atol=1e-13)
+    # upper wall: normal +y
+    Ft = M.wall_force(oracle.params(), W, G, None, mg.TAG_WALL_TOP)
+    np.testing.assert_allclose(Ft, [0.0, 1.5 * p, 0.0], rtol=0, atol=1e-13)
