@@ -165,6 +165,59 @@ cgks_status cgks_check(cgks_ctx *ctx);
 cgks_status cgks_wall_force(cgks_ctx *ctx, const double *W, const double *G, const double *alpha, int32_t tag,
                             double *F);
 
+/*
+ * Discrete adjoint (vector-Jacobian products of the operators above).
+ *
+ * The fine operator is E(W, G, alpha) = (R, G_new, alpha_new) of cgks_residual.
+ * cgks_linearize records its exact local Jacobians at one state (device W, G,
+ * alpha nullable = ones): per Gauss point the derivatives of the time-averaged
+ * flux, interface value and compression factor (paper Eq. 2nd-flux, Sec. 2.4,
+ * Sec. 3.3) with respect to the two reconstructed states, their gradients and
+ * the face step; per cell and component those of the HWENO coefficients (Sec. 3)
+ * with respect to the stencil data; per cell that of the local time step.
+ * Device memory kept: about (451 x 4F + 1650 N) doubles, released with the
+ * context.  CGKS_E_PHYS if a Gauss-point state is non-physical.  Any later
+ * cgks_set_mesh, cgks_set_bc, cgks_set_params or cgks_agglomerate invalidates it.
+ */
+cgks_status cgks_linearize(cgks_ctx *ctx, const double *W, const double *G, const double *alpha);
+
+/*
+ * barW[5N], barG[15N], barAlpha[N] (device out, barAlpha nullable) =
+ *   (dE/d(W, G, alpha))^T (barR[5N], barGnew[15N], barAnew[N]) at the linearised state.
+ * barGnew and barAnew may be NULL (zero cotangents).  CGKS_E_STATE without cgks_linearize.
+ */
+cgks_status cgks_vjp_residual(cgks_ctx *ctx, const double *barR, const double *barGnew, const double *barAnew,
+                              double *barW, double *barG, double *barAlpha);
+
+/*
+ * Gradient of J = e . F_wall(tag) (cgks_wall_force) at the linearised state with
+ * respect to (W, G, alpha): device barW[5N], barG[15N], barAlpha[N] (nullable); e host double[3].
+ */
+cgks_status cgks_vjp_wall_force(cgks_ctx *ctx, int32_t tag, const double *e, double *barW, double *barG,
+                                double *barAlpha);
+
+/*
+ * Coarse KFVS operator of cgks_kfvs_residual on `level` (>= 1, paper Sec. 4.2):
+ * barWc[5n] = (dR_c/dW_c)^T barRc[5n] at the coarse state Wc (all device, FP64).
+ * Exact face Jacobians, recomputed per call; deterministic gathers.
+ */
+cgks_status cgks_vjp_kfvs(cgks_ctx *ctx, int32_t level, const double *Wc, const double *barRc, double *barWc);
+
+/*
+ * Adjoint fixed point of the V-cycle (cgks_vcycle, FP64, one pre-sweep per level,
+ * no post-sweeps) at the linearised state, which must be converged:
+ *   lam = (dPhi/dU)^T lam + dJ/dU,  J = e . F_wall(tag),  U = (W, G, alpha),
+ * iterated until |lam_k+1 - lam_k| <= tol |lam_k+1| or max_iter.  Device outputs
+ * (each nullable): lamW[5N], lamG[15N], lamA[N]; and the cotangents cR[5N], cG[15N],
+ * cA[N] on the fine operator's outputs (R, G_new, alpha_new) with which a parameter
+ * p enters: dJ/dp = dJ/dp|_U + cR . dR/dp + cG . dG_new/dp + cA . dalpha_new/dp.
+ * hist (host, nullable, max_iter doubles) receives the relative change per iteration;
+ * n_done (host) the iterations run.  Synchronises once per iteration.
+ */
+cgks_status cgks_adjoint_solve(cgks_ctx *ctx, int32_t tag, const double *e, int32_t max_iter, double tol,
+                               double *lamW, double *lamG, double *lamA, double *cR, double *cG, double *cA,
+                               double *hist, int32_t *n_done);
+
 /* RMS of R_rho/|Omega| (device R in, device scalar out). */
 cgks_status cgks_residual_norm(cgks_ctx *ctx, const double *R, double *out);
 

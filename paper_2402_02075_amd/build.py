@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcgks.so")
-SOURCES = ["api.hip", "mesh.hip", "fine.hip", "coarse.hip"]
+SOURCES = ["api.hip", "mesh.hip", "fine.hip", "coarse.hip", "adjoint.hip"]
 ARCH = os.environ.get("CGKS_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",

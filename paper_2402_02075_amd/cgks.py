@@ -22,7 +22,8 @@ EXPORTS = ["cgks_default_params", "cgks_create", "cgks_destroy", "cgks_last_erro
            "cgks_set_stream", "cgks_set_mesh", "cgks_set_bc", "cgks_mesh_info", "cgks_geometry", "cgks_local_dt",
            "cgks_reconstruct", "cgks_residual", "cgks_step", "cgks_check", "cgks_residual_norm",
            "cgks_agglomerate_graph", "cgks_agglomerate", "cgks_level_map", "cgks_kfvs_residual", "cgks_restrict",
-           "cgks_prolong", "cgks_vcycle", "cgks_timing", "cgks_wall_force"]
+           "cgks_prolong", "cgks_vcycle", "cgks_timing", "cgks_wall_force", "cgks_linearize", "cgks_vjp_residual",
+           "cgks_vjp_wall_force", "cgks_vjp_kfvs", "cgks_adjoint_solve"]
 
 
 class Params(C.Structure):
@@ -59,7 +60,9 @@ def lib():
             "cgks_agglomerate": [P], "cgks_level_map": [P, I32, P], "cgks_kfvs_residual": [P, I32, P, P],
             "cgks_restrict": [P, I32, P, P, P, P], "cgks_prolong": [P, I32, P, P],
             "cgks_vcycle": [P, P, P, P, I32, D, P, P], "cgks_timing": [P, I32, P, P],
-            "cgks_wall_force": [P, P, P, P, I32, P],
+            "cgks_wall_force": [P, P, P, P, I32, P], "cgks_linearize": [P, P, P, P],
+            "cgks_vjp_residual": [P, P, P, P, P, P, P], "cgks_vjp_wall_force": [P, I32, P, P, P, P],
+            "cgks_vjp_kfvs": [P, I32, P, P, P], "cgks_adjoint_solve": [P, I32, P, I32, D, P, P, P, P, P, P, P, P],
         }
         for name, args in sig.items():
             if not hasattr(L, name):
@@ -209,6 +212,50 @@ class Solver:
         """Force of the gas on the boundary faces with `tag`: device tensor of 3 doubles."""
         out = self.empty(3)
         self._check(lib().cgks_wall_force(self.h, _ptr(W), _ptr(G), _ptr(alpha), C.c_int32(int(tag)), _ptr(out)))
+        return out
+
+    # ---------------------------------------------------------------- discrete adjoint
+    def linearize(self, W, G, alpha=None):
+        """Record the exact local Jacobians of the fine operator at (W, G, alpha)."""
+        self._check(lib().cgks_linearize(self.h, _ptr(W), _ptr(G), _ptr(alpha)))
+
+    def vjp_residual(self, barR, barGnew=None, barAnew=None):
+        """(dE/dU)^T (barR, barGnew, barAnew) at the linearised state -> (barW, barG, barAlpha)."""
+        N = self.n_cells
+        bW, bG, bA = self.empty(5, N), self.empty(15, N), self.empty(N)
+        self._check(lib().cgks_vjp_residual(self.h, _ptr(barR), _ptr(barGnew), _ptr(barAnew), _ptr(bW), _ptr(bG),
+                                            _ptr(bA)))
+        return bW, bG, bA
+
+    def vjp_wall_force(self, tag, e=(1.0, 0.0, 0.0)):
+        """Gradient of e . F_wall(tag) with respect to (W, G, alpha) at the linearised state."""
+        N = self.n_cells
+        bW, bG, bA = self.empty(5, N), self.empty(15, N), self.empty(N)
+        ev = (C.c_double * 3)(*[float(x) for x in e])
+        self._check(lib().cgks_vjp_wall_force(self.h, C.c_int32(int(tag)), ev, _ptr(bW), _ptr(bG), _ptr(bA)))
+        return bW, bG, bA
+
+    def vjp_kfvs(self, level, Wc, barRc):
+        out = self.empty(*tuple(Wc.shape))
+        self._check(lib().cgks_vjp_kfvs(self.h, C.c_int32(int(level)), _ptr(Wc), _ptr(barRc), _ptr(out)))
+        return out
+
+    def adjoint_solve(self, tag, e=(1.0, 0.0, 0.0), max_iter=20000, tol=1e-10):
+        """Adjoint fixed point through the transposed V-cycle at the linearised (converged) state.
+
+        Returns dict with lamW, lamG, lamA, cR, cG, cA (device tensors), hist (numpy) and iterations."""
+        N = self.n_cells
+        out = {k: self.empty(*s) for k, s in (("lamW", (5, N)), ("lamG", (15, N)), ("lamA", (N,)), ("cR", (5, N)),
+                                                ("cG", (15, N)), ("cA", (N,)))}
+        hist = np.zeros(int(max_iter))
+        nd = C.c_int32(0)
+        ev = (C.c_double * 3)(*[float(x) for x in e])
+        self._check(lib().cgks_adjoint_solve(self.h, C.c_int32(int(tag)), ev, C.c_int32(int(max_iter)), float(tol),
+                                             _ptr(out["lamW"]), _ptr(out["lamG"]), _ptr(out["lamA"]), _ptr(out["cR"]),
+                                             _ptr(out["cG"]), _ptr(out["cA"]), hist.ctypes.data_as(C.c_void_p),
+                                             C.byref(nd)))
+        out["hist"] = hist[:nd.value]
+        out["iterations"] = nd.value
         return out
 
     # ---------------------------------------------------------------- multigrid

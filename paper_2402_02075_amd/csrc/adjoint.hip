@@ -1,0 +1,1026 @@
+// Discrete adjoint of the fine CGKS operator and of the coarse KFVS operator,
+// and the adjoint fixed-point iteration through the transposed V-cycle.
+//
+// Fine operator (Sec. 2.2 Eq. semidiscrete, Sec. 2.3 Eq. 2nd-flux, Sec. 2.4,
+// Sec. 3): E(W, G, alpha) = (R, G_new, alpha_new) with the local face step
+// dt_f = min(dt_L, dt_R) of the local time steps.  Its linearisation is taken once
+// at a state and kept in HBM:
+//   * per Gauss-point slot the 11 x 41 Jacobian of (time-averaged flux, interface
+//     value W(dt_f), compression factor) with respect to (W_L, dW_L, W_R, dW_R,
+//     dt_f), computed exactly with dual numbers (boundary faces differentiate
+//     through the ghost state);
+//   * per (cell, component) the 10 x 30 Jacobian of the HWENO coefficients with
+//     respect to the own averages, the own compression factor and the neighbours'
+//     averages and gradients of that component;
+//   * per cell the derivative of the local time step with respect to its state.
+// A vector-Jacobian product is then a chain of coalesced transposed products and
+// deterministic cell gathers (no atomics): record cotangents per face -> Gauss-
+// point cotangents -> polynomial coefficients -> reconstruction inputs -> cells.
+//
+// Coarse operator (Sec. 4.2): first-order KFVS residual on an agglomerated level;
+// its face Jacobians are recomputed on the fly with dual numbers (cheap).
+//
+// Fixed point: one V-cycle U -> Phi(U) at fixed agglomeration (fine smoother with
+// local steps, fine residual at the smoothed state, restriction, delta-form coarse
+// sweeps with forcing, prolongation).  At a converged state every term that
+// multiplies a residual vanishes, and the transposed linearised cycle is
+//   X_1 = P_1^T lam_W, X_{l+1} = P_{l+1}^T X_l, Rs_L = (dt/V)_L X_L,
+//   t = R_{l+1}^T Rs_{l+1}, D_l = X_l + dK_l^T t, Rs_l = t + (dt/V)_l D_l,
+//   lam_r = R_1^T Rs_1, lam_1 = lam + dR^T lam_r,
+//   lam' = (lam_1,W, 0, 0) + dE^T((dt/V) lam_1,W, lam_1,G, lam_1,alpha) + dJ/dU,
+// iterated to a fixed point; P = injection prolongation, R = summing restriction.
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+#include "gks_device.hpp"
+#include "dual.hpp"
+#include "bc_device.hpp"
+#include "recon_ops.hpp"
+
+namespace cgks {
+
+constexpr int GP_IN = 41, GP_OUT = 11;
+constexpr int K_FACE = 4;   // tangent directions per pass of the Gauss-point Jacobian
+constexpr int K_RECON = 6;  // tangent directions per pass of the reconstruction Jacobian
+
+static inline dim3 B1(int64_t n, int bs = 256) { return dim3(blocks_for(n > 0 ? n : 1, bs)); }
+
+// ---------------------------------------------------------------- local time step derivative
+template <class T>
+__device__ inline T local_dt_t(int64_t i, int64_t F, double gam, double cfl, double mu, int viscous, const T w[5],
+                               const int32_t *cf_ptr, const int32_t *cf_face, const double *favec, const double *farea,
+                               double V)
+{
+    const T rho = w[0], ir = 1.0 / rho;
+    const T u = w[1] * ir, v = w[2] * ir, ww = w[3] * ir;
+    const T p = (gam - 1.0) * (w[4] - 0.5 * rho * (u * u + v * v + ww * ww));
+    const T cs = Fp<T>::sqrt_(gam * p * ir);
+    T sum = T(0.0);
+    for (int k = cf_ptr[i]; k < cf_ptr[i + 1]; ++k) {
+        const int f = cf_face[k] >> 1;
+        const double ax = favec[f], ay = favec[F + f], az = favec[2 * F + f];
+        const double S = farea[f];
+        const T un = abs_(u * ax + v * ay + ww * az) / sqrt(ax * ax + ay * ay + az * az);
+        const T lam = viscous ? un + cs + 2.0 * mu * S / (rho * V) : un + cs;
+        sum += lam * S;
+    }
+    return cfl * V / sum;
+}
+
+__global__ void k_dt_jac(int64_t N, int64_t F, double gam, double cfl, double mu, int viscous, const double *W,
+                         const int32_t *cf_ptr, const int32_t *cf_face, const double *favec, const double *farea,
+                         const double *vol, double *ddt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    Dual<5> w[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        w[c] = Dual<5>(W[c * N + i]);
+        w[c].d[c] = 1.0;
+    }
+    const Dual<5> dt = local_dt_t(i, F, gam, cfl, mu, viscous, w, cf_ptr, cf_face, favec, farea, vol[i]);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) ddt[c * N + i] = dt.d[c];
+}
+
+__global__ void k_dt_side(int64_t F, const int32_t *fl, const int32_t *fr, const double *dt, uint8_t *dtL)
+{
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const int L = fl[f], R = fr[f];
+    dtL[f] = (R < 0 || dt[L] <= dt[R]) ? 1 : 0;
+}
+
+// slot of the same face in the neighbour's slot list
+__global__ void k_rev_slots(int64_t N, int64_t Fi, const int32_t *cf_ptr, const int32_t *cf_face, const int32_t *fl,
+                            const int32_t *fr, int8_t *rev)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int b = cf_ptr[i], e = cf_ptr[i + 1];
+    for (int s = 0; s < 6; ++s) {
+        int8_t r = -1;
+        if (b + s < e) {
+            const int it = cf_face[b + s];
+            const int f = it >> 1;
+            if (fr[f] >= 0) {
+                const int o = (it & 1) ? fl[f] : fr[f];
+                for (int k = cf_ptr[o]; k < cf_ptr[o + 1]; ++k)
+                    if ((cf_face[k] >> 1) == f && (cf_face[k] & 1) != (it & 1)) r = (int8_t)(k - cf_ptr[o]);
+            }
+        }
+        rev[s * N + i] = r;
+    }
+}
+
+// ---------------------------------------------------------------- Gauss-point outputs
+struct GpArgs {
+    int64_t N, F, NS;
+    GksCfg cfg;
+    const double *coef, *dt, *cen, *gpx, *gpw, *gpn, *fshift;
+    const uint8_t *dtL;
+    const int32_t *fl, *fr, *ftag, *fngp;
+    const BcTable *bc;
+    double *Jf, *agp;
+    int32_t *bad;
+};
+
+// Outputs of one Gauss point in the global frame: time-averaged flux (5), interface value
+// W(dt_f) (5), compression factor (1); the same arithmetic as the face kernel.
+template <class T>
+__device__ inline bool gp_outputs(const GpArgs &A, int f, int R, const double n[3], const T WL[5], const T GL[15],
+                                  const T WRi[5], const T GRi[15], const T &dtf, T out[GP_OUT])
+{
+    T WR[5], GR[15];
+    if (R >= 0) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) WR[q] = WRi[q];
+#pragma unroll
+        for (int q = 0; q < 15; ++q) GR[q] = GRi[q];
+    } else {
+        const int tag = A.ftag[f];
+        ghost_state(*A.bc, tag, n, WL, A.cfg.gamma, WR);
+        ghost_grad(*A.bc, tag, n, GL, GR);
+    }
+    double t1[3], t2[3];
+    onb(n, t1, t2);
+    T wl[5], wr[5], gl[3][5], gr[3][5];
+    to_local(WL, GL, n, t1, t2, wl, gl);
+    to_local(WR, GR, n, t1, t2, wr, gr);
+    GksMoments<T> mo;
+    if (!gks_moments<T>(wl, gl, wr, gr, T(A.cfg.gamma), T(A.cfg.K), mo, true)) return false;
+    T tau, taun;
+    collision_times(mo, dtf, A.cfg, tau, taun);
+    T Fl[5], Fg[5];
+    flux_integrated(mo, dtf, tau, taun, A.cfg, Fl);
+    to_global(Fl, n, t1, t2, Fg);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[q] = Fg[q] / dtf;
+    T Wt[5], Wg[5];
+    value_at(mo, dtf, tau, taun, Wt);
+    to_global(Wt, n, t1, t2, Wg);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[5 + q] = Wg[q];
+    out[10] = R >= 0 ? cf_factor(wl, wr, mo.pl, mo.pr, T(A.cfg.gamma)) : T(1.0);
+    return true;
+}
+
+__device__ inline void eval_cell(const double *coef, int64_t cell, const double dx[3], double w[5], double g[15])
+{
+    const double *cc = coef + cell * 50;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        double r[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) r[k] = cc[10 * c + k];
+        poly_eval(r, dx, w[c], &g[3 * c]);
+    }
+}
+
+// One lane per Gauss-point slot; pass p differentiates along inputs [pK, pK + K).
+template <int K> __global__ __launch_bounds__(64) void k_face_jac(GpArgs A, int pass)
+{
+    const int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = gp >> 2;
+    const int k = (int)(gp & 3);
+    if (f >= A.F || k >= A.fngp[f]) return;
+    const int64_t F = A.F, N = A.N, NS = A.NS;
+    const int L = A.fl[f], R = A.fr[f];
+    const double x[3] = {A.gpx[(3 * k) * F + f], A.gpx[(3 * k + 1) * F + f], A.gpx[(3 * k + 2) * F + f]};
+    const double n[3] = {A.gpn[(3 * k) * F + f], A.gpn[(3 * k + 1) * F + f], A.gpn[(3 * k + 2) * F + f]};
+    const double dtv = A.dtL[f] ? A.dt[L] : A.dt[R];
+    double v[GP_IN];
+    {
+        const double dx[3] = {x[0] - A.cen[L], x[1] - A.cen[N + L], x[2] - A.cen[2 * N + L]};
+        eval_cell(A.coef, L, dx, v, v + 5);
+    }
+    if (R >= 0) {
+        const double dx[3] = {x[0] - A.fshift[f] - A.cen[R], x[1] - A.fshift[F + f] - A.cen[N + R],
+                              x[2] - A.fshift[2 * F + f] - A.cen[2 * N + R]};
+        eval_cell(A.coef, R, dx, v + 20, v + 25);
+    } else {
+#pragma unroll
+        for (int q = 20; q < 40; ++q) v[q] = 0.0;
+    }
+    v[40] = dtv;
+    using D = Dual<K>;
+    D in[GP_IN];
+#pragma unroll
+    for (int q = 0; q < GP_IN; ++q) {
+        in[q] = D(v[q]);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (q == pass * K + j) in[q].d[j] = 1.0;
+    }
+    D out[GP_OUT];
+    const bool ok = gp_outputs(A, (int)f, R, n, in, in + 5, in + 20, in + 25, in[40], out);
+    if (!ok) atomicMin(A.bad, L);
+#pragma unroll
+    for (int o = 0; o < GP_OUT; ++o)
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int q = pass * K + j;
+            if (q < GP_IN) A.Jf[(int64_t)(o * GP_IN + q) * NS + gp] = ok ? out[o].d[j] : 0.0;
+        }
+    if (pass == 0) A.agp[gp] = ok ? out[10].v : 1.0;
+}
+
+// ---------------------------------------------------------------- face VJP
+struct FvArgs {
+    int64_t N, F, NS;
+    const double *cen, *gpx, *gpw, *gpn, *fshift, *Jf, *agp, *brec;
+    const int32_t *fl, *fr, *fngp;
+    double *bface;  // [F][101]: coefficient cotangents of L (50) and R (50), face step (1)
+};
+
+__device__ __forceinline__ double sum4(double v)
+{
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    return v;
+}
+
+// cotangent of R(x) = sum_k r_k phi_k(dx) from cotangents of its value (bw) and gradient (bg)
+__device__ __forceinline__ void poly_vjp(const double dx[3], double bw, const double bg[3], double b[10])
+{
+    const double x = dx[0], y = dx[1], z = dx[2];
+    b[0] += bw;
+    b[1] += bw * x + bg[0];
+    b[2] += bw * y + bg[1];
+    b[3] += bw * z + bg[2];
+    b[4] += bw * x * x + 2.0 * x * bg[0];
+    b[5] += bw * y * y + 2.0 * y * bg[1];
+    b[6] += bw * z * z + 2.0 * z * bg[2];
+    b[7] += bw * x * y + y * bg[0] + x * bg[1];
+    b[8] += bw * y * z + z * bg[1] + y * bg[2];
+    b[9] += bw * x * z + z * bg[0] + x * bg[2];
+}
+
+__global__ __launch_bounds__(256) void k_face_vjp(FvArgs A)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = gid >> 2;
+    const int k = (int)(gid & 3);
+    if (f >= A.F) return;  // whole groups of four leave together
+    const int64_t F = A.F, N = A.N, NS = A.NS;
+    const bool act = k < A.fngp[f];
+    const int L = A.fl[f], R = A.fr[f];
+    const double *br = A.brec + f * 21;
+    const double a = act ? A.agp[gid] : 1.0;
+    const double others = __shfl_xor(a, 1, 64) * __shfl_xor(a, 2, 64) * __shfl_xor(a, 3, 64);
+    double bl[50], bq[50], bdt = 0.0;
+#pragma unroll
+    for (int j = 0; j < 50; ++j) bl[j] = bq[j] = 0.0;
+    if (act) {
+        const double wS = A.gpw[k * F + f];
+        const double x[3] = {A.gpx[(3 * k) * F + f], A.gpx[(3 * k + 1) * F + f], A.gpx[(3 * k + 2) * F + f]};
+        const double n[3] = {A.gpn[(3 * k) * F + f], A.gpn[(3 * k + 1) * F + f], A.gpn[(3 * k + 2) * F + f]};
+        double bo[GP_OUT];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            bo[q] = wS * br[q];
+            bo[5 + q] = wS * (n[0] * br[5 + 3 * q] + n[1] * br[6 + 3 * q] + n[2] * br[7 + 3 * q]);
+        }
+        bo[10] = br[20] * others;
+        double bi[GP_IN];
+#pragma unroll
+        for (int q = 0; q < GP_IN; ++q) {
+            double s = 0.0;
+#pragma unroll
+            for (int o = 0; o < GP_OUT; ++o) s += A.Jf[(int64_t)(o * GP_IN + q) * NS + gid] * bo[o];
+            bi[q] = s;
+        }
+        {
+            const double dx[3] = {x[0] - A.cen[L], x[1] - A.cen[N + L], x[2] - A.cen[2 * N + L]};
+#pragma unroll
+            for (int c = 0; c < 5; ++c) poly_vjp(dx, bi[c], bi + 5 + 3 * c, bl + 10 * c);
+        }
+        if (R >= 0) {
+            const double dx[3] = {x[0] - A.fshift[f] - A.cen[R], x[1] - A.fshift[F + f] - A.cen[N + R],
+                                  x[2] - A.fshift[2 * F + f] - A.cen[2 * N + R]};
+#pragma unroll
+            for (int c = 0; c < 5; ++c) poly_vjp(dx, bi[20 + c], bi + 25 + 3 * c, bq + 10 * c);
+        }
+        bdt = bi[40];
+    }
+    double *o = A.bface + f * 101;
+#pragma unroll
+    for (int j = 0; j < 50; ++j) {
+        const double sl = sum4(bl[j]);
+        const double sr = sum4(bq[j]);
+        if (k == 0) {
+            o[j] = sl;
+            o[50 + j] = sr;
+        }
+    }
+    bdt = sum4(bdt);
+    if (k == 0) o[100] = bdt;
+}
+
+// per cell: coefficient cotangents and time-step cotangent from its faces, CSR order
+__global__ __launch_bounds__(256) void k_coef_gather(int64_t N, const int32_t *cf_ptr, const int32_t *cf_face,
+                                                     const int32_t *fr, const uint8_t *dtL, const double *bface,
+                                                     double *bcoef, double *bdt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double b[50];
+#pragma unroll
+    for (int j = 0; j < 50; ++j) b[j] = 0.0;
+    double t = 0.0;
+    for (int k = cf_ptr[i]; k < cf_ptr[i + 1]; ++k) {
+        const int it = cf_face[k];
+        const int f = it >> 1;
+        const bool isR = it & 1;
+        const double *o = bface + (int64_t)f * 101 + (isR ? 50 : 0);
+#pragma unroll
+        for (int j = 0; j < 50; ++j) b[j] += o[j];
+        const bool fromL = fr[f] < 0 || dtL[f];
+        if (isR != fromL) t += bface[(int64_t)f * 101 + 100];
+    }
+#pragma unroll
+    for (int j = 0; j < 50; ++j) bcoef[i * 50 + j] = b[j];
+    bdt[i] = t;
+}
+
+// ---------------------------------------------------------------- reconstruction Jacobian and VJP
+template <int K, int C> __device__ __forceinline__ void recon_jac_comp(const ReconArgs &A, int64_t i, int pass, double *Jr)
+{
+    const int64_t N = A.N;
+    using D = Dual<K>;
+    double v[RECON_IN];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[c] = A.W[c * N + i];
+    v[5] = A.alpha ? A.alpha[i] : 1.0;
+    for (int s = 0; s < 6; ++s) {
+        const int nbv = A.slot_nb[s * N + i];
+        const bool in = nbv >= 0;
+        v[6 + 4 * s] = in ? A.W[C * N + nbv] : 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) v[7 + 4 * s + d] = in ? A.G[(3 * C + d) * N + nbv] : 0.0;
+    }
+    D x[RECON_IN];
+#pragma unroll
+    for (int q = 0; q < RECON_IN; ++q) {
+        x[q] = D(v[q]);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (q == pass * K + j) x[q].d[j] = 1.0;
+    }
+    D nbw[6], nbg[6][3];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        nbw[s] = x[6 + 4 * s];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) nbg[s][d] = x[7 + 4 * s + d];
+    }
+    D r[10];
+    recon_generic<D, C>(A, i, x, x[5], nbw, nbg, r);
+#pragma unroll
+    for (int o = 0; o < 10; ++o)
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int q = pass * K + j;
+            if (q < RECON_IN) Jr[(int64_t)(o * RECON_IN + q) * 5 * N + C * N + i] = r[o].d[j];
+        }
+}
+
+template <int K> __global__ __launch_bounds__(320) void k_recon_jac(ReconArgs A, int pass, double *Jr)
+{
+    const int64_t i = (int64_t)blockIdx.x * OP_GROUP + (threadIdx.x & (OP_GROUP - 1));
+    if (i >= A.N) return;
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+    case 0: recon_jac_comp<K, 0>(A, i, pass, Jr); break;
+    case 1: recon_jac_comp<K, 1>(A, i, pass, Jr); break;
+    case 2: recon_jac_comp<K, 2>(A, i, pass, Jr); break;
+    case 3: recon_jac_comp<K, 3>(A, i, pass, Jr); break;
+    default: recon_jac_comp<K, 4>(A, i, pass, Jr); break;
+    }
+}
+
+// per (component, cell): input cotangents = Jr^T (coefficient cotangents)
+__global__ __launch_bounds__(256) void k_recon_vjp(int64_t N, const double *Jr, const double *bcoef, double *bown,
+                                                   double *bslot)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 5 * N) return;
+    const int C = (int)(t / N);
+    const int64_t i = t - C * N;
+    double br[10];
+#pragma unroll
+    for (int o = 0; o < 10; ++o) br[o] = bcoef[i * 50 + 10 * C + o];
+#pragma unroll
+    for (int q = 0; q < RECON_IN; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int o = 0; o < 10; ++o) s += Jr[(int64_t)(o * RECON_IN + q) * 5 * N + t] * br[o];
+        if (q < 6) bown[(C * 6 + q) * N + i] = s;
+        else bslot[((int64_t)(C * 6 + (q - 6) / 4) * 4 + (q - 6) % 4) * N + i] = s;
+    }
+}
+
+// per cell: state, gradient and compression-factor cotangents from the own and the
+// neighbours' reconstructions and from the local time step
+__global__ __launch_bounds__(256) void k_recon_gather(int64_t N, const int32_t *slot_nb, const int8_t *rev,
+                                                      const double *bown, const double *bslot, const double *bdt,
+                                                      const double *ddt, double *oW, double *oG, double *oA, int acc)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    double bw[5], bg[15], ba = 0.0;
+    const double t = bdt[j];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int C = 0; C < 5; ++C) s += bown[(C * 6 + c) * N + j];
+        bw[c] = s + t * ddt[c * N + j];
+    }
+#pragma unroll
+    for (int C = 0; C < 5; ++C) ba += bown[(C * 6 + 5) * N + j];
+#pragma unroll
+    for (int q = 0; q < 15; ++q) bg[q] = 0.0;
+    for (int s = 0; s < 6; ++s) {
+        const int nbv = slot_nb[s * N + j];
+        if (nbv == INT32_MIN) break;
+        if (nbv < 0) continue;
+        const int rs = rev[s * N + j];
+        if (rs < 0) continue;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const double *b = bslot + ((int64_t)(c * 6 + rs) * 4) * N + nbv;
+            bw[c] += b[0];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) bg[3 * c + d] += b[(1 + d) * N];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) oW[c * N + j] = acc ? oW[c * N + j] + bw[c] : bw[c];
+    if (oG)
+#pragma unroll
+        for (int q = 0; q < 15; ++q) oG[q * N + j] = acc ? oG[q * N + j] + bg[q] : bg[q];
+    if (oA) oA[j] = acc ? oA[j] + ba : ba;
+}
+
+// ---------------------------------------------------------------- operator outputs -> face records
+__global__ void k_bat(int64_t N, const double *bG, const double *bA, const double *Sgv, double *bat)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double s = bA ? bA[i] : 0.0;
+    if (bG)
+#pragma unroll
+        for (int q = 0; q < 15; ++q) s += bG[q * N + i] * Sgv[q * N + i];
+    bat[i] = s;
+}
+
+// R_i = -sum s rec_flux, G_new,i = alpha_i / V_i sum s rec_val, alpha_i = prod rec_cf (s = +1 left, -1 right)
+__global__ void k_brec(int64_t N, int64_t F, const int32_t *fl, const int32_t *fr, const double *vol,
+                       const double *Anew, const double *rec, const double *bR, const double *bG, const double *bat,
+                       double *brec)
+{
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const int L = fl[f], R = fr[f];
+    double *o = brec + f * 21;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) o[q] = (bR ? -bR[q * N + L] + (R >= 0 ? bR[q * N + R] : 0.0) : 0.0);
+    if (bG) {
+        const double hl = Anew[L] / vol[L], hr = R >= 0 ? Anew[R] / vol[R] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 15; ++q) o[5 + q] = hl * bG[q * N + L] - (R >= 0 ? hr * bG[q * N + R] : 0.0);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 15; ++q) o[5 + q] = 0.0;
+    }
+    o[20] = (bat && R >= 0) ? (bat[L] * Anew[L] + bat[R] * Anew[R]) / rec[f * 21 + 20] : 0.0;
+}
+
+// objective e . (force on the boundary faces with tag)
+__global__ void k_brec_wall(int64_t F, const int32_t *fr, const int32_t *ftag, int32_t tag, double e0, double e1,
+                            double e2, double *brec)
+{
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    double *o = brec + f * 21;
+    const bool on = fr[f] < 0 && ftag[f] == tag;
+#pragma unroll
+    for (int q = 0; q < 21; ++q) o[q] = 0.0;
+    if (on) {
+        o[1] = e0;
+        o[2] = e1;
+        o[3] = e2;
+    }
+}
+
+// ---------------------------------------------------------------- coarse KFVS VJP
+struct KvArgs {
+    int64_t n, m, nb;
+    double gam, K;
+    const double *W, *bR, *A, *bA;
+    const int32_t *pa, *pb, *bown, *btag;
+    const BcTable *bc;
+    double *kb;  // [m + nb][10]
+};
+
+__global__ __launch_bounds__(128) void k_kfvs_vjp_face(KvArgs A)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = A.m + A.nb;
+    if (j >= tot) return;
+    using D = Dual<10>;
+    double av[3];
+    int a, b = -1;
+    if (j < A.m) {
+        for (int d = 0; d < 3; ++d) av[d] = A.A[d * A.m + j];
+        a = A.pa[j];
+        b = A.pb[j];
+    } else {
+        for (int d = 0; d < 3; ++d) av[d] = A.bA[d * A.nb + (j - A.m)];
+        a = A.bown[j - A.m];
+    }
+    double *o = A.kb + j * 10;
+    const double S = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
+    if (S == 0.0) {
+#pragma unroll
+        for (int q = 0; q < 10; ++q) o[q] = 0.0;
+        return;
+    }
+    double bff[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) bff[q] = -A.bR[q * A.n + a] + (b >= 0 ? A.bR[q * A.n + b] : 0.0);
+    const double n[3] = {av[0] / S, av[1] / S, av[2] / S};
+    D wa[5], wb[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        wa[q] = D(A.W[q * A.n + a]);
+        wa[q].d[q] = 1.0;
+        if (b >= 0) {
+            wb[q] = D(A.W[q * A.n + b]);
+            wb[q].d[5 + q] = 1.0;
+        }
+    }
+    if (b < 0) ghost_state(*A.bc, A.btag[j - A.m], n, wa, A.gam, wb);
+    double t1[3], t2[3];
+    onb(n, t1, t2);
+    D la[5], lb[5];
+    la[0] = wa[0];
+    la[1] = wa[1] * n[0] + wa[2] * n[1] + wa[3] * n[2];
+    la[2] = wa[1] * t1[0] + wa[2] * t1[1] + wa[3] * t1[2];
+    la[3] = wa[1] * t2[0] + wa[2] * t2[1] + wa[3] * t2[2];
+    la[4] = wa[4];
+    lb[0] = wb[0];
+    lb[1] = wb[1] * n[0] + wb[2] * n[1] + wb[3] * n[2];
+    lb[2] = wb[1] * t1[0] + wb[2] * t1[1] + wb[3] * t1[2];
+    lb[3] = wb[1] * t2[0] + wb[2] * t2[1] + wb[3] * t2[2];
+    lb[4] = wb[4];
+    D Fl[5];
+    kfvs_local(la, lb, D(A.gam), D(A.K), Fl);
+    D ff[5];
+    ff[0] = S * Fl[0];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ff[1 + d] = S * (Fl[1] * n[d] + Fl[2] * t1[d] + Fl[3] * t2[d]);
+    ff[4] = S * Fl[4];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < 5; ++p) s += ff[p].d[q] * bff[p];
+        o[q] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_kfvs_vjp_gather(int64_t n, int64_t m, const int32_t *ptr, const int32_t *item,
+                                                         const double *kb, double *oW, int acc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double r[5] = {0, 0, 0, 0, 0};
+    for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+        const int it = item[k];
+        const double *o = it >= 0 ? kb + (int64_t)(it >> 1) * 10 + ((it & 1) ? 5 : 0) : kb + (m + (-it - 1)) * 10;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) r[q] += o[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) oW[q * n + i] = acc ? oW[q * n + i] + r[q] : r[q];
+}
+
+// ---------------------------------------------------------------- transfers and vector helpers
+// transpose of the summing restriction: fine cell takes its coarse value
+__global__ void k_restrict_t(int64_t nf, int64_t nc, const int32_t *f2c, const double *bc, double *bf)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    const int k = f2c[i];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) bf[q * nf + i] = bc[q * nc + k];
+}
+
+// transpose of the injection prolongation: coarse cell sums its fine members (ascending order)
+__global__ void k_prolong_t(int64_t nc, int64_t nf, const int32_t *ptr, const int32_t *idx, const double *bf, double *bc)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nc) return;
+    double s[5] = {0, 0, 0, 0, 0};
+    for (int q = ptr[k]; q < ptr[k + 1]; ++q) {
+        const int i = idx[q];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) s[c] += bf[c * nf + i];
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) bc[c * nc + k] = s[c];
+}
+
+// y = x * dt / V per cell (5 components); y may alias x
+__global__ void k_scale_dtv(int64_t n, const double *dt, const double *V, const double *x, double *y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double h = dt[i] / V[i];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) y[q * n + i] = h * x[q * n + i];
+}
+
+// y = a + b * dt / V (5 components)
+__global__ void k_add_scaled_dtv(int64_t n, const double *dt, const double *V, const double *a, const double *b,
+                                 double *y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double h = dt[i] / V[i];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) y[q * n + i] = a[q * n + i] + h * b[q * n + i];
+}
+
+__global__ void k_copy(int64_t n, const double *a, double *b)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+__global__ void k_axpy(int64_t n, double s, const double *a, double *b)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] += s * a[i];
+}
+
+__global__ void k_div(int64_t n, const double *a, const double *den, int64_t ncol, double *b)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n * ncol) b[t] = a[t] / den[t % n];
+}
+
+// deterministic partial sums of |a - b|^2 and |a|^2 (fixed tree per block)
+__global__ __launch_bounds__(256) void k_diff_part(int64_t n, const double *a, const double *b, double *part)
+{
+    __shared__ double s1[256], s2[256];
+    double x = 0.0, y = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double d = a[i] - b[i];
+        x += d * d;
+        y += a[i] * a[i];
+    }
+    s1[threadIdx.x] = x;
+    s2[threadIdx.x] = y;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+            s2[threadIdx.x] += s2[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s1[0];
+        part[2 * blockIdx.x + 1] = s2[0];
+    }
+}
+
+// ---------------------------------------------------------------- host side
+static AdjTape &tape(cgks_ctx *c)
+{
+    if (!c->adj || !c->adj->ready) throw Error{CGKS_E_STATE, "no linearisation: call cgks_linearize first"};
+    return *c->adj;
+}
+
+static ReconArgs recon_args(cgks_ctx *c, const double *W, const double *G, const double *al)
+{
+    ReconArgs A;
+    A.N = c->N;
+    A.F = c->F;
+    A.gam = c->prm.gamma;
+    A.weno_eps = c->prm.weno_eps;
+    A.g2 = c->prm.gamma_lin;
+    A.W = W;
+    A.G = G;
+    A.alpha = al;
+    A.vol = c->vol.p;
+    A.mom2 = c->mom2.p;
+    A.slot_av = c->slot_av.p;
+    A.op = c->op.p;
+    A.slot_nb = c->slot_nb.p;
+    A.ftag = c->ftag.p;
+    A.op_off = c->op_off.p;
+    A.bc = c->bc.p;
+    A.coef = nullptr;
+    return A;
+}
+
+void adj_linearize(cgks_ctx *c, const double *W, const double *G, const double *alpha)
+{
+    if (!c->adj) c->adj = new AdjTape();
+    AdjTape &T = *c->adj;
+    T.ready = false;
+    hipStream_t st = c->stream;
+    const int64_t N = c->N, F = c->F, NS = 4 * F;
+    T.W.ensure(5 * N);
+    T.G.ensure(15 * N);
+    T.al.ensure(N);
+    CGKS_HIP(hipMemcpyAsync(T.W.p, W, sizeof(double) * 5 * N, hipMemcpyDeviceToDevice, st));
+    CGKS_HIP(hipMemcpyAsync(T.G.p, G, sizeof(double) * 15 * N, hipMemcpyDeviceToDevice, st));
+    if (alpha) CGKS_HIP(hipMemcpyAsync(T.al.p, alpha, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    else launch_fill(T.al.p, 1.0, N, st);
+    // local steps and their derivatives
+    T.dt.ensure(N);
+    T.ddt.ensure(5 * N);
+    T.dtL.ensure(F);
+    launch_local_dt(c, T.W.p, T.dt.p);
+    hipLaunchKernelGGL(k_dt_jac, B1(N), dim3(256), 0, st, N, F, c->prm.gamma, c->prm.cfl, c->prm.mu, c->prm.viscous,
+                       T.W.p, c->cf_ptr.p, c->cf_face.p, c->favec.p, c->farea.p, c->vol.p, T.ddt.p);
+    hipLaunchKernelGGL(k_dt_side, B1(F), dim3(256), 0, st, F, c->fl.p, c->fr.p, T.dt.p, T.dtL.p);
+    // primal pass: coefficients, face records, G_new, alpha_new
+    T.coef.ensure(50 * N);
+    launch_recon(c, T.W.p, T.G.p, T.al.p, T.coef.p);
+    launch_face(c, MODE_RES, T.coef.p, T.dt.p, -1.0, false);
+    T.rec.ensure(21 * F);
+    CGKS_HIP(hipMemcpyAsync(T.rec.p, c->fout.p, sizeof(double) * 21 * F, hipMemcpyDeviceToDevice, st));
+    T.Anew.ensure(N);
+    T.Sgv.ensure(15 * N);
+    c->Rw.ensure(5 * N);
+    launch_gather_res(c, c->Rw.p, T.Sgv.p, T.Anew.p, MODE_RES);
+    hipLaunchKernelGGL(k_div, B1(15 * N), dim3(256), 0, st, N, T.Sgv.p, T.Anew.p, (int64_t)15, T.Sgv.p);
+    // Gauss-point Jacobians
+    T.Jf.ensure((size_t)GP_OUT * GP_IN * NS);
+    T.agp.ensure(NS);
+    GpArgs A;
+    A.N = N;
+    A.F = F;
+    A.NS = NS;
+    A.cfg = cfg_of(c);
+    A.coef = T.coef.p;
+    A.dt = T.dt.p;
+    A.cen = c->cen.p;
+    A.gpx = c->gpx.p;
+    A.gpw = c->gpw.p;
+    A.gpn = c->gpn.p;
+    A.fshift = c->fshift.p;
+    A.dtL = T.dtL.p;
+    A.fl = c->fl.p;
+    A.fr = c->fr.p;
+    A.ftag = c->ftag.p;
+    A.fngp = c->fngp.p;
+    A.bc = c->bc.p;
+    A.Jf = T.Jf.p;
+    A.agp = T.agp.p;
+    A.bad = c->bad.p;
+    for (int p = 0; p * K_FACE < GP_IN; ++p)
+        hipLaunchKernelGGL(k_face_jac<K_FACE>, B1(NS, 64), dim3(64), 0, st, A, p);
+    // reconstruction Jacobians
+    T.Jr.ensure((size_t)10 * RECON_IN * 5 * N);
+    const ReconArgs RA = recon_args(c, T.W.p, T.G.p, T.al.p);
+    for (int p = 0; p * K_RECON < RECON_IN; ++p)
+        hipLaunchKernelGGL(k_recon_jac<K_RECON>, dim3(blocks_for(N, OP_GROUP)), dim3(5 * OP_GROUP), 0, st, RA, p,
+                           T.Jr.p);
+    T.rev.ensure(6 * N);
+    hipLaunchKernelGGL(k_rev_slots, B1(N), dim3(256), 0, st, N, c->Fi, c->cf_ptr.p, c->cf_face.p, c->fl.p, c->fr.p,
+                       T.rev.p);
+    // work buffers
+    T.brec.ensure(21 * F);
+    T.bface.ensure(101 * F);
+    T.bcoef.ensure(50 * N);
+    T.bdt.ensure(N);
+    T.bown.ensure(30 * N);
+    T.bslot.ensure(120 * N);
+    T.bat.ensure(N);
+    // coarse states at the linearisation point: restricted fine state, level by level
+    const int nl = (int)c->lev.size();
+    while ((int)T.cW.size() < nl) {
+        T.cW.push_back(new DBuf<double>());
+        T.cdt.push_back(new DBuf<double>());
+        T.cD.push_back(new DBuf<double>());
+        T.cRs.push_back(new DBuf<double>());
+        T.cX.push_back(new DBuf<double>());
+    }
+    for (int l = 1; l < nl; ++l) {
+        Level *Lv = c->lev[l];
+        T.cW[l]->ensure(5 * Lv->n);
+        T.cdt[l]->ensure(Lv->n);
+        restrict_level(c, l, l == 1 ? T.W.p : T.cW[l - 1]->p, nullptr, T.cW[l]->p, nullptr);
+        coarse_dt_level(c, l, T.cW[l]->p, T.cdt[l]->p);
+    }
+    CGKS_HIP(hipGetLastError());
+    int32_t hb = 0;
+    CGKS_HIP(hipMemcpyAsync(&hb, c->bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    CGKS_HIP(hipStreamSynchronize(st));
+    if (hb != INT32_MAX) {
+        const int32_t big = INT32_MAX;
+        CGKS_HIP(hipMemcpy(c->bad.p, &big, sizeof(int32_t), hipMemcpyHostToDevice));
+        throw Error{CGKS_E_PHYS, "non-physical Gauss-point state while linearising, cell " + std::to_string(hb)};
+    }
+    T.ready = true;
+}
+
+// face-record cotangents in T.brec -> state cotangents
+static void vjp_from_records(cgks_ctx *c, double *oW, double *oG, double *oA, bool acc)
+{
+    AdjTape &T = tape(c);
+    hipStream_t st = c->stream;
+    const int64_t N = c->N, F = c->F;
+    FvArgs A;
+    A.N = N;
+    A.F = F;
+    A.NS = 4 * F;
+    A.cen = c->cen.p;
+    A.gpx = c->gpx.p;
+    A.gpw = c->gpw.p;
+    A.gpn = c->gpn.p;
+    A.fshift = c->fshift.p;
+    A.Jf = T.Jf.p;
+    A.agp = T.agp.p;
+    A.brec = T.brec.p;
+    A.fl = c->fl.p;
+    A.fr = c->fr.p;
+    A.fngp = c->fngp.p;
+    A.bface = T.bface.p;
+    hipLaunchKernelGGL(k_face_vjp, B1(4 * F), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_coef_gather, B1(N), dim3(256), 0, st, N, c->cf_ptr.p, c->cf_face.p, c->fr.p, T.dtL.p,
+                       T.bface.p, T.bcoef.p, T.bdt.p);
+    hipLaunchKernelGGL(k_recon_vjp, B1(5 * N), dim3(256), 0, st, N, T.Jr.p, T.bcoef.p, T.bown.p, T.bslot.p);
+    hipLaunchKernelGGL(k_recon_gather, B1(N), dim3(256), 0, st, N, c->slot_nb.p, T.rev.p, T.bown.p, T.bslot.p,
+                       T.bdt.p, T.ddt.p, oW, oG, oA, acc ? 1 : 0);
+}
+
+void adj_vjp_residual(cgks_ctx *c, const double *bR, const double *bG, const double *bA, double *oW, double *oG,
+                      double *oA, bool acc)
+{
+    AdjTape &T = tape(c);
+    hipStream_t st = c->stream;
+    const int64_t N = c->N, F = c->F;
+    const bool full = bG || bA;
+    if (full) hipLaunchKernelGGL(k_bat, B1(N), dim3(256), 0, st, N, bG, bA, T.Sgv.p, T.bat.p);
+    hipLaunchKernelGGL(k_brec, B1(F), dim3(256), 0, st, N, F, c->fl.p, c->fr.p, c->vol.p, T.Anew.p, T.rec.p, bR, bG,
+                       full ? T.bat.p : nullptr, T.brec.p);
+    vjp_from_records(c, oW, oG, oA, acc);
+}
+
+void adj_vjp_wall(cgks_ctx *c, int32_t tag, const double e[3], double *oW, double *oG, double *oA, bool acc)
+{
+    AdjTape &T = tape(c);
+    hipLaunchKernelGGL(k_brec_wall, B1(c->F), dim3(256), 0, c->stream, c->F, c->fr.p, c->ftag.p, tag, e[0], e[1], e[2],
+                       T.brec.p);
+    vjp_from_records(c, oW, oG, oA, acc);
+}
+
+void adj_vjp_kfvs(cgks_ctx *c, int level, const double *Wc, const double *bR, double *oW, bool acc)
+{
+    if (level < 1 || level >= (int)c->lev.size()) throw Error{CGKS_E_STATE, "no such level: call cgks_agglomerate"};
+    Level *L = c->lev[level];
+    if (!c->adj) c->adj = new AdjTape();
+    AdjTape &T = *c->adj;
+    const int64_t tot = L->m + L->nb;
+    T.bface.ensure(10 * tot + 10);  // shares the face-cotangent buffer
+    KvArgs A;
+    A.n = L->n;
+    A.m = L->m;
+    A.nb = L->nb;
+    A.gam = c->prm.gamma;
+    A.K = (5.0 - 3.0 * c->prm.gamma) / (c->prm.gamma - 1.0);
+    A.W = Wc;
+    A.bR = bR;
+    A.A = L->A.p;
+    A.bA = L->bA.p;
+    A.pa = L->pa.p;
+    A.pb = L->pb.p;
+    A.bown = L->bown.p;
+    A.btag = L->btag.p;
+    A.bc = c->bc.p;
+    A.kb = T.bface.p;
+    hipLaunchKernelGGL(k_kfvs_vjp_face, B1(tot, 128), dim3(128), 0, c->stream, A);
+    hipLaunchKernelGGL(k_kfvs_vjp_gather, B1(L->n), dim3(256), 0, c->stream, L->n, L->m, L->cf_ptr.p, L->cf_item.p,
+                       T.bface.p, oW, acc ? 1 : 0);
+}
+
+int adj_solve(cgks_ctx *c, int32_t tag, const double e[3], int max_iter, double tol, double *lamW, double *lamG,
+              double *lamA, double *cR, double *cG, double *cA, double *hist)
+{
+    AdjTape &T = tape(c);
+    const cgks_params &p = c->prm;
+    if (p.precision != 0) throw Error{CGKS_E_STATE, "the adjoint runs in FP64 (precision 0)"};
+    const int nl = (int)c->lev.size();
+    if (std::max(1, p.nu_pre[0]) != 1) throw Error{CGKS_E_STATE, "the adjoint supports one fine pre-sweep"};
+    for (int l = 0; l < std::max(nl, 1); ++l)
+        if (p.nu_post[l] != 0 || (l > 0 && p.nu_pre[l] != 1))
+            throw Error{CGKS_E_STATE, "the adjoint supports one pre-sweep and no post-sweeps per level"};
+    hipStream_t st = c->stream;
+    const int64_t N = c->N, n21 = 21 * N;
+    T.lam.ensure(n21);
+    T.lam1.ensure(n21);
+    T.tmp.ensure(n21);
+    T.jv.ensure(n21);
+    T.bR.ensure(5 * N);
+    T.cR.ensure(5 * N);
+    const int nbk = 512;
+    T.part.ensure(2 * nbk);
+    for (int l = 1; l < nl; ++l) {
+        const int64_t n = c->lev[l]->n;
+        T.cD[l]->ensure(5 * n);
+        T.cRs[l]->ensure(5 * n);
+        T.cX[l]->ensure(5 * n);
+    }
+    // dJ/dU, layout (W 5N, G 15N, alpha N)
+    double *jW = T.jv.p, *jG = jW + 5 * N, *jA = jG + 15 * N;
+    adj_vjp_wall(c, tag, e, jW, jG, jA, false);
+    hipLaunchKernelGGL(k_copy, B1(n21), dim3(256), 0, st, n21, T.jv.p, T.lam.p);
+    double *lW = T.lam.p;
+    double *l1W = T.lam1.p, *l1G = l1W + 5 * N, *l1A = l1G + 15 * N;
+    double *nW = T.tmp.p, *nG = nW + 5 * N, *nA = nG + 15 * N;
+    std::vector<double> hp(2 * nbk);
+    int it = 0;
+    for (; it < max_iter; ++it) {
+        // coarse chain: lam_r = R_1^T Rs_1
+        if (nl > 1) {
+            Level *L1 = c->lev[1];
+            hipLaunchKernelGGL(k_prolong_t, B1(L1->n), dim3(256), 0, st, L1->n, L1->nfine, L1->c2f_ptr.p,
+                               L1->c2f_idx.p, lW, T.cX[1]->p);
+            for (int l = 1; l + 1 < nl; ++l) {
+                Level *Lc = c->lev[l + 1];
+                hipLaunchKernelGGL(k_prolong_t, B1(Lc->n), dim3(256), 0, st, Lc->n, Lc->nfine, Lc->c2f_ptr.p,
+                                   Lc->c2f_idx.p, T.cX[l]->p, T.cX[l + 1]->p);
+            }
+            {
+                Level *Lt = c->lev[nl - 1];
+                hipLaunchKernelGGL(k_scale_dtv, B1(Lt->n), dim3(256), 0, st, Lt->n, T.cdt[nl - 1]->p, Lt->V.p,
+                                   T.cX[nl - 1]->p, T.cRs[nl - 1]->p);
+            }
+            for (int l = nl - 2; l >= 1; --l) {
+                Level *Lv = c->lev[l], *Lc = c->lev[l + 1];
+                double *t = T.cD[l]->p;  // t = R_{l+1}^T Rs_{l+1}, then D_l
+                hipLaunchKernelGGL(k_restrict_t, B1(Lv->n), dim3(256), 0, st, Lv->n, Lc->n, Lc->f2c.p, T.cRs[l + 1]->p,
+                                   T.cRs[l]->p);
+                hipLaunchKernelGGL(k_copy, B1(5 * Lv->n), dim3(256), 0, st, 5 * Lv->n, T.cX[l]->p, t);
+                adj_vjp_kfvs(c, l, T.cW[l]->p, T.cRs[l]->p, t, true);
+                hipLaunchKernelGGL(k_add_scaled_dtv, B1(Lv->n), dim3(256), 0, st, Lv->n, T.cdt[l]->p, Lv->V.p,
+                                   T.cRs[l]->p, t, T.cRs[l]->p);
+            }
+            hipLaunchKernelGGL(k_restrict_t, B1(N), dim3(256), 0, st, N, L1->n, L1->f2c.p, T.cRs[1]->p, T.bR.p);
+        } else {
+            launch_fill(T.bR.p, 0.0, 5 * N, st);
+        }
+        // lam_1 = lam + dR^T lam_r
+        hipLaunchKernelGGL(k_copy, B1(n21), dim3(256), 0, st, n21, T.lam.p, T.lam1.p);
+        adj_vjp_residual(c, T.bR.p, nullptr, nullptr, l1W, l1G, l1A, true);
+        // parameter cotangents: c_R = lam_r + (dt/V) lam_1,W; c_G = lam_1,G; c_alpha = lam_1,alpha
+        hipLaunchKernelGGL(k_add_scaled_dtv, B1(N), dim3(256), 0, st, N, T.dt.p, c->vol.p, T.bR.p, l1W, T.cR.p);
+        hipLaunchKernelGGL(k_scale_dtv, B1(N), dim3(256), 0, st, N, T.dt.p, c->vol.p, l1W, T.bR.p);
+        // lam' = (lam_1,W, 0, 0) + dE^T((dt/V) lam_1,W, lam_1,G, lam_1,alpha) + dJ/dU
+        hipLaunchKernelGGL(k_copy, B1(n21), dim3(256), 0, st, n21, T.jv.p, T.tmp.p);
+        hipLaunchKernelGGL(k_axpy, B1(5 * N), dim3(256), 0, st, 5 * N, 1.0, l1W, nW);
+        adj_vjp_residual(c, T.bR.p, l1G, l1A, nW, nG, nA, true);
+        // convergence: |lam' - lam| / |lam'|
+        hipLaunchKernelGGL(k_diff_part, dim3(nbk), dim3(256), 0, st, n21, T.tmp.p, T.lam.p, T.part.p);
+        CGKS_HIP(hipMemcpyAsync(hp.data(), T.part.p, sizeof(double) * 2 * nbk, hipMemcpyDeviceToHost, st));
+        std::swap(T.lam.p, T.tmp.p);
+        lW = T.lam.p;
+        nW = T.tmp.p;
+        nG = nW + 5 * N;
+        nA = nG + 15 * N;
+        CGKS_HIP(hipStreamSynchronize(st));
+        double d2 = 0.0, a2 = 0.0;
+        for (int b = 0; b < nbk; ++b) {
+            d2 += hp[2 * b];
+            a2 += hp[2 * b + 1];
+        }
+        const double rel = a2 > 0.0 ? std::sqrt(d2 / a2) : 0.0;
+        if (!std::isfinite(rel)) throw Error{CGKS_E_NONFINITE, "adjoint iteration produced a non-finite value"};
+        if (hist) hist[it] = rel;
+        if (rel <= tol) {
+            ++it;
+            break;
+        }
+    }
+    // outputs
+    const double *fW = T.lam.p;
+    if (lamW) CGKS_HIP(hipMemcpyAsync(lamW, fW, sizeof(double) * 5 * N, hipMemcpyDeviceToDevice, st));
+    if (lamG) CGKS_HIP(hipMemcpyAsync(lamG, fW + 5 * N, sizeof(double) * 15 * N, hipMemcpyDeviceToDevice, st));
+    if (lamA) CGKS_HIP(hipMemcpyAsync(lamA, fW + 20 * N, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    if (cR) CGKS_HIP(hipMemcpyAsync(cR, T.cR.p, sizeof(double) * 5 * N, hipMemcpyDeviceToDevice, st));
+    if (cG) CGKS_HIP(hipMemcpyAsync(cG, l1G, sizeof(double) * 15 * N, hipMemcpyDeviceToDevice, st));
+    if (cA) CGKS_HIP(hipMemcpyAsync(cA, l1A, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    CGKS_HIP(hipStreamSynchronize(st));
+    return it;
+}
+
+}  // namespace cgks

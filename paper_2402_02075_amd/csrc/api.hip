@@ -14,6 +14,7 @@ cgks_ctx::~cgks_ctx()
     lev.clear();
     if (pinned) (void)hipHostFree(pinned);
     if (pinned_i) (void)hipHostFree(pinned_i);
+    delete adj;
 }
 
 #define API_BEGIN(ctx)                                     \
@@ -138,6 +139,7 @@ const char *cgks_last_error(const cgks_ctx *c) { return c ? c->err.c_str() : "nu
 cgks_status cgks_set_params(cgks_ctx *c, const cgks_params *p)
 {
     API_BEGIN(c)
+    if (c->adj) c->adj->ready = false;  // the linearisation no longer matches
     if (!p) throw Error{CGKS_E_ARG, "null params"};
     check_params(p);
     c->prm = *p;
@@ -156,6 +158,7 @@ cgks_status cgks_set_mesh(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64
                           const int64_t *bnode, const int32_t *btag, const int64_t *node_canon)
 {
     API_BEGIN(c)
+    if (c->adj) c->adj->ready = false;  // the linearisation no longer matches
     if (!xyz || !ctype || !cnode_ptr || !cnode || (n_bfaces > 0 && (!bnode_ptr || !bnode || !btag)) || n_bfaces < 0)
         throw Error{CGKS_E_ARG, "null mesh array"};
     for (Level *l : c->lev) delete l;
@@ -168,6 +171,7 @@ cgks_status cgks_set_mesh(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64
 cgks_status cgks_set_bc(cgks_ctx *c, int32_t tag, int32_t kind, const double *prim)
 {
     API_BEGIN(c)
+    if (c->adj) c->adj->ready = false;  // the linearisation no longer matches
     if (tag < 1 || tag > 63) throw Error{CGKS_E_ARG, "tag must be in 1..63"};
     if (kind != CGKS_BC_SLIP && kind != CGKS_BC_NOSLIP_ADIABATIC && kind != CGKS_BC_FARFIELD)
         throw Error{CGKS_E_ARG, "unknown boundary kind"};
@@ -256,6 +260,60 @@ cgks_status cgks_wall_force(cgks_ctx *c, const double *W, const double *G, const
     API_END(c)
 }
 
+cgks_status cgks_linearize(cgks_ctx *c, const double *W, const double *G, const double *alpha)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    if (!W || !G) throw Error{CGKS_E_ARG, "W and G required"};
+    adj_linearize(c, W, G, alpha);
+    API_END(c)
+}
+
+cgks_status cgks_vjp_residual(cgks_ctx *c, const double *barR, const double *barGnew, const double *barAnew,
+                              double *barW, double *barG, double *barAlpha)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    if (!barR || !barW || !barG) throw Error{CGKS_E_ARG, "barR, barW and barG required"};
+    adj_vjp_residual(c, barR, barGnew, barAnew, barW, barG, barAlpha, false);
+    CGKS_HIP(hipGetLastError());
+    API_END(c)
+}
+
+cgks_status cgks_vjp_wall_force(cgks_ctx *c, int32_t tag, const double *e, double *barW, double *barG,
+                                double *barAlpha)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    if (!e || !barW || !barG) throw Error{CGKS_E_ARG, "e, barW and barG required"};
+    if (tag < 1 || tag > 63) throw Error{CGKS_E_ARG, "tag must be in 1..63"};
+    adj_vjp_wall(c, tag, e, barW, barG, barAlpha, false);
+    CGKS_HIP(hipGetLastError());
+    API_END(c)
+}
+
+cgks_status cgks_vjp_kfvs(cgks_ctx *c, int32_t level, const double *Wc, const double *barRc, double *barWc)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    if (!Wc || !barRc || !barWc) throw Error{CGKS_E_ARG, "null pointer"};
+    adj_vjp_kfvs(c, level, Wc, barRc, barWc, false);
+    CGKS_HIP(hipGetLastError());
+    API_END(c)
+}
+
+cgks_status cgks_adjoint_solve(cgks_ctx *c, int32_t tag, const double *e, int32_t max_iter, double tol,
+                               double *lamW, double *lamG, double *lamA, double *cR, double *cG, double *cA,
+                               double *hist, int32_t *n_done)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    if (!e || !n_done || max_iter < 1) throw Error{CGKS_E_ARG, "e, n_done and max_iter >= 1 required"};
+    if (tag < 1 || tag > 63) throw Error{CGKS_E_ARG, "tag must be in 1..63"};
+    *n_done = adj_solve(c, tag, e, max_iter, tol, lamW, lamG, lamA, cR, cG, cA, hist);
+    API_END(c)
+}
+
 cgks_status cgks_step(cgks_ctx *c, double *W, double *G, double *alpha, double dt_global, double *resnorm)
 {
     API_BEGIN(c)
@@ -317,6 +375,7 @@ cgks_status cgks_agglomerate_graph(cgks_ctx *c, int64_t n, const double *V, cons
 cgks_status cgks_agglomerate(cgks_ctx *c)
 {
     API_BEGIN(c)
+    if (c->adj) c->adj->ready = false;  // the linearisation no longer matches
     need_mesh(c);
     build_hierarchy(c);
     API_END(c)

@@ -612,23 +612,6 @@ template <class T> struct CoarseArgs {
     T *fflux;  // [5][m + nb], S n . F
 };
 
-template <class T> __device__ __forceinline__ void kfvs_local(const T wl[5], const T wr[5], T gam, T K, T F[5])
-{
-    const Side<T> sl = side_of(wl, gam), sr = side_of(wr, gam);
-    Tab<T> t;
-    T q[5];
-    tab_vw(t, sl, K);
-    tab_u_half(t, sl, T(1));
-    mpsi<1, 0, 0>(t, q);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) F[c] = sl.rho * q[c];
-    tab_vw(t, sr, K);
-    tab_u_half(t, sr, T(-1));
-    mpsi<1, 0, 0>(t, q);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) F[c] += sr.rho * q[c];
-}
-
 template <class T> __global__ __launch_bounds__(256) void k_kfvs_face(CoarseArgs<T> A)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -859,6 +842,8 @@ template <class T> static void coarse_dt_impl(cgks_ctx *c, int level, const T *W
     hipLaunchKernelGGL((k_coarse_dt<T>), G1(L->n), dim3(256), 0, c->stream, L->n, L->m, L->nb, c->prm.gamma, c->prm.cfl,
                        c->prm.mu, c->prm.viscous, W, L->cf_ptr.p, L->cf_item.p, L->S.p, L->A.p, L->bA.p, L->V.p, dt);
 }
+
+void coarse_dt_level(cgks_ctx *c, int level, const double *W, double *dt) { coarse_dt_impl<double>(c, level, W, dt); }
 
 static const double *finer_vol(cgks_ctx *c, int level)
 {

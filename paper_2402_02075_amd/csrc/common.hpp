@@ -88,6 +88,38 @@ struct Level {
     DBuf<float> W0f, Wf, Df, Rf, Ff, Rsf, dtf, ffluxf;
 };
 
+// Linearisation of the fine operator at one state, kept for repeated
+// vector-Jacobian products (the discrete adjoint).  Sizes: NS = 4F Gauss-point
+// slots, N cells, F faces.
+struct AdjTape {
+    bool ready = false;
+    DBuf<double> W, G, al;     // linearisation point (5N, 15N, N)
+    DBuf<double> dt, ddt;      // local step (N) and its derivative w.r.t. the own state (5N)
+    DBuf<uint8_t> dtL;         // [F] 1: the face step is the left cell's
+    DBuf<double> coef;         // cell-major polynomial coefficients (50N)
+    DBuf<double> rec;          // face records of the full mode (21F)
+    DBuf<double> Anew, Sgv;    // CF product per cell (N), sum w S W n / |Omega| (15N)
+    DBuf<double> agp;          // CF factor per Gauss-point slot (NS)
+    DBuf<double> Jf;           // [11*41][NS] Gauss-point Jacobians, output-major
+    DBuf<double> Jr;           // [10*30][5N] reconstruction Jacobians per (component, cell)
+    DBuf<int8_t> rev;          // [6][N] slot of the same face in the neighbour's list
+    // cotangent work buffers
+    DBuf<double> brec, bface, bcoef, bdt, bown, bslot, bat;
+    // coarse levels at the linearisation point (restricted states and steps), level l at index l
+    std::vector<DBuf<double> *> cW, cdt;
+    // adjoint iteration work
+    DBuf<double> lam, lam1, tmp, bR, jv, cR, cG, cA, part;
+    std::vector<DBuf<double> *> cD, cRs, cX;
+    ~AdjTape()
+    {
+        for (auto *b : cW) delete b;
+        for (auto *b : cdt) delete b;
+        for (auto *b : cD) delete b;
+        for (auto *b : cRs) delete b;
+        for (auto *b : cX) delete b;
+    }
+};
+
 }  // namespace cgks
 
 struct cgks_ctx {
@@ -127,6 +159,8 @@ struct cgks_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
+    // discrete-adjoint linearisation (allocated by cgks_linearize)
+    cgks::AdjTape *adj = nullptr;
     // host pinned scalar for per-cycle reads
     double *pinned = nullptr;
     int32_t *pinned_i = nullptr;
@@ -166,6 +200,18 @@ void kfvs_residual32(cgks_ctx *c, int level, const float *W, float *R);
 void restrict_level(cgks_ctx *c, int level, const double *Wf, const double *Rf, double *Wc, double *Rc);
 void prolong_level(cgks_ctx *c, int level, const double *dWc, double *Wf);
 void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flux, bool fp32_coarse);
+struct GksCfg;
+GksCfg cfg_of(const cgks_ctx *c);
+void coarse_dt_level(cgks_ctx *c, int level, const double *W, double *dt);
+
+// discrete adjoint
+void adj_linearize(cgks_ctx *c, const double *W, const double *G, const double *alpha);
+void adj_vjp_residual(cgks_ctx *c, const double *bR, const double *bG, const double *bA, double *oW, double *oG,
+                      double *oA, bool accumulate);
+void adj_vjp_wall(cgks_ctx *c, int32_t tag, const double e[3], double *oW, double *oG, double *oA, bool accumulate);
+void adj_vjp_kfvs(cgks_ctx *c, int level, const double *Wc, const double *bR, double *oW, bool accumulate);
+int adj_solve(cgks_ctx *c, int32_t tag, const double e[3], int max_iter, double tol, double *lamW, double *lamG,
+              double *lamA, double *cR, double *cG, double *cA, double *hist);
 
 inline int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 

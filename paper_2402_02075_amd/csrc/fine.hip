@@ -13,6 +13,7 @@
 #include "common.hpp"
 #include "gks_device.hpp"
 #include "bc_device.hpp"
+#include "recon_ops.hpp"
 
 namespace cgks {
 
@@ -42,23 +43,6 @@ __global__ void k_local_dt(int64_t N, int64_t F, double gam, double cfl, double 
 }
 
 // ---------------------------------------------------------------- reconstruction
-struct ReconArgs {
-    int64_t N, F;
-    double gam, weno_eps, g2;
-    const double *W, *G, *alpha, *vol, *mom2, *slot_av, *op;
-    const int32_t *slot_nb, *ftag;
-    const int64_t *op_off;
-    const BcTable *bc;
-    double *coef;
-};
-
-// Operator entries of one interior neighbour m of a cell, 39 per neighbour: 9 multiply the
-// average difference, 27 the neighbour gradient (row k, direction d at 9 + 3k + d), 3 the
-// linear least-squares gradient (36 + d).  Cells are interleaved in groups of 64, so entry
-// e of cell i sits at op_off[i] + 64 e and a wave reads each entry with one coalesced load.
-constexpr int OP_PER_NB = 39;
-constexpr int OP_GROUP = 64;
-
 // One thread per (cell, conservative component): the reconstruction acts on each
 // component separately, so a block holds 64 consecutive cells and five waves, one per
 // component, all reading the same operator entries.
@@ -530,7 +514,7 @@ __global__ void k_fill(double *p, double v, int64_t n)
 }
 
 // ---------------------------------------------------------------- launchers
-static GksCfg cfg_of(const cgks_ctx *c)
+GksCfg cfg_of(const cgks_ctx *c)
 {
     GksCfg g;
     g.gamma = c->prm.gamma;

@@ -41,6 +41,8 @@ CGKS_HD double abs_(double x) { return fabs(x); }
 CGKS_HD float abs_(float x) { return fabsf(x); }
 CGKS_HD double sign_(double x) { return copysign(1.0, x); }
 CGKS_HD float sign_(float x) { return copysignf(1.0f, x); }
+// x^e for a constant exponent
+CGKS_HD double powc_(double x, double e) { return ::pow(x, e); }
 
 // 1/sqrt(pi)
 #define CGKS_RSQRT_PI 0.56418958354775628694807945156077
@@ -397,6 +399,25 @@ template <class T> CGKS_HD void value_at(const GksMoments<T> &m, T t, T tau, T t
     combine(c, m.Vc, m.Vk, Wt);
 }
 
+// First-order kinetic flux vector splitting in the face frame (coarse levels, Sec. 4.2):
+// F = rho_l <u psi>_{u>0} + rho_r <u psi>_{u<0}.
+template <class T> CGKS_HD void kfvs_local(const T wl[5], const T wr[5], T gam, T K, T F[5])
+{
+    const Side<T> sl = side_of(wl, gam), sr = side_of(wr, gam);
+    Tab<T> t;
+    T q[5];
+    tab_vw(t, sl, K);
+    tab_u_half(t, sl, T(1));
+    mpsi<1, 0, 0>(t, q);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) F[c] = sl.rho * q[c];
+    tab_vw(t, sr, K);
+    tab_u_half(t, sr, T(-1));
+    mpsi<1, 0, 0>(t, q);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) F[c] += sr.rho * q[c];
+}
+
 // ---------------------------------------------------------------- frames
 // Orthonormal basis completing a unit normal (Duff et al. 2017, branchless).
 template <class T> CGKS_HD void onb(const T n[3], T t1[3], T t2[3])
@@ -425,15 +446,15 @@ template <class S> CGKS_HD void poly_eval(const S r[10], const S dx[3], S &w, S 
 }
 
 // conservative state and gradients G[3c+d] into the frame (n, t1, t2): wl[c'], gl[j][c']
-template <class S, class T>
-CGKS_HD void to_local(const S w[5], const S g[15], const S n[3], const S t1[3], const S t2[3], T wl[5], T gl[3][5])
+template <class S, class T, class Gm>
+CGKS_HD void to_local(const S w[5], const S g[15], const Gm n[3], const Gm t1[3], const Gm t2[3], T wl[5], T gl[3][5])
 {
     wl[0] = T(w[0]);
     wl[1] = T(w[1] * n[0] + w[2] * n[1] + w[3] * n[2]);
     wl[2] = T(w[1] * t1[0] + w[2] * t1[1] + w[3] * t1[2]);
     wl[3] = T(w[1] * t2[0] + w[2] * t2[1] + w[3] * t2[2]);
     wl[4] = T(w[4]);
-    const S *E[3] = {n, t1, t2};
+    const Gm *E[3] = {n, t1, t2};
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         S D[5];
@@ -447,8 +468,8 @@ CGKS_HD void to_local(const S w[5], const S g[15], const S n[3], const S t1[3], 
     }
 }
 
-template <class T, class S>
-CGKS_HD void to_global(const T l[5], const S n[3], const S t1[3], const S t2[3], S o[5])
+template <class T, class S, class Gm>
+CGKS_HD void to_global(const T l[5], const Gm n[3], const Gm t1[3], const Gm t2[3], S o[5])
 {
     o[0] = S(l[0]);
 #pragma unroll
