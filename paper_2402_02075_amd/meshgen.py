@@ -570,6 +570,34 @@ def random_smooth_state(centroids_hint: np.ndarray, seed=3, amp=0.05, gamma=1.4)
     return W
 
 
+def smooth_state_and_gradients(x: np.ndarray, seed=3, amp=0.05, gamma=1.4):
+    """The field of random_smooth_state at points x (N, 3) together with its exact
+    gradients: W (5, N) conserved values, G (15, N) with G[3c + d] = dW_c/dx_d."""
+    r = uniform01(seed, 64)
+    base = [1.0, 0.5, 0.1, -0.05, 1.0 / gamma]
+    val, grad = [], []
+    for c in range(5):
+        v = np.full(x.shape[0], base[c])
+        g = np.zeros((3, x.shape[0]))
+        for mth in range(3):
+            kv = (r[(c * 12 + mth * 4) % 64: (c * 12 + mth * 4) % 64 + 3] * 4.0 + 1.0)
+            ph = r[(c * 12 + mth * 4 + 3) % 64] * 2 * np.pi
+            v = v + amp * np.sin(x @ kv + ph) / (mth + 1)
+            g = g + amp * np.cos(x @ kv + ph)[None, :] * kv[:, None] / (mth + 1)
+        val.append(v)
+        grad.append(g)
+    rho, u, v, w, p = val
+    dr, du, dv, dw, dp = grad
+    W = np.stack([rho, rho * u, rho * v, rho * w, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)])
+    G = np.zeros((15, x.shape[0]))
+    G[0:3] = dr
+    G[3:6] = u * dr + rho * du
+    G[6:9] = v * dr + rho * dv
+    G[9:12] = w * dr + rho * dw
+    G[12:15] = dp / (gamma - 1.0) + 0.5 * (u * u + v * v + w * w) * dr + rho * (u * du + v * dv + w * dw)
+    return W, G
+
+
 def cell_node_mean(m: Mesh) -> np.ndarray:
     """Mean of each cell's node coordinates (a point inside the cell; used only to
     place analytic input fields, not a geometric quantity of the scheme)."""

@@ -1,0 +1,249 @@
+"""GPU checks of the discrete adjoint (vector-Jacobian products and the adjoint fixed point).
+
+* VJP of the fine operator E = (R, G_new, alpha_new) against central differences of
+  the library's own operator (dot-product test, Richardson-extrapolated) and
+  against central differences of the CPU oracle's operator at the same seeded state.
+* VJP of the coarse KFVS operator and of the wall force, likewise.
+* torch.autograd path through ResidualFunction.
+* Gradients of the lower-wall x-force with respect to the inflow Mach number and
+  the bump amplitude from the adjoint fixed point, against central differences of
+  the converged objective, on a small hexahedral bump channel that converges to
+  the round-off floor.
+Inputs come from the seeded generators; no expected value comes from the library.
+"""
+import numpy as np
+import pytest
+
+from paper_2402_02075_amd import meshgen as mg
+
+from gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def ad(torch):
+    from paper_2402_02075_amd import adjoint
+    return adjoint
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _smooth(torch, m, seed, amp=0.05):
+    """Smooth state with exact gradients; compression factors in [0.3, 0.6] keep the
+    scaled Green-Gauss indicator clearly below the least-squares one, away from the
+    kink of beta_1 = min(beta_GG, beta_LS) (for smooth data the two nearly coincide)."""
+    W, G = mg.smooth_state_and_gradients(mg.cell_node_mean(m), seed=seed, amp=amp)
+    al = np.random.default_rng(seed).uniform(0.3, 0.6, size=m.n_cells)
+    return _dev(torch, W), _dev(torch, G), _dev(torch, al)
+
+
+def _randn(torch, g, *shape):
+    return torch.randn(*shape, dtype=torch.float64, device="cuda", generator=g)
+
+
+def _ops_dot(S, W, G, al, w, v, h):
+    """w . (E(U + h v) - E(U - h v)) / 2h with the library operator."""
+    Ep = S.residual(W + h * v[0], G + h * v[1], al + h * v[2])
+    Em = S.residual(W - h * v[0], G - h * v[1], al - h * v[2])
+    return sum(float((wi * (a - b)).sum()) for wi, a, b in zip(w, Ep, Em)) / (2 * h)
+
+
+def _richardson(f, h):
+    return (4.0 * f(h / 2) - f(h)) / 3.0
+
+
+# The nonlinear weights vary on the scale of weno_eps = 1e-5 in the normalised indicators,
+# so central differences reach their asymptotic range only for steps of about 1e-7.
+H_FD = 2e-7
+
+
+MESHES = {
+    "hex": lambda: mg.bump_channel(24, 8, 4, n_prism=0, n_pyr=0),
+    "mixed": lambda: mg.bump_channel(16, 10, 4, n_prism=2, n_pyr=3, jitter=0.08, seed=5, amp=0.05),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_vjp_residual_dot(torch, ad, name):
+    m = MESHES[name]()
+    say(f"[gpu] adjoint vjp dot {name} cells={m.n_cells}")
+    S = ad.channel_solver(m, 0.5)
+    W, G, al = _smooth(torch, m, seed=11)
+    S.linearize(W, G, al)
+    N = m.n_cells
+    g = torch.Generator(device="cuda").manual_seed(2)
+    w = (_randn(torch, g, 5, N), _randn(torch, g, 15, N), _randn(torch, g, N))
+    v = (_randn(torch, g, 5, N) * W.abs().mean(1, keepdim=True), _randn(torch, g, 15, N) * 0.1,
+         _randn(torch, g, N) * 0.1)
+    bW, bG, bA = S.vjp_residual(*w)
+    lhs = float((bW * v[0]).sum() + (bG * v[1]).sum() + (bA * v[2]).sum())
+    rhs = _richardson(lambda h: _ops_dot(S, W, G, al, w, v, h), H_FD)
+    rel = abs(lhs - rhs) / abs(rhs)
+    say(f"    vjp {lhs:.12e} fd {rhs:.12e} rel {rel:.2e}")
+    assert rel < 1e-6
+
+
+def test_vjp_residual_vs_oracle(torch, ad, oracle):
+    """Directional derivative of the oracle's operator (central differences, CPU) against
+    the library's VJP at the same seeded state."""
+    m = mg.bump_channel(12, 6, 2, n_prism=2, n_pyr=2, jitter=0.08, seed=5, amp=0.05)
+    say(f"[gpu] adjoint vjp vs oracle cells={m.n_cells}")
+    S = ad.channel_solver(m, 0.5, agglomerate=False)
+    M = oracle.Mesh(m)
+    prim = np.array([1.0, 0.5, 0.0, 0.0, 1 / 1.4])
+    for tag in (mg.TAG_INLET, mg.TAG_OUTLET):
+        M.set_bc(tag, oracle.BC_FARFIELD, prim)
+    for tag in (mg.TAG_WALL_BOTTOM, mg.TAG_WALL_TOP, mg.TAG_WALL_SIDE):
+        M.set_bc(tag, oracle.BC_SLIP)
+    Wn, Gn = mg.smooth_state_and_gradients(mg.cell_node_mean(m), seed=13, amp=0.05)
+    aln = np.random.default_rng(13).uniform(0.3, 0.6, size=m.n_cells)
+    rng = np.random.default_rng(4)
+    N = m.n_cells
+    wn = (rng.normal(size=(5, N)), rng.normal(size=(15, N)), rng.normal(size=N))
+    vn = (rng.normal(size=(5, N)) * np.abs(Wn).mean(1, keepdims=True), rng.normal(size=(15, N)) * 0.1,
+          rng.normal(size=N) * 0.1)
+    par = oracle.params()
+
+    def ora(h):
+        Rp, Gp, Ap, _ = M.residual(par, Wn + h * vn[0], Gn + h * vn[1], aln + h * vn[2])
+        Rm, Gm, Am, _ = M.residual(par, Wn - h * vn[0], Gn - h * vn[1], aln - h * vn[2])
+        return sum(float((wi * (a - b)).sum()) for wi, a, b in zip(wn, (Rp, Gp, Ap), (Rm, Gm, Am))) / (2 * h)
+
+    rhs = _richardson(ora, H_FD)
+    S.linearize(_dev(torch, Wn), _dev(torch, Gn), _dev(torch, aln))
+    bW, bG, bA = S.vjp_residual(*(_dev(torch, a) for a in wn))
+    lhs = float((bW.cpu().numpy() * vn[0]).sum() + (bG.cpu().numpy() * vn[1]).sum() + (bA.cpu().numpy() * vn[2]).sum())
+    rel = abs(lhs - rhs) / abs(rhs)
+    say(f"    vjp {lhs:.12e} oracle fd {rhs:.12e} rel {rel:.2e}")
+    assert rel < 1e-6
+
+
+def test_vjp_kfvs_dot(torch, ad):
+    m = MESHES["mixed"]()
+    say(f"[gpu] adjoint kfvs vjp cells={m.n_cells}")
+    S = ad.channel_solver(m, 0.5)
+    W, G, al = _smooth(torch, m, seed=12)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    Wl = W
+    for lev in (1, 2):
+        Wl, _ = S.restrict(lev, Wl, torch.zeros_like(Wl))
+        n = Wl.shape[1]
+        w = _randn(torch, g, 5, n)
+        v = _randn(torch, g, 5, n) * Wl.abs().mean(1, keepdim=True)
+        lhs = float((S.vjp_kfvs(lev, Wl, w) * v).sum())
+        rhs = _richardson(lambda h: float((w * (S.kfvs_residual(lev, Wl + h * v) -
+                                                S.kfvs_residual(lev, Wl - h * v))).sum()) / (2 * h), 2e-4)
+        rel = abs(lhs - rhs) / abs(rhs)
+        say(f"    level {lev}: vjp {lhs:.12e} fd {rhs:.12e} rel {rel:.2e}")
+        assert rel < 1e-9
+
+
+def test_vjp_wall_force_dot(torch, ad):
+    m = MESHES["hex"]()
+    say(f"[gpu] adjoint wall-force vjp cells={m.n_cells}")
+    S = ad.channel_solver(m, 0.5, agglomerate=False)
+    W, G, al = _smooth(torch, m, seed=14)
+    S.linearize(W, G, al)
+    e = (1.0, -0.4, 0.2)
+    bW, bG, bA = S.vjp_wall_force(mg.TAG_WALL_BOTTOM, e)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    N = m.n_cells
+    v = (_randn(torch, g, 5, N) * W.abs().mean(1, keepdim=True), _randn(torch, g, 15, N) * 0.1,
+         _randn(torch, g, N) * 0.1)
+    ev = torch.tensor(e, dtype=torch.float64, device="cuda")
+
+    def fd(h):
+        Fp = S.wall_force(W + h * v[0], G + h * v[1], al + h * v[2], mg.TAG_WALL_BOTTOM)
+        Fm = S.wall_force(W - h * v[0], G - h * v[1], al - h * v[2], mg.TAG_WALL_BOTTOM)
+        return float(torch.dot(Fp - Fm, ev)) / (2 * h)
+
+    lhs = float((bW * v[0]).sum() + (bG * v[1]).sum() + (bA * v[2]).sum())
+    rhs = _richardson(fd, H_FD)
+    rel = abs(lhs - rhs) / abs(rhs)
+    say(f"    vjp {lhs:.12e} fd {rhs:.12e} rel {rel:.2e}")
+    assert rel < 1e-6
+
+
+def test_autograd_function(torch, ad):
+    m = MESHES["hex"]()
+    say(f"[gpu] adjoint autograd cells={m.n_cells}")
+    S = ad.channel_solver(m, 0.5, agglomerate=False)
+    W, G, al = _smooth(torch, m, seed=15)
+    N = m.n_cells
+    g = torch.Generator(device="cuda").manual_seed(6)
+    w = (_randn(torch, g, 5, N), _randn(torch, g, 15, N), _randn(torch, g, N))
+    Wr, Gr, ar = (t.clone().requires_grad_(True) for t in (W, G, al))
+    R, Gn, an = ad.residual(S, Wr, Gr, ar)
+    loss = (w[0] * R).sum() + (w[1] * Gn).sum() + (w[2] * an).sum()
+    loss.backward()
+    S.linearize(W, G, al)
+    bW, bG, bA = S.vjp_residual(*w)
+    assert torch.equal(Wr.grad, bW) and torch.equal(Gr.grad, bG) and torch.equal(ar.grad, bA)
+    # forward values are the plain residual
+    R0, G0, a0 = S.residual(W, G, al)
+    assert torch.equal(R.detach(), R0) and torch.equal(Gn.detach(), G0) and torch.equal(an.detach(), a0)
+
+
+def test_adjoint_state_errors(torch, ad):
+    from paper_2402_02075_amd import cgks as cg
+    m = MESHES["hex"]()
+    S = ad.channel_solver(m, 0.5)
+    W, G, al = _smooth(torch, m, seed=16)
+    N = m.n_cells
+    with pytest.raises(cg.CgksError):
+        S.vjp_residual(torch.zeros(5, N, dtype=torch.float64, device="cuda"))
+    S.linearize(W, G, al)
+    S.set_bc(mg.TAG_WALL_TOP, cg.BC_SLIP)  # any configuration change drops the linearisation
+    with pytest.raises(cg.CgksError):
+        S.vjp_residual(torch.zeros(5, N, dtype=torch.float64, device="cuda"))
+    S.linearize(W, G, al)
+    S.set_params(nu_post=[1, 0, 0, 0, 0, 0, 0, 0])
+    S.linearize(W, G, al)
+    with pytest.raises(cg.CgksError):
+        S.adjoint_solve(mg.TAG_WALL_BOTTOM, max_iter=2)
+
+
+def test_adjoint_gradients_vs_converged_fd(torch, ad):
+    """dJ/dMach and dJ/dA from the adjoint fixed point against central differences of the
+    objective at converged perturbed states (J = lower-wall x-force)."""
+
+    def mesh_fn(a):
+        return mg.bump_channel(24, 8, 4, n_prism=0, n_pyr=0, amp=a)
+
+    amp, mach = 0.05, 0.5
+    m = mesh_fn(amp)
+    say(f"[gpu] adjoint gradients cells={m.n_cells}")
+    S = ad.channel_solver(m, mach)
+    W, G, al, hist, _ = ad.converge(S, m, cycles=30000, tol=1e-14)
+    say(f"    primal {len(hist)} cycles drop {hist[-1] / hist[0]:.2e}")
+    assert hist[-1] / hist[0] < 1e-12
+    gr = ad.gradients(mesh_fn, amp, mach, W, G, al, max_iter=30000, tol=1e-12)
+    say(f"    adjoint {gr['adjoint_iterations']} iterations, last change {gr['adjoint_final_change']:.2e}")
+    h = 1e-5
+    fd = {}
+    for name, mf, mp in (("M", lambda s: mesh_fn(amp), lambda s: mach + s),
+                         ("A", lambda s: mesh_fn(amp + s), lambda s: mach)):
+        J = []
+        for sgn in (1.0, -1.0):
+            Sx = ad.channel_solver(mf(sgn * h), mp(sgn * h))
+            Wx, Gx, ax = W.clone(), G.clone(), al.clone()
+            hx, _ = Sx.vcycle(Wx, Gx, ax, 20000, 1e-12)
+            say(f"    {name} {sgn:+.0f}: {len(hx)} cycles, residual {hx[0]:.2e} -> {hx[-1]:.2e}")
+            assert hx[-1] < 3e-14
+            J.append(float(Sx.wall_force(Wx, Gx, ax, mg.TAG_WALL_BOTTOM)[0]))
+        fd[name] = (J[0] - J[1]) / (2 * h)
+    for name, key in (("M", "dJ_dMach"), ("A", "dJ_dA")):
+        rel = abs(gr[key] - fd[name]) / abs(fd[name])
+        say(f"    {key}: adjoint {gr[key]:.12e} fd {fd[name]:.12e} rel {rel:.2e}")
+        assert rel < 1e-6
