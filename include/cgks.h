@@ -135,7 +135,8 @@ cgks_status cgks_reconstruct(cgks_ctx *ctx, const double *W, const double *G, co
  *   G_new[15N]    = alpha_new / |Omega| * sum_p sum_k w_k W_pk(dt_f) n_pk S_p;
  *   alpha_new[N]  = product over interior-face Gauss points of 1/(1 + A^2).
  * Inputs W, G, alpha (alpha of the previous update, scales the Green-Gauss p^1).
- * G_new and alpha_new may be NULL (residual only).  All device.
+ * G_new and alpha_new may be NULL (residual only).  All device.  With precision 1 the
+ * Gauss-point flux is evaluated in FP32 (sums, update and outputs stay FP64).
  */
 cgks_status cgks_residual(cgks_ctx *ctx, const double *W, const double *G, const double *alpha, double *R,
                           double *G_new, double *alpha_new);
@@ -242,7 +243,8 @@ cgks_status cgks_agglomerate(cgks_ctx *ctx);
 /* Level map: f2c[n_{level-1}] (device int32) from level-1 cells to level cells; level >= 1. */
 cgks_status cgks_level_map(cgks_ctx *ctx, int32_t level, int32_t *f2c);
 
-/* Coarse KFVS residual on level >= 1 (paper Secs. 1, 4.2): R = - sum S n.F_kfvs. Device W, R (5 N_l). */
+/* Coarse KFVS residual on level >= 1 (paper Secs. 1, 4.2): R = - sum S n.F_kfvs. Device W, R (5 N_l),
+ * FP64; with precision 1 the operator is evaluated in FP32 (as on the coarse levels of the mixed cycle). */
 cgks_status cgks_kfvs_residual(cgks_ctx *ctx, int32_t level, const double *W, double *R);
 
 /* Restriction to level >= 1 (paper Sec. 4.2): Wc = sum V W / Vc, Rc = sum R (either pair nullable). */

@@ -240,7 +240,7 @@ cgks_status cgks_residual(cgks_ctx *c, const double *W, const double *G, const d
     launch_local_dt(c, W, c->dtc.p);
     launch_recon(c, W, G, alpha, c->coef.p);
     const int mode = G_new ? MODE_RES : MODE_RESONLY;
-    launch_face(c, mode, c->coef.p, c->dtc.p, -1.0, false);
+    launch_face(c, mode, c->coef.p, c->dtc.p, -1.0, c->prm.precision == 1);
     launch_gather_res(c, R, G_new, alpha_new, mode);
     CGKS_HIP(hipGetLastError());
     API_END(c)
@@ -403,7 +403,8 @@ cgks_status cgks_kfvs_residual(cgks_ctx *c, int32_t level, const double *W, doub
     need_mesh(c);
     level_at(c, level);
     if (!W || !R) throw Error{CGKS_E_ARG, "null pointer"};
-    kfvs_residual(c, level, W, R);
+    if (c->prm.precision == 1) kfvs_residual_fp32(c, level, W, R);
+    else kfvs_residual(c, level, W, R);
     CGKS_HIP(hipGetLastError());
     API_END(c)
 }

@@ -836,6 +836,24 @@ void kfvs_residual32(cgks_ctx *c, int level, const float *W, float *R)
     kfvs_impl<float>(c, level, W, R, L->ffluxf.p);
 }
 
+template <class A, class B> __global__ void k_convert(int64_t n, const A *__restrict__ a, B *__restrict__ b)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = B(a[i]);
+}
+
+// FP32 KFVS residual of an FP64 state, returned in FP64 (the mixed-precision coarse operator)
+void kfvs_residual_fp32(cgks_ctx *c, int level, const double *W, double *R)
+{
+    Level *L = level_of(c, level);
+    const int64_t n5 = 5 * L->n;
+    L->Wf.ensure(n5);
+    L->Rf.ensure(n5);
+    hipLaunchKernelGGL((k_convert<double, float>), G1(n5), dim3(256), 0, c->stream, n5, W, L->Wf.p);
+    kfvs_residual32(c, level, L->Wf.p, L->Rf.p);
+    hipLaunchKernelGGL((k_convert<float, double>), G1(n5), dim3(256), 0, c->stream, n5, L->Rf.p, R);
+}
+
 template <class T> static void coarse_dt_impl(cgks_ctx *c, int level, const T *W, T *dt)
 {
     Level *L = level_of(c, level);

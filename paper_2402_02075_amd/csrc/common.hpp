@@ -197,6 +197,7 @@ void agglomerate_graph(cgks_ctx *c, int64_t n, const double *V, const double *P,
 void build_hierarchy(cgks_ctx *c);
 void kfvs_residual(cgks_ctx *c, int level, const double *W, double *R);
 void kfvs_residual32(cgks_ctx *c, int level, const float *W, float *R);
+void kfvs_residual_fp32(cgks_ctx *c, int level, const double *W, double *R);
 void restrict_level(cgks_ctx *c, int level, const double *Wf, const double *Rf, double *Wc, double *Rc);
 void prolong_level(cgks_ctx *c, int level, const double *dWc, double *Wf);
 void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flux, bool fp32_coarse);

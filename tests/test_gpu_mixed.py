@@ -1,0 +1,112 @@
+"""Mixed precision: FP32 flux evaluation and FP32 coarse levels, errors against the FP64 oracle.
+
+* The fine residual with Gauss-point fluxes evaluated in FP32 (sums and outputs FP64)
+  against the FP64 oracle: the error is stated in units of the cell's flux scale.
+* The coarse KFVS operator in FP32 against the FP64 oracle, likewise.
+* The mixed V-cycle (FP32 coarse levels, transfers and flux until the switch, then FP64
+  flux) converges to the same discrete fixed point as the FP64 cycle: the coarse
+  correction is proportional to the fine residual (delta form), so its FP32 rounding
+  vanishes at convergence.
+"""
+import numpy as np
+import pytest
+
+from paper_2402_02075_amd import meshgen as mg
+
+from gpu_common import assert_residual_close, cell_surface, flux_scale, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def ad(torch):
+    from paper_2402_02075_amd import adjoint
+    return adjoint
+
+
+def _oracle_channel(oracle, m):
+    M = oracle.Mesh(m)
+    prim = np.array([1.0, 0.5, 0.0, 0.0, 1 / 1.4])
+    for tag in (mg.TAG_INLET, mg.TAG_OUTLET):
+        M.set_bc(tag, oracle.BC_FARFIELD, prim)
+    for tag in (mg.TAG_WALL_BOTTOM, mg.TAG_WALL_TOP, mg.TAG_WALL_SIDE):
+        M.set_bc(tag, oracle.BC_SLIP)
+    return M
+
+
+MESH = lambda: mg.bump_channel(16, 10, 4, n_prism=2, n_pyr=3, jitter=0.08, seed=5, amp=0.05)
+
+
+def test_fp32_flux_residual_error(oracle, torch, ad):
+    m = MESH()
+    say(f"[gpu] mixed fp32 flux residual cells={m.n_cells}")
+    S = ad.channel_solver(m, 0.5, agglomerate=False)
+    M = _oracle_channel(oracle, m)
+    W, G = mg.smooth_state_and_gradients(mg.cell_node_mean(m), seed=21, amp=0.05)
+    al = np.random.default_rng(21).uniform(0.6, 1.0, size=m.n_cells)
+    Ro, Go, ao, _ = M.residual(oracle.params(), W, G, al)
+    dev = [torch.from_numpy(a).cuda() for a in (W, G, al)]
+    S.set_params(precision=1)
+    R, Gn, an = (t.cpu().numpy() for t in S.residual(*dev))
+    S.set_params(precision=0)
+    R64 = S.residual(*dev)[0].cpu().numpy()
+    F = M.faces()
+    surf = cell_surface(F, m.n_cells)
+    fs = flux_scale(W)
+    ratio32 = assert_residual_close(R, Ro, surf, fs, tol=1e-5, what="R fp32")
+    ratio64 = assert_residual_close(R64, Ro, surf, fs, tol=1e-12, what="R fp64")
+    rel_alpha = float(np.abs(an - ao).max())
+    say(f"    FP32 flux: max |R - R_oracle| / (S_i F_c) = {ratio32 * 1e-5:.2e} (FP64 path: {ratio64 * 1e-12:.2e}); "
+        f"alpha max abs err {rel_alpha:.2e}")
+    assert rel_alpha < 1e-5
+
+
+def test_fp32_kfvs_error(oracle, torch, ad):
+    """Each side restricts the same seeded fine state with its own restriction (the
+    agglomerations are bit-identical), then the FP32 KFVS is compared with the FP64 oracle."""
+    m = MESH()
+    say(f"[gpu] mixed fp32 kfvs cells={m.n_cells}")
+    S = ad.channel_solver(m, 0.5)
+    M = _oracle_channel(oracle, m)
+    H = oracle.Hierarchy(M, levels=3, passes=3, seed=1)
+    W = mg.random_smooth_state(mg.cell_node_mean(m), seed=22, amp=0.05)
+    par = oracle.params()
+    Wl, Wo = torch.from_numpy(W).cuda(), W
+    for lev in (1, 2):
+        Wl, _ = S.restrict(lev, Wl, torch.zeros_like(Wl))
+        Wo, _ = H.restrict(lev, Wo, np.zeros_like(Wo))
+        Ro = H.kfvs_residual(par, lev, Wo)
+        S.set_params(precision=1)
+        R32 = S.kfvs_residual(lev, Wl).cpu().numpy()
+        S.set_params(precision=0)
+        R64 = S.kfvs_residual(lev, Wl).cpu().numpy()
+        den = np.abs(Ro).max(axis=1)
+        err32 = np.abs(R32 - Ro).max(axis=1) / den
+        err64 = np.abs(R64 - Ro).max(axis=1) / den
+        say(f"    level {lev}: max |R - R_oracle| / max |R_oracle| per component, FP32 "
+            + " ".join(f"{e:.2e}" for e in err32) + " | FP64 " + " ".join(f"{e:.2e}" for e in err64))
+        assert err32.max() < 1e-5
+        assert err64.max() < 1e-12
+
+
+def test_mixed_vcycle_reaches_fp64_fixed_point(torch, ad):
+    m = mg.bump_channel(24, 8, 4, n_prism=0, n_pyr=0)
+    say(f"[gpu] mixed vcycle fixed point cells={m.n_cells}")
+    out = {}
+    for prec in (0, 1):
+        S = ad.channel_solver(m, 0.5, precision=prec)
+        W, G, al, hist, ok = ad.converge(S, m, cycles=30000, tol=1e-12)
+        say(f"    precision {prec}: {len(hist)} cycles, drop {hist[-1] / hist[0]:.2e}")
+        assert ok
+        out[prec] = (W.cpu().numpy(), len(hist))
+    d = np.abs(out[1][0] - out[0][0]).max(axis=1) / np.abs(out[0][0]).max(axis=1)
+    say("    mixed vs FP64 converged state, max rel difference per component: " + " ".join(f"{x:.2e}" for x in d))
+    assert d.max() < 1e-9
