@@ -12,8 +12,10 @@ two coarse levels, prolongation and the residual-norm read.
 Reported `value`: fine CGKS residual evaluations per second over the timed
 steps (each V-cycle evaluates the fine residual twice).  Extra fields: the
 isolated cgks_residual rate, time and cycles to a 1e-10 residual drop in FP64
-and in mixed precision, the roofline of the face-flux kernel, and the CPU
-oracle on a bounded sample.
+and in mixed precision (on this mesh, which stalls, and on the same channel
+meshed with hexahedra only, which converges), the roofline of the face-flux
+kernel, adjoint timings on this state with a gradient check against converged
+finite differences on a small channel, and the CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -94,6 +96,108 @@ def cpu_baseline(mg, budget_s=15.0):
                       f"subset, {elapsed:.1f} s), scaled to whole-mesh evaluations"}
 
 
+def hex_convergence(cg, mg, max_cycles):
+    """Time to a 1e-10 drop, FP64 and mixed, on the same channel meshed with hexahedra only
+    (96 x 32 x 16 = 49,152 cells), where the scheme converges to round-off."""
+    import torch
+    m = mg.bump_channel(n_prism=0, n_pyr=0)
+    res = {"cells": m.n_cells, "mesh": "bump channel 96x32x16, hexahedra only"}
+    Wref = None
+    for prec, key in ((0, "fp64"), (1, "mixed")):
+        S = cg.Solver(precision=prec)
+        S.set_mesh(m)
+        prim = np.array([1.0, 0.5, 0.0, 0.0, 1.0 / 1.4])
+        for tag in (mg.TAG_INLET, mg.TAG_OUTLET):
+            S.set_bc(tag, cg.BC_FARFIELD, prim)
+        for tag in (mg.TAG_WALL_BOTTOM, mg.TAG_WALL_TOP, mg.TAG_WALL_SIDE):
+            S.set_bc(tag, cg.BC_SLIP)
+        S.agglomerate()
+        W0, G0 = mg.uniform_state(m.n_cells)
+        W = torch.from_numpy(W0).cuda()
+        G = torch.from_numpy(G0).cuda()
+        al = torch.ones(m.n_cells, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h, ok = S.vcycle(W, G, al, max_cycles, 1e-10)
+        torch.cuda.synchronize()
+        dt_c = time.perf_counter() - t0
+        res[key] = {"seconds": dt_c, "cycles": int(len(h)), "reached": bool(ok), "final_drop": float(h[-1] / h[0])}
+        F = S.wall_force(W, G, al, mg.TAG_WALL_BOTTOM).cpu().numpy()
+        res[key]["lower_wall_force"] = [float(x) for x in F]
+        if Wref is None:
+            Wref = W.clone()
+        else:
+            d = (W - Wref)[0].abs()
+            res["mixed_vs_fp64"] = {"density_max_abs_diff": float(d.max()),
+                                    "density_l2_diff": float(torch.sqrt((d * d).mean()))}
+        log(f"hex channel {key}: {len(h)} cycles {dt_c:.2f}s drop {h[-1] / h[0]:.3e}")
+    return res
+
+
+def adjoint_measurements(cg, mg, S, W, G, al):
+    """Linearisation and vector-Jacobian-product timings on the benchmark state, and the
+    adjoint gradients of the lower-wall x-force against converged finite differences on a
+    small all-hexahedral channel (768 cells)."""
+    import torch
+    from paper_2402_02075_amd import adjoint as ad
+    out = {}
+    N = W.shape[1]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.linearize(W, G, al)
+    torch.cuda.synchronize()
+    out["linearize_s"] = time.perf_counter() - t0
+    g = torch.Generator(device="cuda").manual_seed(1)
+    w = [torch.randn(*sh, dtype=torch.float64, device="cuda", generator=g) for sh in ((5, N), (15, N), (N,))]
+    S.vjp_residual(*w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        S.vjp_residual(*w)
+    torch.cuda.synchronize()
+    out["vjp_residual_ms"] = (time.perf_counter() - t0) / 20 * 1e3
+    t0 = time.perf_counter()
+    r = S.adjoint_solve(mg.TAG_WALL_BOTTOM, max_iter=20, tol=0.0)
+    out["adjoint_iteration_ms"] = (time.perf_counter() - t0) / max(r["iterations"], 1) * 1e3
+    out["tape_bytes"] = int(8 * (451 * 4 * S.n_faces + 1650 * N))
+
+    # gradient check on a channel that converges to round-off
+    def mesh_fn(a):
+        return mg.bump_channel(24, 8, 4, n_prism=0, n_pyr=0, amp=a)
+
+    amp, mach, h = 0.05, 0.5, 1e-5
+    m = mesh_fn(amp)
+    Sc = ad.channel_solver(m, mach)
+    t0 = time.perf_counter()
+    Wc, Gc, ac, hist, _ = ad.converge(Sc, m, cycles=30000, tol=1e-14)
+    t_primal = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    gr = ad.gradients(mesh_fn, amp, mach, Wc, Gc, ac, max_iter=30000, tol=1e-12)
+    t_adj = time.perf_counter() - t0
+    fd = {}
+    for name, mf, mp in (("Mach", lambda s_: mesh_fn(amp), lambda s_: mach + s_),
+                         ("A", lambda s_: mesh_fn(amp + s_), lambda s_: mach)):
+        J = []
+        for sgn in (1.0, -1.0):
+            Sx = ad.channel_solver(mf(sgn * h), mp(sgn * h))
+            Wx, Gx, ax = Wc.clone(), Gc.clone(), ac.clone()
+            Sx.vcycle(Wx, Gx, ax, 20000, 1e-12)
+            J.append(float(Sx.wall_force(Wx, Gx, ax, mg.TAG_WALL_BOTTOM)[0]))
+        fd[name] = (J[0] - J[1]) / (2 * h)
+    out["gradient_check"] = {
+        "workload": "bump channel 24x8x4 hexahedra (768 cells), Mach 0.5, J = lower-wall x-force",
+        "primal_cycles": int(len(hist)), "primal_drop": float(hist[-1] / hist[0]), "primal_s": t_primal,
+        "adjoint_iterations": int(gr["adjoint_iterations"]), "adjoint_s": t_adj,
+        "dJ_dMach": {"adjoint": gr["dJ_dMach"], "fd": fd["Mach"],
+                     "rel_err": abs(gr["dJ_dMach"] - fd["Mach"]) / abs(fd["Mach"])},
+        "dJ_dA": {"adjoint": gr["dJ_dA"], "fd": fd["A"], "rel_err": abs(gr["dJ_dA"] - fd["A"]) / abs(fd["A"])},
+        "fd_step": h}
+    log(f"adjoint: linearize {out['linearize_s']:.2f}s vjp {out['vjp_residual_ms']:.2f}ms "
+        f"iteration {out['adjoint_iteration_ms']:.2f}ms; gradient rel err "
+        f"{out['gradient_check']['dJ_dMach']['rel_err']:.2e} {out['gradient_check']['dJ_dA']['rel_err']:.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +205,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--develop", type=int, default=100, help="untimed V-cycles that develop the flow first")
     ap.add_argument("--converge", type=int, default=4000, help="max cycles for the time-to-1e-10 runs (0: skip)")
+    ap.add_argument("--converge-hex", type=int, default=60000,
+                    help="max cycles for the time-to-1e-10 runs on the all-hexahedral channel (0: skip)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timings and gradient check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true", help="run a plain 1 GiB copy first (counter scaling)")
     args = ap.parse_args()
@@ -196,6 +303,10 @@ def main():
                                         "density_l2_diff": float(torch.sqrt((d * d).mean()))}
             log(f"{key}: {len(h)} cycles {dt_c:.2f}s drop {h[-1] / h[0]:.3e}")
         S.set_params(precision=0)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_measurements(cg, mg, S, W, G, al)
+    if args.converge_hex:
+        out["time_to_1e-10_hex_channel"] = hex_convergence(cg, mg, args.converge_hex)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mg)
     print(json.dumps(out))
