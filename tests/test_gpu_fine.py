@@ -194,6 +194,42 @@ def test_s2o4_density_wave(oracle, cg, torch):
     np.testing.assert_allclose(tot, (W0 * vol).sum(1), rtol=0, atol=1e-13)
 
 
+def test_density_wave_100_steps_and_order(oracle, cg, torch):
+    """The periodic density-wave configuration: 8^3 hexahedra, 100 two-stage fourth-order steps at
+    CFL 0.5 (global step), against the exact translated solution; conservation over the run; then
+    the same final time on 16^3 and 32^3 (step T / ceil(T / dt_CFL)): observed L1 order near 3."""
+    par = oracle.params()
+    errs, T = [], None
+    for n in (8, 16, 32):
+        m = mg.periodic_hex_cube(n)
+        S = cg.Solver()
+        S.set_mesh(m)
+        W, G = mg.density_wave_averages(n)
+        vol = oracle.Mesh(m).cells()[0] if n == 8 else None
+        dt_cfl = float(S.local_dt(to_dev(torch, W)).min())
+        if T is None:
+            T, ns = 100 * dt_cfl, 100
+        else:
+            ns = int(np.ceil(T / dt_cfl))
+        Wd, Gd = to_dev(torch, W), to_dev(torch, G)
+        ad = torch.ones(m.n_cells, dtype=torch.float64, device="cuda")
+        for _ in range(ns):
+            S.step(Wd, Gd, ad, T / ns)
+        S.check()
+        We, _ = mg.density_wave_averages(n, T=T)
+        Wf = Wd.cpu().numpy()
+        errs.append(np.abs(Wf[0] - We[0]).mean())
+        say(f"[gpu] density wave n={n} steps={ns} T={T:.4f} L1(rho) error {errs[-1]:.3e}")
+        if n == 8:
+            tot0 = (W * vol).sum(1)
+            tot = (Wf * vol).sum(1)
+            np.testing.assert_allclose(tot, tot0, rtol=0, atol=1e-13 * ns)
+            assert errs[-1] < 5e-2
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    say(f"    observed orders {orders}")
+    assert orders[-1] > 2.6, errs
+
+
 def test_full_size_bump_sampled(oracle, cg, torch):
     """Bump channel at its full size (96x32x16 base, ~189k cells): sampled cells against the oracle."""
     m = mg.bump_channel()
@@ -209,6 +245,37 @@ def test_full_size_bump_sampled(oracle, cg, torch):
     surf = cell_surface(F, M.n_cells)
     assert_residual_close(R.cpu().numpy()[:, sub], oR[:, sub], surf[sub], flux_scale(W), what="R sampled")
     np.testing.assert_allclose(an.cpu().numpy()[sub], oan[sub], rtol=1e-10, atol=1e-14)
+
+
+@pytest.mark.parametrize("level,layers,prisms", [(5, 32, 12), (6, 33, 12)])
+def test_full_size_sphere_sampled(oracle, cg, torch, level, layers, prisms):
+    """Viscous sphere at its full sizes (1.47M and 6.14M cells: Mach 0.2, Re 100 on D, Pr 0.72,
+    adiabatic no-slip wall, Riemann far field at r = 20): sampled cells against the oracle,
+    FP64 and with the Gauss-point flux in FP32."""
+    m = mg.sphere_shell(level=level, n_layers=layers, n_prism=prisms)
+    say(f"[gpu] full-size sphere cells={m.n_cells}")
+    par = dict(viscous=1, mu=2e-3, prandtl=0.72)
+    prim = np.array([1.0, 0.2, 0.0, 0.0, 1.0 / 1.4])
+    bcs = [(mg.TAG_SPHERE, 2, None), (mg.TAG_FARFIELD, 3, prim)]
+    M, S = _pair(oracle, cg, m, bcs, **par)
+    W, G, alpha = _smooth_state(m, 52, amp=0.03, grad_amp=0.05)
+    Wd, Gd, ad_ = to_dev(torch, W), to_dev(torch, G), to_dev(torch, alpha)
+    R, Gn, an = S.residual(Wd, Gd, ad_)
+    S.check()
+    S.set_params(precision=1)
+    R32 = S.residual(Wd, Gd, ad_)[0]
+    S.set_params(precision=0)
+    rng = np.random.default_rng(1)
+    sub = np.unique(np.concatenate([rng.choice(m.n_cells, 40, replace=False), np.arange(12), [m.n_cells - 1]]))
+    opar = oracle.params(viscous=1, mu=2e-3, prandtl=0.72)
+    oR, oGn, oan, _ = M.residual(opar, W, G, alpha, sub=sub)
+    F = M.faces()
+    surf = cell_surface(F, M.n_cells)
+    fs = flux_scale(W)
+    assert_residual_close(R.cpu().numpy()[:, sub], oR[:, sub], surf[sub], fs, what="R sampled")
+    r32 = assert_residual_close(R32.cpu().numpy()[:, sub], oR[:, sub], surf[sub], fs, tol=1e-5, what="R fp32")
+    np.testing.assert_allclose(an.cpu().numpy()[sub], oan[sub], rtol=1e-10, atol=1e-14)
+    say(f"    FP32 flux sampled error {r32 * 1e-5:.2e} of the flux scale")
 
 
 @pytest.mark.parametrize("wall_kind", [1, 2])
