@@ -137,6 +137,8 @@ struct cgks_ctx {
     cgks::DBuf<double> vol, cen, mom2;  // [N], [3][N], [6][N]
     cgks::DBuf<int32_t> fl, fr, ftag;   // [F]
     cgks::DBuf<int32_t> fngp;           // [F] 3 or 4
+    cgks::DBuf<int32_t> lmap;           // [NL] face-kernel lane -> 4 face + Gauss point, -1 idle
+    int64_t NL = 0;                     // lanes of the face kernel (multiple of 256)
     cgks::DBuf<double> gpx, gpw, gpn;   // [4*3][F], [4][F] (w_k S), [4*3][F]
     cgks::DBuf<double> fshift, favec, farea, fmom;  // [3][F], [3][F], [F], [3][F]
     cgks::DBuf<int32_t> cf_ptr, cf_face;  // CSR cell -> 2*face + (cell is R)

@@ -170,7 +170,7 @@ struct FaceArgs {
     GksCfg cfg;
     double dt_global;
     const double *coef, *dtc, *cen, *gpx, *gpw, *gpn, *fshift;
-    const int32_t *fl, *fr, *ftag, *fngp;
+    const int32_t *fl, *fr, *ftag, *fngp, *lmap;
     const BcTable *bc;
     double *out;  // [F][nq], face-major
     int32_t *bad;
@@ -189,23 +189,31 @@ __device__ __forceinline__ void eval_poly(const double *__restrict__ coef, int64
     }
 }
 
-__device__ __forceinline__ double group4_sum(double v)
+// Sums (products) over the lanes of one face: the face's lanes are consecutive within the
+// wave, starting at its first Gauss point's lane; the result is valid on that lane.
+__device__ __forceinline__ double face_sum(double v, int ln, int ngp)
 {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    return v;
+    const double v1 = __shfl(v, ln + 1, 64), v2 = __shfl(v, ln + 2, 64), v3 = __shfl(v, ln + 3, 64);
+    return ((v + v1) + v2) + (ngp == 4 ? v3 : 0.0);
+}
+__device__ __forceinline__ double face_prod(double v, int ln, int ngp)
+{
+    const double v1 = __shfl(v, ln + 1, 64), v2 = __shfl(v, ln + 2, 64), v3 = __shfl(v, ln + 3, 64);
+    return ((v * v1) * v2) * (ngp == 4 ? v3 : 1.0);
 }
 
-// One lane per (face, Gauss point); four lanes per face, summed with lane shuffles.
+// One lane per face Gauss point, faces packed into waves with 3 or 4 lanes each (lane map
+// built at set-up), face sums by lane shuffles.
 template <class T, int MODE, bool VAL> __global__ __launch_bounds__(256) void k_face(FaceArgs A)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t f = gid >> 2;
-    const int k = (int)(gid & 3);
-    if (f >= A.F) return;  // whole groups of four leave together
+    const int ln = threadIdx.x & 63;
+    const int lm = A.lmap[gid];  // the grid covers the padded lane map exactly
+    const bool act = lm >= 0;
+    const int64_t f = act ? (lm >> 2) : 0;
+    const int k = lm & 3;
     const int64_t F = A.F, N = A.N;
-    const int ngp = A.fngp[f];
-    const bool act = k < ngp;
+    const int ngp = act ? A.fngp[f] : 0;
     const int L = A.fl[f], R = A.fr[f];
     constexpr int NQ = MODE == MODE_RES ? 21 : MODE == MODE_RESONLY ? 5 : MODE == MODE_S1 ? 41 : 26;
     double acc[NQ];
@@ -303,13 +311,10 @@ template <class T, int MODE, bool VAL> __global__ __launch_bounds__(256) void k_
         }
     }
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] = group4_sum(acc[q]);
-    if (MODE != MODE_RESONLY) {
-        alpha_k *= __shfl_xor(alpha_k, 1, 64);
-        alpha_k *= __shfl_xor(alpha_k, 2, 64);
-    }
+    for (int q = 0; q < NQ; ++q) acc[q] = face_sum(acc[q], ln, ngp);
+    if (MODE != MODE_RESONLY) alpha_k = face_prod(alpha_k, ln, ngp);
     // face-major record of NQ values (flux sums, interface-value sums, CF product last)
-    if (k == 0) {
+    if (act && k == 0) {
         double *o = A.out + f * NQ;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) o[q] = acc[q];
@@ -584,8 +589,9 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
     A.fngp = c->fngp.p;
     A.bc = c->bc.p;
     A.out = c->fout.p;
+    A.lmap = c->lmap.p;
     A.bad = c->bad.p;
-    const dim3 grid(blocks_for(4 * c->F, 256)), blk(256);
+    const dim3 grid(blocks_for(c->NL, 256)), blk(256);
     const bool prfix = c->prm.viscous && c->prm.prandtl != 1.0;  // heat-flux correction needs the value moments
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool timed = c->timing && mode == MODE_RES;

@@ -475,6 +475,8 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
     std::vector<int32_t> hfl(F), hfr(F), htag(F), fnode(4 * F), fshn(2 * F, -1);
     std::vector<int32_t> deg(N + 1, 0);
     int64_t ngp = 0;
+    std::vector<int32_t> lmap;  // face-kernel lanes: 4 f + k, or -1 for an idle lane
+    lmap.reserve(4 * F + 256);
     for (int64_t f = 0; f < F; ++f) {
         const FaceRec &r = faces[f];
         hfl[f] = r.L;
@@ -483,6 +485,10 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
         const int *lf = face_of(ctype[r.L], r.lfL);
         const int nn = lf[3] < 0 ? 3 : 4;
         ngp += nn;
+        // pack faces into 64-lane waves, nn lanes each, never splitting a face across waves
+        if ((int64_t)(lmap.size() % 64) + nn > 64)
+            while (lmap.size() % 64) lmap.push_back(-1);
+        for (int k = 0; k < nn; ++k) lmap.push_back((int32_t)(4 * f + k));
         for (int a = 0; a < 4; ++a) fnode[a * F + f] = a < nn ? (int32_t)cnode[cptr[r.L] + lf[a]] : -1;
         deg[r.L + 1]++;
         if (r.R >= 0) {
@@ -545,6 +551,9 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
     c->Fi = Fi;
     c->Fb = F - Fi;
     c->NGP = ngp;
+    while (lmap.size() % 256) lmap.push_back(-1);
+    c->NL = (int64_t)lmap.size();
+    c->lmap.upload(lmap, s);
     DBuf<double> dxyz;
     DBuf<int32_t> dhexn, dfnode, dfsh;
     dxyz.upload(xyz, 3 * n_nodes, s);
