@@ -139,6 +139,8 @@ struct cgks_ctx {
     cgks::DBuf<int32_t> fngp;           // [F] 3 or 4
     cgks::DBuf<int32_t> lmap;           // [NL] face-kernel lane -> 4 face + Gauss point, -1 idle
     int64_t NL = 0;                     // lanes of the face kernel (multiple of 256)
+    cgks::DBuf<int4> lidx;              // [NL] {4 f + k, L, R, 8 tag + ngp}, f = -1 idle
+    cgks::DBuf<double> lgeo;            // [10][NL] dx_L (3), dx_R (3), n (3), w S, lane-major
     cgks::DBuf<double> gpx, gpw, gpn;   // [4*3][F], [4][F] (w_k S), [4*3][F]
     cgks::DBuf<double> fshift, favec, farea, fmom;  // [3][F], [3][F], [F], [3][F]
     cgks::DBuf<int32_t> cf_ptr, cf_face;  // CSR cell -> 2*face + (cell is R)

@@ -169,8 +169,10 @@ struct FaceArgs {
     int64_t N, F;
     GksCfg cfg;
     double dt_global;
-    const double *coef, *dtc, *cen, *gpx, *gpw, *gpn, *fshift;
-    const int32_t *fl, *fr, *ftag, *fngp, *lmap;
+    const double *coef, *dtc;
+    const int4 *lidx;    // per lane {4 f + k, L, R, 8 tag + ngp}, f = -1 idle
+    const double *lgeo;  // per lane dx_L, dx_R, n, w S ([10][NL])
+    int64_t NL;
     const BcTable *bc;
     double *out;  // [F][nq], face-major
     int32_t *bad;
@@ -208,35 +210,34 @@ template <class T, int MODE, bool VAL> __global__ __launch_bounds__(256) void k_
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int ln = threadIdx.x & 63;
-    const int lm = A.lmap[gid];  // the grid covers the padded lane map exactly
-    const bool act = lm >= 0;
-    const int64_t f = act ? (lm >> 2) : 0;
-    const int k = lm & 3;
-    const int64_t F = A.F, N = A.N;
-    const int ngp = act ? A.fngp[f] : 0;
-    const int L = A.fl[f], R = A.fr[f];
+    const int64_t NL = A.NL, N = A.N;
+    const int4 id = A.lidx[gid];  // the grid covers the padded lane map exactly
+    const bool act = id.x >= 0;
+    const int64_t f = id.x >> 2;
+    const int k = id.x & 3;
+    const int L = id.y, R = id.z;
+    const int ngp = id.w & 7;
     constexpr int NQ = MODE == MODE_RES ? 21 : MODE == MODE_RESONLY ? 5 : MODE == MODE_S1 ? 41 : 26;
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     double alpha_k = 1.0;
     if (act) {
-        const double x[3] = {A.gpx[(3 * k) * F + f], A.gpx[(3 * k + 1) * F + f], A.gpx[(3 * k + 2) * F + f]};
-        const double n[3] = {A.gpn[(3 * k) * F + f], A.gpn[(3 * k + 1) * F + f], A.gpn[(3 * k + 2) * F + f]};
-        const double wS = A.gpw[k * F + f];
+        const double *g = A.lgeo + gid;
+        const double n[3] = {g[6 * NL], g[7 * NL], g[8 * NL]};
+        const double wS = g[9 * NL];
         double dtf = A.dt_global;
         if (dtf <= 0.0) dtf = R >= 0 ? fmin(A.dtc[L], A.dtc[R]) : A.dtc[L];
         double WL[5], GL[15], WR[5], GR[15];
         {
-            const double dx[3] = {x[0] - A.cen[L], x[1] - A.cen[N + L], x[2] - A.cen[2 * N + L]};
+            const double dx[3] = {g[0], g[NL], g[2 * NL]};
             eval_poly(A.coef, L, dx, WL, GL);
         }
         if (R >= 0) {
-            const double dx[3] = {x[0] - A.fshift[f] - A.cen[R], x[1] - A.fshift[F + f] - A.cen[N + R],
-                                  x[2] - A.fshift[2 * F + f] - A.cen[2 * N + R]};
+            const double dx[3] = {g[3 * NL], g[4 * NL], g[5 * NL]};
             eval_poly(A.coef, R, dx, WR, GR);
         } else {
-            const int tag = A.ftag[f];
+            const int tag = id.w >> 3;
             ghost_state(*A.bc, tag, n, WL, A.cfg.gamma, WR);
             ghost_grad(*A.bc, tag, n, GL, GR);
         }
@@ -578,18 +579,11 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
     A.dt_global = dt_global;
     A.coef = coef;
     A.dtc = dt_cell;
-    A.cen = c->cen.p;
-    A.gpx = c->gpx.p;
-    A.gpw = c->gpw.p;
-    A.gpn = c->gpn.p;
-    A.fshift = c->fshift.p;
-    A.fl = c->fl.p;
-    A.fr = c->fr.p;
-    A.ftag = c->ftag.p;
-    A.fngp = c->fngp.p;
+    A.lidx = c->lidx.p;
+    A.lgeo = c->lgeo.p;
+    A.NL = c->NL;
     A.bc = c->bc.p;
     A.out = c->fout.p;
-    A.lmap = c->lmap.p;
     A.bad = c->bad.p;
     const dim3 grid(blocks_for(c->NL, 256)), blk(256);
     const bool prfix = c->prm.viscous && c->prm.prandtl != 1.0;  // heat-flux correction needs the value moments

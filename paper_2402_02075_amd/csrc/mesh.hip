@@ -256,6 +256,37 @@ __global__ void k_slots(int64_t N, int64_t F, const int32_t *__restrict__ cf_ptr
     }
 }
 
+// Per face-kernel lane (lane-major, coalesced): Gauss point offsets from the left and right
+// cell centroids (the right one through the periodic shift), unit normal, weight w_k S, and
+// the packed indices {4 f + k, L, R, 8 tag + ngp}; idle lanes get zeros and f = -1.
+__global__ void k_lane_geom(int64_t NL, int64_t F, int64_t N, const int32_t *__restrict__ lmap,
+                            const double *__restrict__ gpx, const double *__restrict__ gpn,
+                            const double *__restrict__ gpw, const double *__restrict__ fshift,
+                            const double *__restrict__ cen, const int32_t *__restrict__ fl,
+                            const int32_t *__restrict__ fr, const int32_t *__restrict__ ftag,
+                            const int32_t *__restrict__ fngp, int4 *__restrict__ lidx, double *__restrict__ lgeo)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NL) return;
+    const int lm = lmap[t];
+    if (lm < 0) {
+        lidx[t] = make_int4(-1, 0, 0, 0);
+        for (int q = 0; q < 10; ++q) lgeo[q * NL + t] = 0.0;
+        return;
+    }
+    const int64_t f = lm >> 2;
+    const int k = lm & 3;
+    const int L = fl[f], R = fr[f];
+    lidx[t] = make_int4(lm, L, R, 8 * ftag[f] + fngp[f]);
+    for (int d = 0; d < 3; ++d) {
+        const double x = gpx[(3 * k + d) * F + f];
+        lgeo[d * NL + t] = x - cen[d * N + L];
+        lgeo[(3 + d) * NL + t] = R >= 0 ? x - fshift[d * F + f] - cen[d * N + R] : 0.0;
+        lgeo[(6 + d) * NL + t] = gpn[(3 * k + d) * F + f];
+    }
+    lgeo[9 * NL + t] = gpw[k * F + f];
+}
+
 // Per cell: solution operator of the constrained least-squares system of p^2 and the
 // linear least-squares operator used by the smoothness indicator beta_1,LS.
 //  unknowns a_1..a_9 of sum_k a_k (phi_k - avg_0 phi_k), phi = dx dy dz dx^2 dy^2 dz^2 dxdy dydz dxdz;
@@ -590,6 +621,11 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
     hipLaunchKernelGGL(k_face_geom, dim3(blocks_for(F, bs)), dim3(bs), 0, s, F, N, dxyz.p, dfnode.p, c->fl.p, c->cen.p,
                        dfsh.p, c->fngp.p, c->gpx.p, c->gpw.p, c->gpn.p, c->farea.p, c->favec.p, c->fmom.p,
                        c->fshift.p);
+    c->lidx.alloc(c->NL);
+    c->lgeo.alloc(10 * c->NL);
+    hipLaunchKernelGGL(k_lane_geom, dim3(blocks_for(c->NL, bs)), dim3(bs), 0, s, c->NL, F, N, c->lmap.p, c->gpx.p,
+                       c->gpn.p, c->gpw.p, c->fshift.p, c->cen.p, c->fl.p, c->fr.p, c->ftag.p, c->fngp.p, c->lidx.p,
+                       c->lgeo.p);
     hipLaunchKernelGGL(k_slots, dim3(blocks_for(N, bs)), dim3(bs), 0, s, N, F, c->cf_ptr.p, c->cf_face.p, c->fl.p,
                        c->fr.p, c->favec.p, c->vol.p, c->slot_nb.p, c->slot_av.p);
     hipLaunchKernelGGL(k_op_build, dim3(blocks_for(N, 64)), dim3(64), 0, s, N, F, c->cf_ptr.p, c->cf_face.p, c->fl.p,
