@@ -150,6 +150,9 @@ struct cgks_ctx {
     cgks::DBuf<int64_t> op_off;    // [N] first entry of the cell's operator (stride 64), -1: Green-Gauss only
     cgks::DBuf<uint8_t> n_int;     // [N] interior neighbours
     cgks::DBuf<double> op;         // per interior neighbour 39 entries (9 x 4 KKT columns, 3 LS), 64-cell interleaved
+    cgks::DBuf<int64_t> op_gbase;  // [ceil(N/64)] first entry of each 64-cell group
+    cgks::DBuf<int32_t> op_gnb;    // [ceil(N/64)] largest interior-neighbour count of the group's p^2 cells
+    cgks::DBuf<int32_t> inb;       // [6][N] interior neighbours in slot order, -1 past the last
     // boundary conditions
     cgks::BcTable bc_host{};
     cgks::DBuf<cgks::BcTable> bc;

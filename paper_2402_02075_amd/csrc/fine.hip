@@ -44,17 +44,16 @@ __global__ void k_local_dt(int64_t N, int64_t F, double gam, double cfl, double 
 
 // ---------------------------------------------------------------- reconstruction
 // One thread per (cell, conservative component): the reconstruction acts on each
-// component separately, so a block holds 64 consecutive cells and five waves, one per
-// component, all reading the same operator entries.
-template <int C, bool CELL_MAJOR> __device__ __forceinline__ void recon_component(const ReconArgs &A, int64_t i)
+// component separately, so a block holds 64 consecutive cells (one operator group) and five
+// waves, one per component.  The operator entries of the group's m-th interior neighbours
+// (39 x 64 doubles) are staged in LDS once per block and shared by the five waves, so every
+// operator byte crosses the memory hierarchy once.
+
+// Green-Gauss gradient of component C (boundary faces take the ghost of the own average).
+template <int C>
+__device__ __forceinline__ void recon_gg(const ReconArgs &A, int64_t i, double q0, double gg[3])
 {
     const int64_t N = A.N;
-    const double q0 = A.W[C * N + i];
-    const int64_t off = A.op_off[i];
-    double gg[3] = {0.0, 0.0, 0.0}, gl[3] = {0.0, 0.0, 0.0}, a[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) a[k] = 0.0;
-    int m = 0;
     for (int s = 0; s < 6; ++s) {
         const int nbv = A.slot_nb[s * N + i];
         if (nbv == INT32_MIN) break;
@@ -62,21 +61,7 @@ template <int C, bool CELL_MAJOR> __device__ __forceinline__ void recon_componen
         double qm;
         if (nbv >= 0) {
             qm = A.W[C * N + nbv];
-            if (off >= 0) {
-                const double *op = A.op + off + (int64_t)OP_GROUP * OP_PER_NB * m;
-                const double e = qm - q0;
-                const double gx = A.G[(3 * C) * N + nbv], gy = A.G[(3 * C + 1) * N + nbv],
-                             gz = A.G[(3 * C + 2) * N + nbv];
-#pragma unroll
-                for (int k = 0; k < 9; ++k)
-                    a[k] += op[OP_GROUP * k] * e + op[OP_GROUP * (9 + 3 * k)] * gx +
-                            op[OP_GROUP * (10 + 3 * k)] * gy + op[OP_GROUP * (11 + 3 * k)] * gz;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) gl[d] += op[OP_GROUP * (36 + d)] * e;
-            }
-            ++m;
         } else {
-            // boundary face: Green-Gauss uses the boundary-condition ghost of the own average
             const int f = -nbv - 1;
             const double na = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
             const double n[3] = {av[0] / na, av[1] / na, av[2] / na};
@@ -89,6 +74,55 @@ template <int C, bool CELL_MAJOR> __device__ __forceinline__ void recon_componen
 #pragma unroll
         for (int d = 0; d < 3; ++d) gg[d] += 0.5 * (qm + q0) * av[d];
     }
+}
+
+template <bool CELL_MAJOR> __global__ __launch_bounds__(320) void k_recon(ReconArgs A)
+{
+    __shared__ double sop[OP_PER_NB * OP_GROUP];
+    const int lane = threadIdx.x & (OP_GROUP - 1);
+    const int C = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform over a wave
+    const int64_t N = A.N;
+    const int64_t i = (int64_t)blockIdx.x * OP_GROUP + lane;
+    const bool live = i < N;
+    const int64_t ic = live ? i : N - 1;
+    const double q0 = A.W[C * N + ic];
+    const int64_t off = A.op_off[ic];
+    double gg[3] = {0.0, 0.0, 0.0};
+    if (live) {
+        switch (C) {
+        case 0: recon_gg<0>(A, i, q0, gg); break;
+        case 1: recon_gg<1>(A, i, q0, gg); break;
+        case 2: recon_gg<2>(A, i, q0, gg); break;
+        case 3: recon_gg<3>(A, i, q0, gg); break;
+        default: recon_gg<4>(A, i, q0, gg); break;
+        }
+    }
+    // p^2 operator products, one interior neighbour at a time, operators staged in LDS
+    double a[9], gl[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a[k] = 0.0;
+    const int gnb = A.gnb[blockIdx.x];
+    const int nint = A.n_int[ic];
+    const double *gop = A.op + A.gbase[blockIdx.x];
+    for (int m = 0; m < gnb; ++m) {
+        const double *src = gop + (int64_t)OP_GROUP * OP_PER_NB * m;
+        for (int t = threadIdx.x; t < OP_PER_NB * OP_GROUP; t += 5 * OP_GROUP) sop[t] = src[t];
+        __syncthreads();
+        if (live && off >= 0 && m < nint) {
+            const int nb = A.inb[m * N + i];
+            const double e = A.W[C * N + nb] - q0;
+            const double gx = A.G[(3 * C) * N + nb], gy = A.G[(3 * C + 1) * N + nb], gz = A.G[(3 * C + 2) * N + nb];
+            const double *o = sop + lane;
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                a[k] += o[OP_GROUP * k] * e + o[OP_GROUP * (9 + 3 * k)] * gx + o[OP_GROUP * (10 + 3 * k)] * gy +
+                        o[OP_GROUP * (11 + 3 * k)] * gz;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) gl[d] += o[OP_GROUP * (36 + d)] * e;
+        }
+        __syncthreads();
+    }
+    if (!live) return;
     const double al = A.alpha ? A.alpha[i] : 1.0;
     double r[10];
     const double p1x = al * gg[0], p1y = al * gg[1], p1z = al * gg[2];
@@ -147,20 +181,6 @@ template <int C, bool CELL_MAJOR> __device__ __forceinline__ void recon_componen
     for (int k = 0; k < 10; ++k) {
         if (CELL_MAJOR) A.coef[i * 50 + 10 * C + k] = r[k];
         else A.coef[(10 * C + k) * N + i] = r[k];
-    }
-}
-
-template <bool CELL_MAJOR> __global__ __launch_bounds__(320) void k_recon(ReconArgs A)
-{
-    const int64_t i = (int64_t)blockIdx.x * OP_GROUP + (threadIdx.x & (OP_GROUP - 1));
-    if (i >= A.N) return;
-    // the component is uniform over a wave
-    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
-    case 0: recon_component<0, CELL_MAJOR>(A, i); break;
-    case 1: recon_component<1, CELL_MAJOR>(A, i); break;
-    case 2: recon_component<2, CELL_MAJOR>(A, i); break;
-    case 3: recon_component<3, CELL_MAJOR>(A, i); break;
-    default: recon_component<4, CELL_MAJOR>(A, i); break;
     }
 }
 
@@ -565,6 +585,10 @@ void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *a
     A.op_off = c->op_off.p;
     A.bc = c->bc.p;
     A.coef = coef;
+    A.gbase = c->op_gbase.p;
+    A.gnb = c->op_gnb.p;
+    A.inb = c->inb.p;
+    A.n_int = c->n_int.p;
     const dim3 grid(blocks_for(c->N, OP_GROUP)), blk(5 * OP_GROUP);
     if (cell_major) hipLaunchKernelGGL((k_recon<true>), grid, blk, 0, c->stream, A);
     else hipLaunchKernelGGL((k_recon<false>), grid, blk, 0, c->stream, A);

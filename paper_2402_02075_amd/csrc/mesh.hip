@@ -566,7 +566,8 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
     }
     // Operators are interleaved over groups of 64 consecutive cells: entry e of cell i is
     // at op_off[i] + 64 e, each group sized for its largest interior-neighbour count.
-    std::vector<int64_t> off(N);
+    std::vector<int64_t> off(N), gbase((N + 63) / 64);
+    std::vector<int32_t> gnb((N + 63) / 64);
     int64_t tot = 0;
     for (int64_t g0 = 0; g0 < N; g0 += 64) {
         const int64_t g1 = std::min<int64_t>(N, g0 + 64);
@@ -574,7 +575,19 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
         for (int64_t i = g0; i < g1; ++i)
             if (nint[i] >= 3) nbmax = std::max<int>(nbmax, nint[i]);
         for (int64_t i = g0; i < g1; ++i) off[i] = nint[i] >= 3 ? tot + (i - g0) : -1;
+        gbase[g0 / 64] = tot;
+        gnb[g0 / 64] = nbmax;
         tot += 64 * 39 * (int64_t)nbmax;
+    }
+    // interior neighbours of each cell in face (slot) order, the order of the operator columns
+    std::vector<int32_t> inbh(6 * N, -1);
+    for (int64_t i = 0; i < N; ++i) {
+        int m = 0;
+        for (int32_t k = cfp[i]; k < cfp[i + 1]; ++k) {
+            const int64_t f = cff[k] >> 1;
+            if (hfr[f] < 0) continue;
+            inbh[m++ * N + i] = (cff[k] & 1) ? hfl[f] : hfr[f];
+        }
     }
     // upload and compute geometry
     c->N = N;
@@ -598,6 +611,9 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
     c->cf_face.upload(cff, s);
     c->n_int.upload(nint, s);
     c->op_off.upload(off, s);
+    c->op_gbase.upload(gbase, s);
+    c->op_gnb.upload(gnb, s);
+    c->inb.upload(inbh, s);
     c->vol.alloc(N);
     c->cen.alloc(3 * N);
     c->mom2.alloc(6 * N);

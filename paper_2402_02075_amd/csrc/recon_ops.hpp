@@ -20,6 +20,10 @@ struct ReconArgs {
     const int32_t *slot_nb, *ftag;
     const int64_t *op_off;
     const BcTable *bc;
+    const int64_t *gbase;   // per 64-cell group: first operator entry
+    const int32_t *gnb;     // per group: largest interior-neighbour count of its p^2 cells
+    const int32_t *inb;     // [6][N] interior neighbours in slot order (-1 past the last)
+    const uint8_t *n_int;   // [N] interior neighbours
     double *coef;
 };
 
