@@ -153,6 +153,9 @@ struct cgks_ctx {
     cgks::DBuf<int64_t> op_gbase;  // [ceil(N/64)] first entry of each 64-cell group
     cgks::DBuf<int32_t> op_gnb;    // [ceil(N/64)] largest interior-neighbour count of the group's p^2 cells
     cgks::DBuf<int32_t> inb;       // [6][N] interior neighbours in slot order, -1 past the last
+    cgks::DBuf<int32_t> op_gmax;   // [ceil(N/64)] largest interior-neighbour count of the group
+    cgks::DBuf<double> iav;        // [6*3][N] area vector / |Omega| of the interior faces, in that order
+    cgks::DBuf<uint8_t> nface;     // [N] faces of the cell
     // boundary conditions
     cgks::BcTable bc_host{};
     cgks::DBuf<cgks::BcTable> bc;

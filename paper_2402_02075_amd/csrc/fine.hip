@@ -49,28 +49,24 @@ __global__ void k_local_dt(int64_t N, int64_t F, double gam, double cfl, double 
 // (39 x 64 doubles) are staged in LDS once per block and shared by the five waves, so every
 // operator byte crosses the memory hierarchy once.
 
-// Green-Gauss gradient of component C (boundary faces take the ghost of the own average).
+// Green-Gauss contributions of the boundary faces of component C (the ghost of the own average).
 template <int C>
-__device__ __forceinline__ void recon_gg(const ReconArgs &A, int64_t i, double q0, double gg[3])
+__device__ __forceinline__ void recon_gg_boundary(const ReconArgs &A, int64_t i, double q0, double gg[3])
 {
     const int64_t N = A.N;
     for (int s = 0; s < 6; ++s) {
         const int nbv = A.slot_nb[s * N + i];
         if (nbv == INT32_MIN) break;
+        if (nbv >= 0) continue;
         const double av[3] = {A.slot_av[(3 * s) * N + i], A.slot_av[(3 * s + 1) * N + i], A.slot_av[(3 * s + 2) * N + i]};
-        double qm;
-        if (nbv >= 0) {
-            qm = A.W[C * N + nbv];
-        } else {
-            const int f = -nbv - 1;
-            const double na = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
-            const double n[3] = {av[0] / na, av[1] / na, av[2] / na};
-            double Q0[5], Qg[5];
+        const int f = -nbv - 1;
+        const double na = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
+        const double n[3] = {av[0] / na, av[1] / na, av[2] / na};
+        double Q0[5], Qg[5];
 #pragma unroll
-            for (int c = 0; c < 5; ++c) Q0[c] = A.W[c * N + i];
-            ghost_state(*A.bc, A.ftag[f], n, Q0, A.gam, Qg);
-            qm = Qg[C];
-        }
+        for (int c = 0; c < 5; ++c) Q0[c] = A.W[c * N + i];
+        ghost_state(*A.bc, A.ftag[f], n, Q0, A.gam, Qg);
+        const double qm = Qg[C];
 #pragma unroll
         for (int d = 0; d < 3; ++d) gg[d] += 0.5 * (qm + q0) * av[d];
     }
@@ -88,30 +84,47 @@ template <bool CELL_MAJOR> __global__ __launch_bounds__(320) void k_recon(ReconA
     const double q0 = A.W[C * N + ic];
     const int64_t off = A.op_off[ic];
     double gg[3] = {0.0, 0.0, 0.0};
-    if (live) {
+    const int nint = A.n_int[ic];
+    if (live && nint < A.nface[ic]) {
         switch (C) {
-        case 0: recon_gg<0>(A, i, q0, gg); break;
-        case 1: recon_gg<1>(A, i, q0, gg); break;
-        case 2: recon_gg<2>(A, i, q0, gg); break;
-        case 3: recon_gg<3>(A, i, q0, gg); break;
-        default: recon_gg<4>(A, i, q0, gg); break;
+        case 0: recon_gg_boundary<0>(A, i, q0, gg); break;
+        case 1: recon_gg_boundary<1>(A, i, q0, gg); break;
+        case 2: recon_gg_boundary<2>(A, i, q0, gg); break;
+        case 3: recon_gg_boundary<3>(A, i, q0, gg); break;
+        default: recon_gg_boundary<4>(A, i, q0, gg); break;
         }
     }
-    // p^2 operator products, one interior neighbour at a time, operators staged in LDS
+    // interior neighbours one at a time: Green-Gauss term and, for p^2 cells, the operator
+    // products with the entries staged in LDS; the neighbour's data are requested before
+    // the staging so that both loads are in flight together
     double a[9], gl[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < 9; ++k) a[k] = 0.0;
-    const int gnb = A.gnb[blockIdx.x];
-    const int nint = A.n_int[ic];
+    const int gnb = A.gnb[blockIdx.x], gmax = A.gmax[blockIdx.x];
     const double *gop = A.op + A.gbase[blockIdx.x];
-    for (int m = 0; m < gnb; ++m) {
-        const double *src = gop + (int64_t)OP_GROUP * OP_PER_NB * m;
-        for (int t = threadIdx.x; t < OP_PER_NB * OP_GROUP; t += 5 * OP_GROUP) sop[t] = src[t];
+    for (int m = 0; m < gmax; ++m) {
+        const bool use = live && m < nint;
+        const int nb = use ? A.inb[m * N + i] : 0;
+        const double qm = A.W[C * N + nb];
+        const double av[3] = {A.iav[(3 * m) * N + ic], A.iav[(3 * m + 1) * N + ic], A.iav[(3 * m + 2) * N + ic]};
+        const bool p2 = use && off >= 0;
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        if (p2) {
+            gx = A.G[(3 * C) * N + nb];
+            gy = A.G[(3 * C + 1) * N + nb];
+            gz = A.G[(3 * C + 2) * N + nb];
+        }
+        if (m < gnb) {
+            const double *src = gop + (int64_t)OP_GROUP * OP_PER_NB * m;
+            for (int t = threadIdx.x; t < OP_PER_NB * OP_GROUP; t += 5 * OP_GROUP) sop[t] = src[t];
+        }
         __syncthreads();
-        if (live && off >= 0 && m < nint) {
-            const int nb = A.inb[m * N + i];
-            const double e = A.W[C * N + nb] - q0;
-            const double gx = A.G[(3 * C) * N + nb], gy = A.G[(3 * C + 1) * N + nb], gz = A.G[(3 * C + 2) * N + nb];
+        if (use) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) gg[d] += 0.5 * (qm + q0) * av[d];
+        }
+        if (p2) {
+            const double e = qm - q0;
             const double *o = sop + lane;
 #pragma unroll
             for (int k = 0; k < 9; ++k)
@@ -587,8 +600,11 @@ void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *a
     A.coef = coef;
     A.gbase = c->op_gbase.p;
     A.gnb = c->op_gnb.p;
+    A.gmax = c->op_gmax.p;
     A.inb = c->inb.p;
+    A.iav = c->iav.p;
     A.n_int = c->n_int.p;
+    A.nface = c->nface.p;
     const dim3 grid(blocks_for(c->N, OP_GROUP)), blk(5 * OP_GROUP);
     if (cell_major) hipLaunchKernelGGL((k_recon<true>), grid, blk, 0, c->stream, A);
     else hipLaunchKernelGGL((k_recon<false>), grid, blk, 0, c->stream, A);

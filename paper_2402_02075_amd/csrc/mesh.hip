@@ -287,6 +287,25 @@ __global__ void k_lane_geom(int64_t NL, int64_t F, int64_t N, const int32_t *__r
     lgeo[9 * NL + t] = gpw[k * F + f];
 }
 
+// Area vectors / |Omega| of each cell's interior faces in neighbour order (the slot vectors
+// with the boundary slots left out), for the reconstruction's Green-Gauss term.
+__global__ void k_iav(int64_t N, const int32_t *__restrict__ slot_nb, const double *__restrict__ slot_av,
+                      double *__restrict__ iav)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int m = 0;
+    for (int s = 0; s < 6; ++s) {
+        const int nbv = slot_nb[s * N + i];
+        if (nbv == INT32_MIN) break;
+        if (nbv < 0) continue;
+        for (int d = 0; d < 3; ++d) iav[(3 * m + d) * N + i] = slot_av[(3 * s + d) * N + i];
+        ++m;
+    }
+    for (; m < 6; ++m)
+        for (int d = 0; d < 3; ++d) iav[(3 * m + d) * N + i] = 0.0;
+}
+
 // Per cell: solution operator of the constrained least-squares system of p^2 and the
 // linear least-squares operator used by the smoothness indicator beta_1,LS.
 //  unknowns a_1..a_9 of sum_k a_k (phi_k - avg_0 phi_k), phi = dx dy dz dx^2 dy^2 dz^2 dxdy dydz dxdz;
@@ -567,7 +586,7 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
     // Operators are interleaved over groups of 64 consecutive cells: entry e of cell i is
     // at op_off[i] + 64 e, each group sized for its largest interior-neighbour count.
     std::vector<int64_t> off(N), gbase((N + 63) / 64);
-    std::vector<int32_t> gnb((N + 63) / 64);
+    std::vector<int32_t> gnb((N + 63) / 64), gmx((N + 63) / 64);
     int64_t tot = 0;
     for (int64_t g0 = 0; g0 < N; g0 += 64) {
         const int64_t g1 = std::min<int64_t>(N, g0 + 64);
@@ -577,6 +596,9 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
         for (int64_t i = g0; i < g1; ++i) off[i] = nint[i] >= 3 ? tot + (i - g0) : -1;
         gbase[g0 / 64] = tot;
         gnb[g0 / 64] = nbmax;
+        int am = 0;
+        for (int64_t i = g0; i < g1; ++i) am = std::max<int>(am, nint[i]);
+        gmx[g0 / 64] = am;
         tot += 64 * 39 * (int64_t)nbmax;
     }
     // interior neighbours of each cell in face (slot) order, the order of the operator columns
@@ -613,7 +635,13 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
     c->op_off.upload(off, s);
     c->op_gbase.upload(gbase, s);
     c->op_gnb.upload(gnb, s);
+    c->op_gmax.upload(gmx, s);
     c->inb.upload(inbh, s);
+    {
+        std::vector<uint8_t> nf(N);
+        for (int64_t i = 0; i < N; ++i) nf[i] = (uint8_t)(cfp[i + 1] - cfp[i]);
+        c->nface.upload(nf, s);
+    }
     c->vol.alloc(N);
     c->cen.alloc(3 * N);
     c->mom2.alloc(6 * N);
@@ -644,6 +672,8 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
                        c->lgeo.p);
     hipLaunchKernelGGL(k_slots, dim3(blocks_for(N, bs)), dim3(bs), 0, s, N, F, c->cf_ptr.p, c->cf_face.p, c->fl.p,
                        c->fr.p, c->favec.p, c->vol.p, c->slot_nb.p, c->slot_av.p);
+    c->iav.alloc(18 * N);
+    hipLaunchKernelGGL(k_iav, dim3(blocks_for(N, bs)), dim3(bs), 0, s, N, c->slot_nb.p, c->slot_av.p, c->iav.p);
     hipLaunchKernelGGL(k_op_build, dim3(blocks_for(N, 64)), dim3(64), 0, s, N, F, c->cf_ptr.p, c->cf_face.p, c->fl.p,
                        c->fr.p, c->fshift.p, c->vol.p, c->cen.p, c->mom2.p, c->op_off.p, c->op.p, c->bad.p);
     CGKS_HIP(hipGetLastError());

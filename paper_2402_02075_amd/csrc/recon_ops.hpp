@@ -22,8 +22,11 @@ struct ReconArgs {
     const BcTable *bc;
     const int64_t *gbase;   // per 64-cell group: first operator entry
     const int32_t *gnb;     // per group: largest interior-neighbour count of its p^2 cells
+    const int32_t *gmax;    // per group: largest interior-neighbour count of all its cells
     const int32_t *inb;     // [6][N] interior neighbours in slot order (-1 past the last)
+    const double *iav;      // [6*3][N] outward area vector / |Omega| of those faces
     const uint8_t *n_int;   // [N] interior neighbours
+    const uint8_t *nface;   // [N] faces
     double *coef;
 };
 
