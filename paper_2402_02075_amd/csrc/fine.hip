@@ -102,9 +102,11 @@ template <bool CELL_MAJOR> __global__ __launch_bounds__(320) void k_recon(ReconA
     for (int k = 0; k < 9; ++k) a[k] = 0.0;
     const int gnb = A.gnb[blockIdx.x], gmax = A.gmax[blockIdx.x];
     const double *gop = A.op + A.gbase[blockIdx.x];
+    int nb_next = (live && nint > 0) ? A.inb[i] : 0;
     for (int m = 0; m < gmax; ++m) {
         const bool use = live && m < nint;
-        const int nb = use ? A.inb[m * N + i] : 0;
+        const int nb = use ? nb_next : 0;
+        nb_next = (live && m + 1 < nint) ? A.inb[(m + 1) * N + i] : 0;  // one neighbour ahead
         const double qm = A.W[C * N + nb];
         const double av[3] = {A.iav[(3 * m) * N + ic], A.iav[(3 * m + 1) * N + ic], A.iav[(3 * m + 2) * N + ic]};
         const bool p2 = use && off >= 0;
