@@ -323,7 +323,7 @@ cgks_status cgks_step(cgks_ctx *c, double *W, double *G, double *alpha, double d
         launch_local_dt(c, W, c->dtc.p);
         launch_recon(c, W, G, alpha, c->coef.p);
         launch_face(c, MODE_RES, c->coef.p, c->dtc.p, -1.0, false);
-        const int nb = norm_blocks(c->N);
+        const int nb = gather_blocks(c->N);
         c->partial.ensure(nb);
         launch_gather_fe(c, W, G, alpha, c->dtc.p, c->Rw.p, c->partial.p);
         if (resnorm) finish_norm(c, c->partial.p, nb, c->N, resnorm);

@@ -602,6 +602,18 @@ void build_hierarchy(cgks_ctx *c)
 }
 
 // ---------------------------------------------------------------- KFVS and transfers
+// Rows of a CSR list handled by RG consecutive lanes each: lane g takes items g, g + RG, ...
+// and the partial sums meet in a fixed xor tree, so results are deterministic and a level of a
+// few ten thousand cells still fills the chip.
+constexpr int RG = 8;
+template <class T> __device__ __forceinline__ T row_sum(T v)
+{
+#pragma unroll
+    for (int o = RG / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+static inline dim3 GR(int64_t rows) { return dim3(blocks_for((rows > 0 ? rows : 1) * RG, 256)); }
+
 template <class T> struct CoarseArgs {
     int64_t n, m, nb;
     double gam, K;
@@ -669,10 +681,12 @@ __global__ __launch_bounds__(256) void k_kfvs_gather(int64_t n, int64_t tot, int
                                                      const int32_t *__restrict__ item, const T *__restrict__ ff,
                                                      T *__restrict__ R)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / RG;
+    const int g = (int)(t % RG);
+    if (i >= n) return;  // whole row groups leave together
     T r[5] = {T(0), T(0), T(0), T(0), T(0)};
-    for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+    for (int k = ptr[i] + g; k < ptr[i + 1]; k += RG) {
         const int it = item[k];
         if (it >= 0) {
             const int j = it >> 1;
@@ -686,7 +700,10 @@ __global__ __launch_bounds__(256) void k_kfvs_gather(int64_t n, int64_t tot, int
         }
     }
 #pragma unroll
-    for (int q = 0; q < 5; ++q) R[q * n + i] = r[q];
+    for (int q = 0; q < 5; ++q) r[q] = row_sum(r[q]);
+    if (g == 0)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) R[q * n + i] = r[q];
 }
 
 // local time step on a coarse level
@@ -697,15 +714,17 @@ __global__ __launch_bounds__(256) void k_coarse_dt(int64_t n, int64_t m, int64_t
                                                    const double *__restrict__ A, const double *__restrict__ bA,
                                                    const double *__restrict__ V, T *__restrict__ dt)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / RG;
+    const int g = (int)(t % RG);
+    if (i >= n) return;  // whole row groups leave together
     const double rho = double(W[i]), ir = 1.0 / rho;
     const double u = double(W[n + i]) * ir, v = double(W[2 * n + i]) * ir, w = double(W[3 * n + i]) * ir;
     const double p = (gam - 1.0) * (double(W[4 * n + i]) - 0.5 * rho * (u * u + v * v + w * w));
     const double cs = sqrt(gam * p * ir);
     const double Vi = V[i];
     double sum = 0.0;
-    for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+    for (int k = ptr[i] + g; k < ptr[i + 1]; k += RG) {
         const int it = item[k];
         double ax, ay, az, s;
         if (it >= 0) {
@@ -725,7 +744,8 @@ __global__ __launch_bounds__(256) void k_coarse_dt(int64_t n, int64_t m, int64_t
         const double lam = cs + (viscous ? 2.0 * mu * s / (rho * Vi) : 0.0);
         sum += uA + lam * s;
     }
-    dt[i] = T(cfl * Vi / sum);
+    sum = row_sum(sum);
+    if (g == 0) dt[i] = T(cfl * Vi / sum);
 }
 
 template <class T>
@@ -760,10 +780,12 @@ __global__ __launch_bounds__(256) void k_restrict(int64_t nc, int64_t nf, const 
                                                   const double *__restrict__ Vc, const Tf *__restrict__ Wf,
                                                   const Tf *__restrict__ Rf, Tc *__restrict__ Wc, Tc *__restrict__ Rc)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nc) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = t / RG;
+    const int g = (int)(t % RG);
+    if (k >= nc) return;  // whole row groups leave together
     double w[5] = {0, 0, 0, 0, 0}, r[5] = {0, 0, 0, 0, 0};
-    for (int q = ptr[k]; q < ptr[k + 1]; ++q) {
+    for (int q = ptr[k] + g; q < ptr[k + 1]; q += RG) {
         const int i = idx[q];
         const double v = Vf[i];
 #pragma unroll
@@ -774,12 +796,17 @@ __global__ __launch_bounds__(256) void k_restrict(int64_t nc, int64_t nf, const 
     }
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-        if (Wc) Wc[c * nc + k] = Tc(w[c] / Vc[k]);
-        if (Rc) Rc[c * nc + k] = Tc(r[c]);
+        w[c] = row_sum(w[c]);
+        r[c] = row_sum(r[c]);
     }
+    if (g == 0)
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            if (Wc) Wc[c * nc + k] = Tc(w[c] / Vc[k]);
+            if (Rc) Rc[c * nc + k] = Tc(r[c]);
+        }
 }
 
-// prolongation of the correction: Wf += (Wc - Wc0)[f2c]
 template <class Tc, class Tf>
 __global__ void k_prolong(int64_t nf, int64_t nc, const int32_t *__restrict__ f2c, const Tc *__restrict__ Wc,
                           const Tc *__restrict__ Wc0, Tf *__restrict__ Wf)
@@ -820,7 +847,7 @@ template <class T> static void kfvs_impl(cgks_ctx *c, int level, const T *W, T *
     A.fflux = ff;
     const int64_t tot = L->m + L->nb;
     hipLaunchKernelGGL((k_kfvs_face<T>), G1(tot), dim3(256), 0, c->stream, A);
-    hipLaunchKernelGGL((k_kfvs_gather<T>), G1(L->n), dim3(256), 0, c->stream, L->n, tot, L->m, L->cf_ptr.p,
+    hipLaunchKernelGGL((k_kfvs_gather<T>), GR(L->n), dim3(256), 0, c->stream, L->n, tot, L->m, L->cf_ptr.p,
                        L->cf_item.p, ff, R);
 }
 
@@ -857,7 +884,7 @@ void kfvs_residual_fp32(cgks_ctx *c, int level, const double *W, double *R)
 template <class T> static void coarse_dt_impl(cgks_ctx *c, int level, const T *W, T *dt)
 {
     Level *L = level_of(c, level);
-    hipLaunchKernelGGL((k_coarse_dt<T>), G1(L->n), dim3(256), 0, c->stream, L->n, L->m, L->nb, c->prm.gamma, c->prm.cfl,
+    hipLaunchKernelGGL((k_coarse_dt<T>), GR(L->n), dim3(256), 0, c->stream, L->n, L->m, L->nb, c->prm.gamma, c->prm.cfl,
                        c->prm.mu, c->prm.viscous, W, L->cf_ptr.p, L->cf_item.p, L->S.p, L->A.p, L->bA.p, L->V.p, dt);
 }
 
@@ -871,7 +898,7 @@ static const double *finer_vol(cgks_ctx *c, int level)
 void restrict_level(cgks_ctx *c, int level, const double *Wf, const double *Rf, double *Wc, double *Rc)
 {
     Level *L = level_of(c, level);
-    hipLaunchKernelGGL((k_restrict<double, double>), G1(L->n), dim3(256), 0, c->stream, L->n, L->nfine, L->c2f_ptr.p,
+    hipLaunchKernelGGL((k_restrict<double, double>), GR(L->n), dim3(256), 0, c->stream, L->n, L->nfine, L->c2f_ptr.p,
                        L->c2f_idx.p, finer_vol(c, level), L->V.p, Wf, Rf, Wc, Rc);
 }
 
@@ -969,7 +996,7 @@ template <class T> static void coarse_visit(cgks_ctx *c, int l)
         hipLaunchKernelGGL((k_sum_state<T>), G1(n5), dim3(256), 0, st, n5, b.W0, b.D, b.W);
         kfvs_impl<T>(c, l, b.W, b.R, b.ff);
         hipLaunchKernelGGL((k_add<T>), G1(n5), dim3(256), 0, st, n5, b.F, b.R);
-        hipLaunchKernelGGL((k_restrict<T, T>), G1(C->n), dim3(256), 0, st, C->n, C->nfine, C->c2f_ptr.p, C->c2f_idx.p,
+        hipLaunchKernelGGL((k_restrict<T, T>), GR(C->n), dim3(256), 0, st, C->n, C->nfine, C->c2f_ptr.p, C->c2f_idx.p,
                            L->V.p, C->V.p, b.W, b.R, cb.W0, cb.Rs);
         coarse_visit<T>(c, l + 1);
         hipLaunchKernelGGL((k_prolong<T, T>), G1(C->nfine), dim3(256), 0, st, C->nfine, C->n, C->f2c.p, cb.D,
@@ -987,7 +1014,7 @@ template <class T> static void coarse_visit(cgks_ctx *c, int l)
 void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flux, bool fp32_coarse)
 {
     hipStream_t st = c->stream;
-    const int nb = norm_blocks(c->N);
+    const int nb = gather_blocks(c->N);
     c->partial.ensure(nb);
     const int npre = std::max(1, c->prm.nu_pre[0]);
     for (int s = 0; s < npre; ++s) {
@@ -1005,14 +1032,14 @@ void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flu
         Level *L = c->lev[1];
         if (!fp32_coarse) {
             LevelBufs<double> b = bufs<double>(L);
-            hipLaunchKernelGGL((k_restrict<double, double>), G1(L->n), dim3(256), 0, st, L->n, L->nfine, L->c2f_ptr.p,
+            hipLaunchKernelGGL((k_restrict<double, double>), GR(L->n), dim3(256), 0, st, L->n, L->nfine, L->c2f_ptr.p,
                                L->c2f_idx.p, c->vol.p, L->V.p, W, c->Rw.p, b.W0, b.Rs);
             coarse_visit<double>(c, 1);
             hipLaunchKernelGGL((k_prolong<double, double>), G1(L->nfine), dim3(256), 0, st, L->nfine, L->n, L->f2c.p,
                                b.D, (const double *)nullptr, W);
         } else {
             LevelBufs<float> b = bufs<float>(L);
-            hipLaunchKernelGGL((k_restrict<double, float>), G1(L->n), dim3(256), 0, st, L->n, L->nfine, L->c2f_ptr.p,
+            hipLaunchKernelGGL((k_restrict<double, float>), GR(L->n), dim3(256), 0, st, L->n, L->nfine, L->c2f_ptr.p,
                                L->c2f_idx.p, c->vol.p, L->V.p, W, c->Rw.p, b.W0, b.Rs);
             coarse_visit<float>(c, 1);
             hipLaunchKernelGGL((k_prolong<float, double>), G1(L->nfine), dim3(256), 0, st, L->nfine, L->n, L->f2c.p,

@@ -196,6 +196,7 @@ void launch_norm(cgks_ctx *c, const double *R, const double *vol, int64_t n, dou
 void launch_wall_force(cgks_ctx *c, int32_t tag, double *out);  // after a MODE_RESONLY face launch
 void finish_norm(cgks_ctx *c, const double *partials, int nblocks, int64_t n, double *out);
 int norm_blocks(int64_t n);
+int gather_blocks(int64_t n);  // blocks (and norm partials) of the FE gather
 void launch_fill(double *p, double v, int64_t n, hipStream_t s);
 
 // coarse levels

@@ -366,22 +366,40 @@ struct GatherArgs {
 };
 
 // R = -sum s F, Gn = alpha S/V, alpha = prod; optionally W += dt/V R (FE) and norm partials.
+// Four lanes per cell (lane g takes the cell's faces g, g + 4, ...), partial sums and products
+// combined in a fixed xor tree: deterministic, and four times the waves of a thread per cell.
+constexpr int CG = 4;
+__device__ __forceinline__ double cell_sum(double v)
+{
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    return v;
+}
+__device__ __forceinline__ double cell_prod(double v)
+{
+    v *= __shfl_xor(v, 1, 64);
+    v *= __shfl_xor(v, 2, 64);
+    return v;
+}
+
 template <bool FE, bool GRAD>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs A, double *__restrict__ R, double *__restrict__ Gn,
                                                 double *__restrict__ an, double *__restrict__ W,
                                                 const double *__restrict__ dt, double *__restrict__ part)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t N = A.N, F = A.F;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / CG;
+    const int g = (int)(t % CG);
+    const int64_t N = A.N;
     double r2 = 0.0;
-    if (i < N) {
+    if (i < N) {  // whole cell groups take the same branch
         double r[5] = {0, 0, 0, 0, 0};
-        double g[15];
+        double gs[15];
 #pragma unroll
-        for (int q = 0; q < 15; ++q) g[q] = 0.0;
+        for (int q = 0; q < 15; ++q) gs[q] = 0.0;
         double al = 1.0;
         constexpr int NQ = GRAD ? 21 : 5;
-        for (int k = A.cf_ptr[i]; k < A.cf_ptr[i + 1]; ++k) {
+        for (int k = A.cf_ptr[i] + g; k < A.cf_ptr[i + 1]; k += CG) {
             const int it = A.cf_face[k];
             const double *o = A.fout + (int64_t)(it >> 1) * NQ;
             const double s = (it & 1) ? -1.0 : 1.0;
@@ -389,25 +407,34 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A, double *__restrict
             for (int q = 0; q < 5; ++q) r[q] -= s * o[q];
             if (GRAD) {
 #pragma unroll
-                for (int q = 0; q < 15; ++q) g[q] += s * o[5 + q];
+                for (int q = 0; q < 15; ++q) gs[q] += s * o[5 + q];
                 al *= o[20];
             }
         }
-        const double iv = 1.0 / A.vol[i];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) R[q * N + i] = r[q];
+        for (int q = 0; q < 5; ++q) r[q] = cell_sum(r[q]);
         if (GRAD) {
 #pragma unroll
-            for (int q = 0; q < 15; ++q) Gn[q * N + i] = al * g[q] * iv;
-            an[i] = al;
+            for (int q = 0; q < 15; ++q) gs[q] = cell_sum(gs[q]);
+            al = cell_prod(al);
         }
-        if (FE) {
-            const double h = dt[i] * iv;
+        const double iv = 1.0 / A.vol[i];
+        if (g == 0) {
 #pragma unroll
-            for (int q = 0; q < 5; ++q) W[q * N + i] += h * r[q];
+            for (int q = 0; q < 5; ++q) R[q * N + i] = r[q];
+            if (GRAD) {
+#pragma unroll
+                for (int q = 0; q < 15; ++q) Gn[q * N + i] = al * gs[q] * iv;
+                an[i] = al;
+            }
+            if (FE) {
+                const double h = dt[i] * iv;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) W[q * N + i] += h * r[q];
+            }
+            const double rr = r[0] * iv;
+            r2 = rr * rr;
         }
-        const double rr = r[0] * iv;
-        r2 = rr * rr;
     }
     if (part) {
         // deterministic block reduction in a fixed tree
@@ -677,10 +704,11 @@ static GatherArgs gargs(cgks_ctx *c)
 }
 
 int norm_blocks(int64_t n) { return blocks_for(n, 256); }
+int gather_blocks(int64_t n) { return blocks_for(CG * n, 256); }
 
 void launch_gather_res(cgks_ctx *c, double *R, double *Gn, double *an, int mode)
 {
-    const dim3 grid(blocks_for(c->N, 256)), blk(256);
+    const dim3 grid(blocks_for(CG * c->N, 256)), blk(256);
     if (mode == MODE_RES)
         hipLaunchKernelGGL((k_gather<false, true>), grid, blk, 0, c->stream, gargs(c), R, Gn, an, nullptr, nullptr, nullptr);
     else
@@ -690,7 +718,7 @@ void launch_gather_res(cgks_ctx *c, double *R, double *Gn, double *an, int mode)
 
 void launch_gather_fe(cgks_ctx *c, double *W, double *G, double *alpha, const double *dt, double *Rout, double *part)
 {
-    const dim3 grid(blocks_for(c->N, 256)), blk(256);
+    const dim3 grid(blocks_for(CG * c->N, 256)), blk(256);
     hipLaunchKernelGGL((k_gather<true, true>), grid, blk, 0, c->stream, gargs(c), Rout, G, alpha, W, dt, part);
 }
 
