@@ -241,12 +241,11 @@ __device__ __forceinline__ double face_prod(double v, int ln, int ngp)
 
 // One lane per face Gauss point, faces packed into waves with 3 or 4 lanes each (lane map
 // built at set-up), face sums by lane shuffles.
-template <class T, int MODE, bool VAL> __global__ __launch_bounds__(256) void k_face(FaceArgs A)
+// The work of one lane: its face's Gauss point k, given the lane's indices and geometry.
+template <class T, int MODE, bool VAL>
+__device__ __forceinline__ void face_lane(const FaceArgs &A, const int4 id, const double g[10], int ln)
 {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int ln = threadIdx.x & 63;
-    const int64_t NL = A.NL, N = A.N;
-    const int4 id = A.lidx[gid];  // the grid covers the padded lane map exactly
+    const int64_t N = A.N;
     const bool act = id.x >= 0;
     const int64_t f = id.x >> 2;
     const int k = id.x & 3;
@@ -258,18 +257,17 @@ template <class T, int MODE, bool VAL> __global__ __launch_bounds__(256) void k_
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     double alpha_k = 1.0;
     if (act) {
-        const double *g = A.lgeo + gid;
-        const double n[3] = {g[6 * NL], g[7 * NL], g[8 * NL]};
-        const double wS = g[9 * NL];
+        const double n[3] = {g[6], g[7], g[8]};
+        const double wS = g[9];
         double dtf = A.dt_global;
         if (dtf <= 0.0) dtf = R >= 0 ? fmin(A.dtc[L], A.dtc[R]) : A.dtc[L];
         double WL[5], GL[15], WR[5], GR[15];
         {
-            const double dx[3] = {g[0], g[NL], g[2 * NL]};
+            const double dx[3] = {g[0], g[1], g[2]};
             eval_poly(A.coef, L, dx, WL, GL);
         }
         if (R >= 0) {
-            const double dx[3] = {g[3 * NL], g[4 * NL], g[5 * NL]};
+            const double dx[3] = {g[3], g[4], g[5]};
             eval_poly(A.coef, R, dx, WR, GR);
         } else {
             const int tag = id.w >> 3;
@@ -356,6 +354,20 @@ template <class T, int MODE, bool VAL> __global__ __launch_bounds__(256) void k_
         for (int q = 0; q < NQ; ++q) o[q] = acc[q];
         if (MODE != MODE_RESONLY) o[NQ - 1] = alpha_k;
     }
+}
+
+
+// One lane per face Gauss point, faces packed into waves with 3 or 4 lanes each (lane map
+// built at set-up), face sums by lane shuffles.
+template <class T, int MODE, bool VAL> __global__ __launch_bounds__(256) void k_face(FaceArgs A)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t NL = A.NL;
+    const int4 id = A.lidx[gid];  // the grid covers the padded lane map exactly
+    double g[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) g[q] = A.lgeo[q * NL + gid];
+    face_lane<T, MODE, VAL>(A, id, g, (int)(threadIdx.x & 63));
 }
 
 // ---------------------------------------------------------------- gathers
