@@ -679,7 +679,7 @@ template <class T> __global__ __launch_bounds__(256) void k_kfvs_face(CoarseArgs
 template <class T>
 __global__ __launch_bounds__(256) void k_kfvs_gather(int64_t n, int64_t tot, int64_t m, const int32_t *__restrict__ ptr,
                                                      const int32_t *__restrict__ item, const T *__restrict__ ff,
-                                                     T *__restrict__ R)
+                                                     const T *__restrict__ add, T *__restrict__ R)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = t / RG;
@@ -703,7 +703,7 @@ __global__ __launch_bounds__(256) void k_kfvs_gather(int64_t n, int64_t tot, int
     for (int q = 0; q < 5; ++q) r[q] = row_sum(r[q]);
     if (g == 0)
 #pragma unroll
-        for (int q = 0; q < 5; ++q) R[q * n + i] = r[q];
+        for (int q = 0; q < 5; ++q) R[q * n + i] = add ? r[q] + add[q * n + i] : r[q];
 }
 
 // local time step on a coarse level
@@ -827,7 +827,8 @@ static Level *level_of(cgks_ctx *c, int level)
     return c->lev[level];
 }
 
-template <class T> static void kfvs_impl(cgks_ctx *c, int level, const T *W, T *R, T *ff)
+// R = KFVS residual of W (+ add when given)
+template <class T> static void kfvs_impl(cgks_ctx *c, int level, const T *W, T *R, T *ff, const T *add = nullptr)
 {
     Level *L = level_of(c, level);
     CoarseArgs<T> A;
@@ -848,7 +849,7 @@ template <class T> static void kfvs_impl(cgks_ctx *c, int level, const T *W, T *
     const int64_t tot = L->m + L->nb;
     hipLaunchKernelGGL((k_kfvs_face<T>), G1(tot), dim3(256), 0, c->stream, A);
     hipLaunchKernelGGL((k_kfvs_gather<T>), GR(L->n), dim3(256), 0, c->stream, L->n, tot, L->m, L->cf_ptr.p,
-                       L->cf_item.p, ff, R);
+                       L->cf_item.p, ff, add, R);
 }
 
 void kfvs_residual(cgks_ctx *c, int level, const double *W, double *R)
@@ -925,6 +926,23 @@ __global__ void k_delta_first(int64_t n, const T *__restrict__ dt, const double 
     for (int q = 0; q < 5; ++q) D[q * n + i] = h * Rs[q * n + i];
 }
 
+// F = Res* - Res_2h(W0) and the first delta-form sweep D = dt/V Res* in one pass
+template <class T>
+__global__ void k_forcing_first(int64_t n, const T *__restrict__ Rs, const T *__restrict__ R0,
+                                const T *__restrict__ dt, const double *__restrict__ V, T *__restrict__ F,
+                                T *__restrict__ D)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T h = dt[i] / T(V[i]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const T rs = Rs[q * n + i];
+        F[q * n + i] = rs - R0[q * n + i];
+        D[q * n + i] = h * rs;
+    }
+}
+
 template <class T>
 __global__ void k_delta_update(int64_t n, const T *__restrict__ dt, const double *__restrict__ V, const T *__restrict__ R,
                                const T *__restrict__ F, T *__restrict__ D)
@@ -976,12 +994,12 @@ template <class T> static void coarse_visit(cgks_ctx *c, int l)
     const int64_t n = L->n, n5 = 5 * n;
     // forcing F = Res* - Res_2h(W0)
     kfvs_impl<T>(c, l, b.W0, b.R, b.ff);
-    hipLaunchKernelGGL((k_coarse_forcing<T>), G1(n5), dim3(256), 0, st, n5, b.Rs, b.R, b.F);
     const int npre = c->prm.nu_pre[l];
     if (npre > 0) {
         coarse_dt_impl<T>(c, l, b.W0, b.dt);
-        hipLaunchKernelGGL((k_delta_first<T>), G1(n), dim3(256), 0, st, n, b.dt, L->V.p, b.Rs, b.D);
+        hipLaunchKernelGGL((k_forcing_first<T>), G1(n), dim3(256), 0, st, n, b.Rs, b.R, b.dt, L->V.p, b.F, b.D);
     } else {
+        hipLaunchKernelGGL((k_coarse_forcing<T>), G1(n5), dim3(256), 0, st, n5, b.Rs, b.R, b.F);
         CGKS_HIP(hipMemsetAsync(b.D, 0, sizeof(T) * n5, st));
     }
     for (int s = 1; s < npre; ++s) {
@@ -994,8 +1012,7 @@ template <class T> static void coarse_visit(cgks_ctx *c, int l)
         Level *C = c->lev[l + 1];
         LevelBufs<T> cb = bufs<T>(C);
         hipLaunchKernelGGL((k_sum_state<T>), G1(n5), dim3(256), 0, st, n5, b.W0, b.D, b.W);
-        kfvs_impl<T>(c, l, b.W, b.R, b.ff);
-        hipLaunchKernelGGL((k_add<T>), G1(n5), dim3(256), 0, st, n5, b.F, b.R);
+        kfvs_impl<T>(c, l, b.W, b.R, b.ff, b.F);  // Res_2h(W0 + D) + F
         hipLaunchKernelGGL((k_restrict<T, T>), GR(C->n), dim3(256), 0, st, C->n, C->nfine, C->c2f_ptr.p, C->c2f_idx.p,
                            L->V.p, C->V.p, b.W, b.R, cb.W0, cb.Rs);
         coarse_visit<T>(c, l + 1);
