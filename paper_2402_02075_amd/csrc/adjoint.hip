@@ -270,9 +270,11 @@ __global__ __launch_bounds__(256) void k_face_vjp(FvArgs A)
     const double *br = A.brec + f * 21;
     const double a = act ? A.agp[gid] : 1.0;
     const double others = __shfl_xor(a, 1, 64) * __shfl_xor(a, 2, 64) * __shfl_xor(a, 3, 64);
-    double bl[50], bq[50], bdt = 0.0;
+    // Gauss-point input cotangents = J^T (output cotangents); zero on idle lanes
+    double bi[GP_IN];
+    double dxl[3] = {0.0, 0.0, 0.0}, dxr[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < 50; ++j) bl[j] = bq[j] = 0.0;
+    for (int q = 0; q < GP_IN; ++q) bi[q] = 0.0;
     if (act) {
         const double wS = A.gpw[k * F + f];
         const double x[3] = {A.gpx[(3 * k) * F + f], A.gpx[(3 * k + 1) * F + f], A.gpx[(3 * k + 2) * F + f]};
@@ -284,65 +286,74 @@ __global__ __launch_bounds__(256) void k_face_vjp(FvArgs A)
             bo[5 + q] = wS * (n[0] * br[5 + 3 * q] + n[1] * br[6 + 3 * q] + n[2] * br[7 + 3 * q]);
         }
         bo[10] = br[20] * others;
-        double bi[GP_IN];
+        // half an output row at a time: about 20 loads in flight, not all 451 (keeps the wave count up)
 #pragma unroll
-        for (int q = 0; q < GP_IN; ++q) {
-            double s = 0.0;
+        for (int o = 0; o < GP_OUT; ++o) {
+            const double *J = A.Jf + (int64_t)o * GP_IN * NS + gid;
 #pragma unroll
-            for (int o = 0; o < GP_OUT; ++o) s += A.Jf[(int64_t)(o * GP_IN + q) * NS + gid] * bo[o];
-            bi[q] = s;
+            for (int q = 0; q < 21; ++q) bi[q] += J[(int64_t)q * NS] * bo[o];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 21; q < GP_IN; ++q) bi[q] += J[(int64_t)q * NS] * bo[o];
+            __builtin_amdgcn_sched_barrier(0);
         }
-        {
-            const double dx[3] = {x[0] - A.cen[L], x[1] - A.cen[N + L], x[2] - A.cen[2 * N + L]};
 #pragma unroll
-            for (int c = 0; c < 5; ++c) poly_vjp(dx, bi[c], bi + 5 + 3 * c, bl + 10 * c);
-        }
-        if (R >= 0) {
-            const double dx[3] = {x[0] - A.fshift[f] - A.cen[R], x[1] - A.fshift[F + f] - A.cen[N + R],
-                                  x[2] - A.fshift[2 * F + f] - A.cen[2 * N + R]};
+        for (int d = 0; d < 3; ++d) dxl[d] = x[d] - A.cen[d * N + L];
+        if (R >= 0)
 #pragma unroll
-            for (int c = 0; c < 5; ++c) poly_vjp(dx, bi[20 + c], bi + 25 + 3 * c, bq + 10 * c);
-        }
-        bdt = bi[40];
+            for (int d = 0; d < 3; ++d) dxr[d] = x[d] - A.fshift[d * F + f] - A.cen[d * N + R];
     }
+    // polynomial transpose one component at a time (10 live sums), face sums by shuffles
     double *o = A.bface + f * 101;
 #pragma unroll
-    for (int j = 0; j < 50; ++j) {
-        const double sl = sum4(bl[j]);
-        const double sr = sum4(bq[j]);
-        if (k == 0) {
-            o[j] = sl;
-            o[50 + j] = sr;
+    for (int side = 0; side < 2; ++side) {
+        const double *dx = side == 0 ? dxl : dxr;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            double b[10];
+#pragma unroll
+            for (int j = 0; j < 10; ++j) b[j] = 0.0;
+            poly_vjp(dx, bi[20 * side + c], bi + 20 * side + 5 + 3 * c, b);
+#pragma unroll
+            for (int j = 0; j < 10; ++j) {
+                const double v = sum4(b[j]);
+                if (k == 0) o[50 * side + 10 * c + j] = v;
+            }
         }
     }
-    bdt = sum4(bdt);
+    const double bdt = sum4(bi[40]);
     if (k == 0) o[100] = bdt;
 }
 
-// per cell: coefficient cotangents and time-step cotangent from its faces, CSR order
+// per (component, cell): the component's 10 coefficient cotangents from the cell's faces, CSR
+// order; the density threads also collect the time-step cotangent
 __global__ __launch_bounds__(256) void k_coef_gather(int64_t N, const int32_t *cf_ptr, const int32_t *cf_face,
                                                      const int32_t *fr, const uint8_t *dtL, const double *bface,
                                                      double *bcoef, double *bdt)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    double b[50];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 5 * N) return;
+    const int c = (int)(t / N);
+    const int64_t i = t - (int64_t)c * N;
+    double b[10];
 #pragma unroll
-    for (int j = 0; j < 50; ++j) b[j] = 0.0;
-    double t = 0.0;
+    for (int j = 0; j < 10; ++j) b[j] = 0.0;
+    double tt = 0.0;
     for (int k = cf_ptr[i]; k < cf_ptr[i + 1]; ++k) {
         const int it = cf_face[k];
         const int f = it >> 1;
         const bool isR = it & 1;
-        const double *o = bface + (int64_t)f * 101 + (isR ? 50 : 0);
+        const double *o = bface + (int64_t)f * 101 + (isR ? 50 : 0) + 10 * c;
 #pragma unroll
-        for (int j = 0; j < 50; ++j) b[j] += o[j];
-        const bool fromL = fr[f] < 0 || dtL[f];
-        if (isR != fromL) t += bface[(int64_t)f * 101 + 100];
+        for (int j = 0; j < 10; ++j) b[j] += o[j];
+        if (c == 0) {
+            const bool fromL = fr[f] < 0 || dtL[f];
+            if (isR != fromL) tt += bface[(int64_t)f * 101 + 100];
+        }
     }
 #pragma unroll
-    for (int j = 0; j < 50; ++j) bcoef[i * 50 + j] = b[j];
-    bdt[i] = t;
+    for (int j = 0; j < 10; ++j) bcoef[i * 50 + 10 * c + j] = b[j];
+    if (c == 0) bdt[i] = tt;
 }
 
 // ---------------------------------------------------------------- reconstruction Jacobian and VJP
@@ -856,7 +867,7 @@ static void vjp_from_records(cgks_ctx *c, double *oW, double *oG, double *oA, bo
     A.fngp = c->fngp.p;
     A.bface = T.bface.p;
     hipLaunchKernelGGL(k_face_vjp, B1(4 * F), dim3(256), 0, st, A);
-    hipLaunchKernelGGL(k_coef_gather, B1(N), dim3(256), 0, st, N, c->cf_ptr.p, c->cf_face.p, c->fr.p, T.dtL.p,
+    hipLaunchKernelGGL(k_coef_gather, B1(5 * N), dim3(256), 0, st, N, c->cf_ptr.p, c->cf_face.p, c->fr.p, T.dtL.p,
                        T.bface.p, T.bcoef.p, T.bdt.p);
     hipLaunchKernelGGL(k_recon_vjp, B1(5 * N), dim3(256), 0, st, N, T.Jr.p, T.bcoef.p, T.bown.p, T.bslot.p);
     hipLaunchKernelGGL(k_recon_gather, B1(N), dim3(256), 0, st, N, c->slot_nb.p, T.rev.p, T.bown.p, T.bslot.p,

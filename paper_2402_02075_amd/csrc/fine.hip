@@ -117,8 +117,20 @@ template <bool CELL_MAJOR> __global__ __launch_bounds__(320) void k_recon(ReconA
             gz = A.G[(3 * C + 2) * N + nb];
         }
         if (m < gnb) {
+            // 2,496 entries over 320 threads: all eight loads in flight before the stores
             const double *src = gop + (int64_t)OP_GROUP * OP_PER_NB * m;
-            for (int t = threadIdx.x; t < OP_PER_NB * OP_GROUP; t += 5 * OP_GROUP) sop[t] = src[t];
+            constexpr int NT = 5 * OP_GROUP, NE = OP_PER_NB * OP_GROUP, NR = (NE + NT - 1) / NT;
+            double v[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int t = threadIdx.x + r * NT;
+                v[r] = t < NE ? src[t] : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int t = threadIdx.x + r * NT;
+                if (t < NE) sop[t] = v[r];
+            }
         }
         __syncthreads();
         if (use) {
