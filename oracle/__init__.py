@@ -23,12 +23,15 @@ BC_SLIP, BC_NOSLIP, BC_FARFIELD = 1, 2, 3
 class OmParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double), ("cfl", C.c_double),
                 ("eps_tau", C.c_double), ("c_tau", C.c_double), ("weno_eps", C.c_double),
-                ("gamma_lin", C.c_double), ("viscous", C.c_int)]
+                ("gamma_lin", C.c_double), ("viscous", C.c_int), ("coarse_smoother", C.c_int),
+                ("relax_sweeps", C.c_int), ("cfl_implicit", C.c_double)]
 
 
 def params(gamma=1.4, mu=0.0, prandtl=1.0, cfl=0.5, eps_tau=0.01, c_tau=1.0, weno_eps=1e-5, gamma_lin=0.5,
-           viscous=False) -> OmParams:
-    return OmParams(gamma, mu, prandtl, cfl, eps_tau, c_tau, weno_eps, gamma_lin, int(bool(viscous)))
+           viscous=False, coarse_smoother=0, relax_sweeps=2, cfl_implicit=2.0) -> OmParams:
+    """coarse_smoother 0: forward Euler on the coarse levels; 1: the implicit smoother of Sec. 4.3."""
+    return OmParams(gamma, mu, prandtl, cfl, eps_tau, c_tau, weno_eps, gamma_lin, int(bool(viscous)),
+                    int(coarse_smoother), int(relax_sweeps), float(cfl_implicit))
 
 
 def lib():
@@ -75,6 +78,8 @@ def lib():
         L.om_hier_level_get.argtypes = [P, C.c_int, P, P, P, P, P, P, P]
         L.om_kfvs_residual.argtypes = [P, C.c_int, P, P, P]
         L.om_coarse_dt.argtypes = [P, C.c_int, P, P, P]
+        L.om_coarse_implicit.argtypes = [P, C.c_int, P, P, P, P]
+        L.om_hier_level_boundary.argtypes = [P, C.c_int, P, P, P]
         L.om_restrict.argtypes = [P, C.c_int, P, P, P, P]
         L.om_prolong.argtypes = [P, C.c_int, P, P]
         L.om_vcycle.argtypes = [P, P, P, P, P, P, P, P, P]
@@ -298,6 +303,13 @@ class Hierarchy:
         lib().om_hier_level_get(self.h, int(l), _p(f2c), _p(V), _p(P), _p(a), _p(b), _p(A), _p(stats))
         return dict(n=n, m=m, nb=nb, f2c=f2c, V=V, P=P, a=a, b=b, A=A, stats=stats)
 
+    def level_boundary(self, l):
+        """Boundary faces of level l: owner cell, boundary tag, outward area vector."""
+        n, m, nb = self.size(l)
+        bown, btag, bA = np.zeros(nb, np.int64), np.zeros(nb, np.int32), np.zeros((nb, 3))
+        lib().om_hier_level_boundary(self.h, int(l), _p(bown), _p(btag), _p(bA))
+        return bown, btag, bA
+
     def kfvs_residual(self, par, l, W):
         n = self.size(l)[0]
         R = np.zeros((5, n))
@@ -309,6 +321,13 @@ class Hierarchy:
         dt = np.zeros(n)
         lib().om_coarse_dt(self.h, int(l), C.byref(par), _p(_f64(W)), _p(dt))
         return dt
+
+    def coarse_implicit(self, par, l, W, rhs):
+        """Increment dU of the implicit coarse smoother (Sec. 4.3) at state W for right-hand side rhs."""
+        n = self.size(l)[0]
+        dU = np.zeros((5, n))
+        lib().om_coarse_implicit(self.h, int(l), C.byref(par), _p(_f64(W)), _p(_f64(rhs)), _p(dU))
+        return dU
 
     def restrict(self, l, Wf, Rf):
         n = self.size(l)[0]

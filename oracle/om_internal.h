@@ -23,6 +23,10 @@ typedef struct {
     double gamma, mu, prandtl, cfl;
     double eps_tau, c_tau, weno_eps, gamma_lin;
     int viscous;
+    /* coarse-level smoother: 0 forward Euler, 1 implicit backward Euler (Sec. 4.3) */
+    int coarse_smoother;
+    int relax_sweeps;    /* point-relaxation sweeps of the implicit smoother */
+    double cfl_implicit; /* CFL number of the implicit smoother's local time step */
 } om_params;
 
 typedef struct {

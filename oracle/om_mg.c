@@ -12,7 +12,8 @@
  *  - coarse update W^{k+1} = W^k + dt/V (Res_2h(W^k) + F) with first-order KFVS
  *    and local time steps (Secs. 1, 4.2, 6);
  *  - correction W_h* = W_h^{n+1} + (W_2h^{k+1} - W_2h^0), averages only;
- *  - three-level V-cycle, one pre-smoothing and no post-smoothing by default.
+ *  - three-level V-cycle, one pre-smoothing and no post-smoothing by default;
+ *  - optionally the implicit coarse smoother of Sec. 4.3 (om_coarse_implicit).
  * Readings: coarse faces carry the summed fine area vectors (n = A/|A|,
  * S = |A|); coarse boundary faces are the fine boundary faces with the coarse
  * owner's ghost state; the coarse operator is inviscid KFVS, its local time
@@ -252,6 +253,15 @@ void om_hier_level_get(const om_hier *h, int l, int64_t *f2c, double *V, double 
     if (stats) memcpy(stats, h->stats[l], sizeof(h->stats[l]));
 }
 
+/* boundary faces of level l: owner, tag and outward area vector (3 per face) */
+void om_hier_level_boundary(const om_hier *h, int l, int64_t *bown, int32_t *btag, double *bA)
+{
+    const om_level *L = &h->lev[l];
+    if (bown) memcpy(bown, L->bown, sizeof(int64_t) * L->nb);
+    if (btag) memcpy(btag, L->btag, sizeof(int32_t) * L->nb);
+    if (bA) memcpy(bA, L->bA, sizeof(double) * 3 * L->nb);
+}
+
 /* KFVS residual on level l (l >= 1): R = - sum S n . F over coarse faces */
 int om_kfvs_residual(const om_hier *h, int l, const om_params *p, const double *W, double *R)
 {
@@ -369,6 +379,142 @@ void om_prolong(const om_hier *h, int l, const double *dWc, double *Wf)
         for (int k = 0; k < 5; ++k) Wf[k * Nf + i] += dWc[k * Nc + C->f2c[i]];
 }
 
+/*
+ * Implicit coarse smoother, paper Sec. 4.3.  Backward Euler on the coarse
+ * level, linearised with the Jacobian of a first-order Lax-Friedrichs flux:
+ * A+- = (A +- lambda I)/2 with lambda the larger of the two cells' spectral
+ * radii |U.n| + c + 2 mu S/(rho |Omega|) (the viscous term carries 1/rho so
+ * that it is a rate).  Because the outward area vectors of a closed cell sum
+ * to zero, the A part of A+ drops out of the diagonal, which is
+ * |Omega_i|/dt_i + (1/2) sum_p lambda_p S_p.  The off-diagonal product is
+ * taken without a matrix: A-_p dU_p ~ F-(U_p + dU_p) - F-(U_p) with
+ * F-(U) = (F_n(U) - lambda U)/2 and F_n the Euler flux along the outward
+ * normal of cell i.  The system
+ *     D_i dU_i + sum_p [F-(U_p + dU_p) - F-(U_p)] S_p = rhs_i
+ * is solved by point relaxation: dU^0 = rhs/D, then each sweep recomputes
+ * every cell from the previous sweep's neighbour increments.
+ * Readings: S is the coarse face's |A| (the factor of its KFVS flux);
+ * boundary faces add lambda S/2 to the diagonal with lambda the larger of the
+ * owner's and the ghost state's radius, and their ghost increment is zero;
+ * dt_i is the coarse local step with the implicit CFL number.
+ */
+static void euler_flux_n(const double *U, const double *n, double gamma, double *F)
+{
+    const double rho = U[0];
+    const double u[3] = {U[1] / rho, U[2] / rho, U[3] / rho};
+    const double pr = (gamma - 1.0) * (U[4] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+    const double un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+    F[0] = rho * un;
+    for (int d = 0; d < 3; ++d) F[1 + d] = U[1 + d] * un + pr * n[d];
+    F[4] = (U[4] + pr) * un;
+}
+
+static double spectral_radius(const double *U, const double *n, double S, double V, const om_params *p)
+{
+    const double rho = U[0];
+    const double u[3] = {U[1] / rho, U[2] / rho, U[3] / rho};
+    const double pr = (p->gamma - 1.0) * (U[4] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+    const double c = sqrt(p->gamma * pr / rho);
+    const double un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+    return fabs(un) + c + (p->viscous ? 2.0 * p->mu * S / (rho * V) : 0.0);
+}
+
+void om_coarse_implicit(const om_hier *h, int l, const om_params *p, const double *W, const double *rhs, double *dU)
+{
+    const om_level *L = &h->lev[l];
+    const int64_t N = L->n;
+    double *dt = malloc(sizeof(double) * N), *diag = malloc(sizeof(double) * N);
+    double *lam = calloc(L->m > 0 ? L->m : 1, sizeof(double));
+    double *prev = malloc(sizeof(double) * 5 * N), *acc = malloc(sizeof(double) * 5 * N);
+    om_params pi = *p;
+    pi.cfl = p->cfl_implicit;
+    om_coarse_dt(h, l, &pi, W, dt);
+    for (int64_t c = 0; c < N; ++c) diag[c] = L->V[c] / dt[c];
+    for (int64_t j = 0; j < L->m; ++j) {
+        const double *A = &L->A[3 * j];
+        const double S = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+        if (S == 0) continue;
+        const double n[3] = {A[0] / S, A[1] / S, A[2] / S};
+        double Ua[5], Ub[5];
+        for (int k = 0; k < 5; ++k) {
+            Ua[k] = W[k * N + L->a[j]];
+            Ub[k] = W[k * N + L->b[j]];
+        }
+        const double la = spectral_radius(Ua, n, S, L->V[L->a[j]], p);
+        const double lb = spectral_radius(Ub, n, S, L->V[L->b[j]], p);
+        lam[j] = la > lb ? la : lb;
+        diag[L->a[j]] += 0.5 * lam[j] * S;
+        diag[L->b[j]] += 0.5 * lam[j] * S;
+    }
+    for (int64_t q = 0; q < L->nb; ++q) {
+        const double *A = &L->bA[3 * q];
+        const double S = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+        const double n[3] = {A[0] / S, A[1] / S, A[2] / S};
+        const int64_t o = L->bown[q];
+        double Uo[5], Ug[5];
+        for (int k = 0; k < 5; ++k) Uo[k] = W[k * N + o];
+        om_bc_ghost_state(&h->mesh->bc[L->btag[q] & 63], n, Uo, p->gamma, Ug);
+        const double lo = spectral_radius(Uo, n, S, L->V[o], p);
+        const double lg = spectral_radius(Ug, n, S, L->V[o], p);
+        diag[o] += 0.5 * (lo > lg ? lo : lg) * S;
+    }
+    for (int64_t c = 0; c < N; ++c)
+        for (int k = 0; k < 5; ++k) dU[k * N + c] = rhs[k * N + c] / diag[c];
+    for (int sweep = 0; sweep < p->relax_sweeps; ++sweep) {
+        memcpy(prev, dU, sizeof(double) * 5 * N);
+        memcpy(acc, rhs, sizeof(double) * 5 * N);
+        for (int64_t j = 0; j < L->m; ++j) {
+            const double *A = &L->A[3 * j];
+            const double S = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+            if (S == 0) continue;
+            const int64_t ab[2] = {L->a[j], L->b[j]};
+            for (int side = 0; side < 2; ++side) {
+                /* cell i = ab[side] with outward normal +-A/S, neighbour p = ab[1 - side] */
+                const int64_t i = ab[side], nb = ab[1 - side];
+                const double sg = side == 0 ? 1.0 : -1.0;
+                const double n[3] = {sg * A[0] / S, sg * A[1] / S, sg * A[2] / S};
+                double Up[5], Un[5], F1[5], F0[5];
+                for (int k = 0; k < 5; ++k) {
+                    Up[k] = W[k * N + nb];
+                    Un[k] = Up[k] + prev[k * N + nb];
+                }
+                euler_flux_n(Un, n, p->gamma, F1);
+                euler_flux_n(Up, n, p->gamma, F0);
+                for (int k = 0; k < 5; ++k)
+                    acc[k * N + i] -= 0.5 * ((F1[k] - F0[k]) - lam[j] * prev[k * N + nb]) * S;
+            }
+        }
+        for (int64_t c = 0; c < N; ++c)
+            for (int k = 0; k < 5; ++k) dU[k * N + c] = acc[k * N + c] / diag[c];
+    }
+    free(dt);
+    free(diag);
+    free(lam);
+    free(prev);
+    free(acc);
+}
+
+/* one coarse sweep: W += dt/V (R + F) (forward Euler) or W += dU of the implicit smoother */
+static void coarse_sweep(const om_hier *h, int l, const om_params *p, const double *F, double *W)
+{
+    const int64_t N = h->lev[l].n;
+    double *R = malloc(sizeof(double) * 5 * N), *dt = malloc(sizeof(double) * N);
+    om_kfvs_residual(h, l, p, W, R);
+    if (p->coarse_smoother == 1) {
+        double *dU = malloc(sizeof(double) * 5 * N);
+        for (int64_t i = 0; i < 5 * N; ++i) R[i] += F[i];
+        om_coarse_implicit(h, l, p, W, R, dU);
+        for (int64_t i = 0; i < 5 * N; ++i) W[i] += dU[i];
+        free(dU);
+    } else {
+        om_coarse_dt(h, l, p, W, dt);
+        for (int64_t c = 0; c < N; ++c)
+            for (int k = 0; k < 5; ++k) W[k * N + c] += dt[c] / h->lev[l].V[c] * (R[k * N + c] + F[k * N + c]);
+    }
+    free(R);
+    free(dt);
+}
+
 typedef struct {
     int nu_pre[8], nu_post[8];
 } om_cycle;
@@ -378,16 +524,11 @@ static void coarse_visit(const om_hier *h, int l, const om_params *p, const om_c
 {
     const int64_t N = h->lev[l].n;
     double *R0 = malloc(sizeof(double) * 5 * N), *F = malloc(sizeof(double) * 5 * N);
-    double *R = malloc(sizeof(double) * 5 * N), *dt = malloc(sizeof(double) * N);
+    double *R = malloc(sizeof(double) * 5 * N);
     om_kfvs_residual(h, l, p, W0, R0);
     for (int64_t i = 0; i < 5 * N; ++i) F[i] = Rs[i] - R0[i];
     memcpy(W, W0, sizeof(double) * 5 * N);
-    for (int s = 0; s < cy->nu_pre[l]; ++s) {
-        om_kfvs_residual(h, l, p, W, R);
-        om_coarse_dt(h, l, p, W, dt);
-        for (int64_t c = 0; c < N; ++c)
-            for (int k = 0; k < 5; ++k) W[k * N + c] += dt[c] / h->lev[l].V[c] * (R[k * N + c] + F[k * N + c]);
-    }
+    for (int s = 0; s < cy->nu_pre[l]; ++s) coarse_sweep(h, l, p, F, W);
     if (l + 1 < h->nlev) {
         const int64_t Nc = h->lev[l + 1].n;
         om_kfvs_residual(h, l, p, W, R);
@@ -402,16 +543,10 @@ static void coarse_visit(const om_hier *h, int l, const om_params *p, const om_c
         free(Rc);
         free(Wc);
     }
-    for (int s = 0; s < cy->nu_post[l]; ++s) {
-        om_kfvs_residual(h, l, p, W, R);
-        om_coarse_dt(h, l, p, W, dt);
-        for (int64_t c = 0; c < N; ++c)
-            for (int k = 0; k < 5; ++k) W[k * N + c] += dt[c] / h->lev[l].V[c] * (R[k * N + c] + F[k * N + c]);
-    }
+    for (int s = 0; s < cy->nu_post[l]; ++s) coarse_sweep(h, l, p, F, W);
     free(R0);
     free(F);
     free(R);
-    free(dt);
 }
 
 /*
