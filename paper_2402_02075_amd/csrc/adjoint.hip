@@ -333,8 +333,8 @@ __global__ __launch_bounds__(256) void k_coef_gather(int64_t N, const int32_t *c
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 5 * N) return;
-    const int c = (int)(t / N);
-    const int64_t i = t - (int64_t)c * N;
+    const int64_t i = t / 5;  // the five component threads of a cell are neighbouring lanes
+    const int c = (int)(t - 5 * i);
     double b[10];
 #pragma unroll
     for (int j = 0; j < 10; ++j) b[j] = 0.0;

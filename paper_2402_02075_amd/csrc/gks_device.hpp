@@ -49,18 +49,26 @@ CGKS_HD double powc_(double x, double e) { return ::pow(x, e); }
 
 template <class T> struct Side {
     T rho, U, V, W, lam;
+    T ir;  // 1/rho
+    T p;   // pressure
+    T h;   // 1/(2 lambda) = p/rho
 };
 
+// Primitive quantities of a conservative state.  rho p = (gamma - 1)(rho E - |m|^2/2) needs no
+// division, and the one reciprocal 1/(rho^2 p) yields both 1/rho and lambda = rho/(2p).
 template <class T> CGKS_HD Side<T> side_of(const T w[5], T gam)
 {
     Side<T> s;
     s.rho = w[0];
-    const T ir = T(1) / w[0];
-    s.U = w[1] * ir;
-    s.V = w[2] * ir;
-    s.W = w[3] * ir;
-    const T p = (gam - T(1)) * (w[4] - T(0.5) * w[0] * (s.U * s.U + s.V * s.V + s.W * s.W));
-    s.lam = T(0.5) * w[0] / p;
+    const T rp = (gam - T(1)) * (w[4] * w[0] - T(0.5) * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]));
+    const T d = T(1) / (w[0] * rp);
+    s.ir = rp * d;
+    s.U = w[1] * s.ir;
+    s.V = w[2] * s.ir;
+    s.W = w[3] * s.ir;
+    s.p = rp * s.ir;
+    s.h = s.p * s.ir;
+    s.lam = T(0.5) * (w[0] * w[0]) * w[0] * d;
     return s;
 }
 
@@ -78,7 +86,7 @@ template <class T> CGKS_HD void recur(T *m, T U, T h)
 
 template <class T> CGKS_HD void tab_vw(Tab<T> &t, const Side<T> &s, T K)
 {
-    const T h = T(0.5) / s.lam;
+    const T h = s.h;
     t.v[0] = T(1);
     t.v[1] = s.V;
     recur(t.v, s.V, h);
@@ -94,16 +102,17 @@ template <class T> CGKS_HD void tab_u_full(Tab<T> &t, const Side<T> &s)
 {
     t.u[0] = T(1);
     t.u[1] = s.U;
-    recur(t.u, s.U, T(0.5) / s.lam);
+    recur(t.u, s.U, s.h);
 }
 
 // half space: sgn = +1 for u > 0, -1 for u < 0
 template <class T> CGKS_HD void tab_u_half(Tab<T> &t, const Side<T> &s, T sgn)
 {
-    const T sl = Fp<T>::sqrt_(s.lam);
+    const T isl = Fp<T>::sqrt_(T(2) * s.h);  // 1/sqrt(lambda)
+    const T sl = s.lam * isl;                // sqrt(lambda)
     t.u[0] = T(0.5) * Fp<T>::erfc_(-sgn * sl * s.U);
-    t.u[1] = s.U * t.u[0] + sgn * T(0.5) * Fp<T>::exp_(-s.lam * s.U * s.U) * T(CGKS_RSQRT_PI) / sl;
-    recur(t.u, s.U, T(0.5) / s.lam);
+    t.u[1] = s.U * t.u[0] + sgn * T(0.5) * Fp<T>::exp_(-s.lam * s.U * s.U) * T(CGKS_RSQRT_PI) * isl;
+    recur(t.u, s.U, s.h);
 }
 
 // <u^n v^m w^k psi_a>, a = 0..4
@@ -118,16 +127,28 @@ template <int n, int m, int k, class T> CGKS_HD void mpsi(const Tab<T> &t, T o[5
     o[4] = T(0.5) * (t.u[n + 2] * vw + t.u[n] * (t.v[m + 2] * t.w[k] + t.v[m] * t.w[k + 2]) + uvw * t.x[1]);
 }
 
-// Solve M a = b for a micro-slope, M = <psi psi^T> of the normalised Maxwellian (closed form).
-template <class T> CGKS_HD void slope_solve(const Side<T> &s, T K, const T b[5], T a[5])
+// Constants of the closed-form inverse for one Maxwellian: e = |U|^2 + (K + 3)/(2 lambda) and
+// c4 = 4 lambda^2/(K + 3), given iK3 = 1/(K + 3).
+template <class T> struct SlopeK {
+    T e, c4;
+};
+template <class T> CGKS_HD SlopeK<T> slope_k(const Side<T> &s, T K, T iK3)
 {
-    const T q2 = s.U * s.U + s.V * s.V + s.W * s.W;
-    const T e = q2 + (K + T(3)) / (T(2) * s.lam);
+    SlopeK<T> k;
+    k.e = s.U * s.U + s.V * s.V + s.W * s.W + (K + T(3)) * s.h;
+    k.c4 = T(4) * s.lam * s.lam * iK3;
+    return k;
+}
+
+// Solve M a = b for a micro-slope, M = <psi psi^T> of the normalised Maxwellian (closed form).
+template <class T> CGKS_HD void slope_solve(const Side<T> &s, const SlopeK<T> &k, const T b[5], T a[5])
+{
+    const T e = k.e;
     const T R1 = b[1] - s.U * b[0];
     const T R2 = b[2] - s.V * b[0];
     const T R3 = b[3] - s.W * b[0];
     const T R4 = T(2) * b[4] - e * b[0];
-    a[4] = T(4) * s.lam * s.lam / (K + T(3)) * (R4 - T(2) * (s.U * R1 + s.V * R2 + s.W * R3));
+    a[4] = k.c4 * (R4 - T(2) * (s.U * R1 + s.V * R2 + s.W * R3));
     a[1] = T(2) * s.lam * R1 - s.U * a[4];
     a[2] = T(2) * s.lam * R2 - s.V * a[4];
     a[3] = T(2) * s.lam * R3 - s.W * a[4];
@@ -187,15 +208,15 @@ template <class T> CGKS_HD void mcol0_acc(const T m[15], T s, T y[5])
 // Space slopes a_j from local-frame gradients g[j][c], and the full-space transport moment
 // tr = sum_j <u_j a_j psi> (so that the time slope solves M A = -tr).
 template <class T>
-CGKS_HD void slopes(const Side<T> &s, const Tab<T> &full, T K, const T g[3][5], T a[3][5], T A[5], T tr[5])
+CGKS_HD void slopes(const Side<T> &s, const Tab<T> &full, T K, T iK3, const T g[3][5], T a[3][5], T A[5], T tr[5])
 {
-    const T ir = T(1) / s.rho;
+    const SlopeK<T> k = slope_k(s, K, iK3);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         T b[5];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) b[c] = g[j][c] * ir;
-        slope_solve(s, K, b, a[j]);
+        for (int c = 0; c < 5; ++c) b[c] = g[j][c] * s.ir;
+        slope_solve(s, k, b, a[j]);
     }
 #pragma unroll
     for (int c = 0; c < 5; ++c) tr[c] = T(0);
@@ -209,7 +230,7 @@ CGKS_HD void slopes(const Side<T> &s, const Tab<T> &full, T K, const T g[3][5], 
     T b[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) b[c] = -tr[c];
-    slope_solve(s, K, b, A);
+    slope_solve(s, k, b, A);
 }
 
 struct GksCfg {
@@ -235,6 +256,7 @@ CGKS_HD bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T
 {
     const Side<T> sl = side_of(wl, gam), sr = side_of(wr, gam);
     if (!(sl.rho > T(0) && sr.rho > T(0) && sl.lam > T(0) && sr.lam > T(0))) return false;
+    const T iK3 = T(1) / (K + T(3));
     T Wc[5] = {T(0), T(0), T(0), T(0), T(0)};
     T dWc[3][5];
 #pragma unroll
@@ -254,7 +276,7 @@ CGKS_HD bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T
         tab_vw(t, s, K);
         tab_u_full(t, s);
         T a[3][5], A[5], tr[5];
-        slopes(s, t, K, g, a, A, tr);
+        slopes(s, t, K, iK3, g, a, A, tr);
         tab_u_half(t, s, side == 0 ? T(1) : T(-1));
         const T rho = s.rho;
         T m[15];
@@ -288,7 +310,7 @@ CGKS_HD bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T
         tab_vw(t, sc, K);
         tab_u_full(t, sc);
         T a[3][5], A[5], tr[5];
-        slopes(sc, t, K, dWc, a, A, tr);
+        slopes(sc, t, K, iK3, dWc, a, A, tr);
         const T rho = sc.rho;
         T m[15];
 #pragma unroll
@@ -311,9 +333,9 @@ CGKS_HD bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T
     o.Uc[0] = sc.U;
     o.Uc[1] = sc.V;
     o.Uc[2] = sc.W;
-    o.pl = sl.rho / (T(2) * sl.lam);
-    o.pr = sr.rho / (T(2) * sr.lam);
-    o.pc = sc.rho / (T(2) * sc.lam);
+    o.pl = sl.p;
+    o.pr = sr.p;
+    o.pc = sc.p;
     return true;
 }
 
@@ -341,9 +363,10 @@ template <class T> CGKS_HD TimeCoef<T> coef_integrated(T Tt, T tau, T taun)
 
 template <class T> CGKS_HD TimeCoef<T> coef_at(T t, T tau, T taun)
 {
-    const T e = Fp<T>::exp_(-t / taun);
+    const T x = t / taun;
+    const T e = Fp<T>::exp_(-x);
     TimeCoef<T> c;
-    c.c1 = -Fp<T>::expm1_(-t / taun);
+    c.c1 = -Fp<T>::expm1_(-x);
     c.c2 = (t + tau) * e - tau;
     c.c3 = t - tau + tau * e;
     c.e = e;
@@ -482,14 +505,12 @@ CGKS_HD void to_global(const T l[5], const Gm n[3], const Gm t1[3], const Gm t2[
 template <class T, class S>
 CGKS_HD S cf_factor(const T wl[5], const T wr[5], S pl, S pr, S gam)
 {
-    const S rl = S(wl[0]), rr = S(wr[0]);
-    const S cl = Fp<S>::sqrt_(gam * pl / rl), cr = Fp<S>::sqrt_(gam * pr / rr);
-    const S unl = S(wl[1]) / rl, unr = S(wr[1]) / rr;
-    const S vtl = Fp<S>::sqrt_(S(wl[2]) * S(wl[2]) + S(wl[3]) * S(wl[3])) / rl;
-    const S vtr = Fp<S>::sqrt_(S(wr[2]) * S(wr[2]) + S(wr[3]) * S(wr[3])) / rr;
-    const S dp = abs_(pl - pr);
-    const S dmn = unl / cl - unr / cr, dmt = vtl / cl - vtr / cr;
-    const S A = dp / pl + dp / pr + dmn * dmn + dmt * dmt;
+    // a Mach number is |m|/(rho c) with rho c = sqrt(gamma p rho); |dp|/p_l + |dp|/p_r = |dp| (p_l + p_r)/(p_l p_r)
+    const S il = S(1) / Fp<S>::sqrt_(gam * pl * S(wl[0])), ir = S(1) / Fp<S>::sqrt_(gam * pr * S(wr[0]));
+    const S mtl = Fp<S>::sqrt_(S(wl[2]) * S(wl[2]) + S(wl[3]) * S(wl[3]));
+    const S mtr = Fp<S>::sqrt_(S(wr[2]) * S(wr[2]) + S(wr[3]) * S(wr[3]));
+    const S dmn = S(wl[1]) * il - S(wr[1]) * ir, dmt = mtl * il - mtr * ir;
+    const S A = abs_(pl - pr) * (pl + pr) / (pl * pr) + dmn * dmn + dmt * dmt;
     return S(1) / (S(1) + A * A);
 }
 
