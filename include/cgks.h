@@ -69,6 +69,10 @@ typedef struct {
     int32_t nu_post[8];  /* post-smoothing sweeps per level (0) */
     double mixed_switch; /* mixed precision: FP64 flux once the residual drop is below this (1e-6) */
     uint64_t seed;       /* hash seed multiplier s (1 reproduces the paper's hash) */
+    int32_t coarse_smoother; /* coarse levels: 0 forward Euler (default), 1 implicit backward Euler
+                                with point relaxation (paper Sec. 4.3) */
+    int32_t relax_sweeps;    /* relaxation sweeps of the implicit coarse smoother (2) */
+    double cfl_implicit;     /* CFL number of the implicit coarse smoother's local step (2.0) */
 } cgks_params;
 
 /* Fill *p with the defaults above. */
@@ -246,6 +250,18 @@ cgks_status cgks_level_map(cgks_ctx *ctx, int32_t level, int32_t *f2c);
 /* Coarse KFVS residual on level >= 1 (paper Secs. 1, 4.2): R = - sum S n.F_kfvs. Device W, R (5 N_l),
  * FP64; with precision 1 the operator is evaluated in FP32 (as on the coarse levels of the mixed cycle). */
 cgks_status cgks_kfvs_residual(cgks_ctx *ctx, int32_t level, const double *W, double *R);
+
+/* Increment of the implicit coarse smoother on level >= 1 (paper Sec. 4.3): backward Euler
+ * linearised with the Lax-Friedrichs flux Jacobian A+- = (A +- lambda I)/2, solved without a
+ * matrix by params.relax_sweeps point-relaxation (Jacobi) sweeps after dU = rhs/D:
+ *   (|Omega_i|/dt_i + 1/2 sum_p lambda_p S_p) dU_i + sum_p [F-(U_p + dU_p) - F-(U_p)] S_p = rhs_i,
+ *   F- = (F_n - lambda U)/2, lambda = max of the two cells' |U.n| + c + 2 mu S/(rho |Omega|),
+ * dt_i the coarse local step at params.cfl_implicit, S the coarse face's |A|; a boundary face adds
+ * lambda S/2 (owner vs ghost state) to the diagonal and no neighbour term.
+ * W, rhs, dU: device [5][N_l] FP64, dU overwritten; with precision 1 evaluated in FP32.
+ * The V-cycle uses it on every coarse sweep when params.coarse_smoother = 1, with rhs =
+ * Res_2h(W) + F (the FAS right-hand side) and W += dU. */
+cgks_status cgks_coarse_implicit(cgks_ctx *ctx, int32_t level, const double *W, const double *rhs, double *dU);
 
 /* Restriction to level >= 1 (paper Sec. 4.2): Wc = sum V W / Vc, Rc = sum R (either pair nullable). */
 cgks_status cgks_restrict(cgks_ctx *ctx, int32_t level, const double *Wf, const double *Rf, double *Wc, double *Rc);

@@ -23,7 +23,7 @@ EXPORTS = ["cgks_default_params", "cgks_create", "cgks_destroy", "cgks_last_erro
            "cgks_reconstruct", "cgks_residual", "cgks_step", "cgks_check", "cgks_residual_norm",
            "cgks_agglomerate_graph", "cgks_agglomerate", "cgks_level_map", "cgks_kfvs_residual", "cgks_restrict",
            "cgks_prolong", "cgks_vcycle", "cgks_timing", "cgks_wall_force", "cgks_linearize", "cgks_vjp_residual",
-           "cgks_vjp_wall_force", "cgks_vjp_kfvs", "cgks_adjoint_solve"]
+           "cgks_vjp_wall_force", "cgks_vjp_kfvs", "cgks_adjoint_solve", "cgks_coarse_implicit"]
 
 
 class Params(C.Structure):
@@ -31,7 +31,8 @@ class Params(C.Structure):
                 ("eps_tau", C.c_double), ("c_tau", C.c_double), ("weno_eps", C.c_double), ("gamma_lin", C.c_double),
                 ("skew_delta", C.c_double), ("skew_sin", C.c_double), ("viscous", C.c_int32), ("levels", C.c_int32),
                 ("passes", C.c_int32), ("precision", C.c_int32), ("nu_pre", C.c_int32 * 8),
-                ("nu_post", C.c_int32 * 8), ("mixed_switch", C.c_double), ("seed", C.c_uint64)]
+                ("nu_post", C.c_int32 * 8), ("mixed_switch", C.c_double), ("seed", C.c_uint64),
+                ("coarse_smoother", C.c_int32), ("relax_sweeps", C.c_int32), ("cfl_implicit", C.c_double)]
 
 
 class CgksError(RuntimeError):
@@ -63,6 +64,7 @@ def lib():
             "cgks_wall_force": [P, P, P, P, I32, P], "cgks_linearize": [P, P, P, P],
             "cgks_vjp_residual": [P, P, P, P, P, P, P], "cgks_vjp_wall_force": [P, I32, P, P, P, P],
             "cgks_vjp_kfvs": [P, I32, P, P, P], "cgks_adjoint_solve": [P, I32, P, I32, D, P, P, P, P, P, P, P, P],
+            "cgks_coarse_implicit": [P, I32, P, P, P],
         }
         for name, args in sig.items():
             if not hasattr(L, name):
@@ -285,6 +287,12 @@ class Solver:
         R = self.empty(5, self.level_sizes[level])
         self._check(lib().cgks_kfvs_residual(self.h, int(level), _ptr(W), _ptr(R)))
         return R
+
+    def coarse_implicit(self, level, W, rhs):
+        """Increment of the implicit coarse smoother (Sec. 4.3) on `level` at state W for rhs."""
+        dU = self.empty(5, self.level_sizes[level])
+        self._check(lib().cgks_coarse_implicit(self.h, int(level), _ptr(W), _ptr(rhs), _ptr(dU)))
+        return dU
 
     def restrict(self, level, Wf, Rf):
         n = self.level_sizes[level]

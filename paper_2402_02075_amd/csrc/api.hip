@@ -49,6 +49,9 @@ static void check_params(const cgks_params *p)
     if (p->levels < 1 || p->levels > 8) throw Error{CGKS_E_ARG, "levels must be in 1..8"};
     if (p->passes < 0 || p->passes > 16) throw Error{CGKS_E_ARG, "passes must be in 0..16"};
     if (p->precision != 0 && p->precision != 1) throw Error{CGKS_E_ARG, "precision must be 0 or 1"};
+    if (p->coarse_smoother != 0 && p->coarse_smoother != 1) throw Error{CGKS_E_ARG, "coarse_smoother must be 0 or 1"};
+    if (p->relax_sweeps < 0 || p->relax_sweeps > 64) throw Error{CGKS_E_ARG, "relax_sweeps must be in 0..64"};
+    if (p->coarse_smoother == 1 && !(p->cfl_implicit > 0.0)) throw Error{CGKS_E_ARG, "cfl_implicit must be positive"};
 }
 
 static void check_bad(cgks_ctx *c)
@@ -90,6 +93,9 @@ cgks_status cgks_default_params(cgks_params *p)
     }
     p->mixed_switch = 1e-6;
     p->seed = 1;
+    p->coarse_smoother = 0;
+    p->relax_sweeps = 2;
+    p->cfl_implicit = 2.0;
     return CGKS_OK;
 }
 
@@ -405,6 +411,19 @@ cgks_status cgks_kfvs_residual(cgks_ctx *c, int32_t level, const double *W, doub
     if (!W || !R) throw Error{CGKS_E_ARG, "null pointer"};
     if (c->prm.precision == 1) kfvs_residual_fp32(c, level, W, R);
     else kfvs_residual(c, level, W, R);
+    CGKS_HIP(hipGetLastError());
+    API_END(c)
+}
+
+cgks_status cgks_coarse_implicit(cgks_ctx *c, int32_t level, const double *W, const double *rhs, double *dU)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    level_at(c, level);
+    if (!W || !rhs || !dU) throw Error{CGKS_E_ARG, "null pointer"};
+    if (!(c->prm.cfl_implicit > 0.0)) throw Error{CGKS_E_ARG, "cfl_implicit must be positive"};
+    if (c->prm.precision == 1) coarse_implicit_fp32(c, level, W, rhs, dU);
+    else coarse_implicit(c, level, W, rhs, dU);
     CGKS_HIP(hipGetLastError());
     API_END(c)
 }

@@ -444,6 +444,7 @@ void build_cell_items(Level *L, const std::vector<int32_t> &pa, const std::vecto
         item[ptr[pb[j]] + fill[pb[j]]++] = (int32_t)(2 * j + 1);
     }
     for (int64_t k = 0; k < nb; ++k) item[ptr[bown[k]] + fill[bown[k]]++] = (int32_t)(-(k + 1));
+    L->nnz = ptr[n];
     L->cf_ptr.upload(ptr, st);
     L->cf_item.upload(item, st);
 }
@@ -882,11 +883,12 @@ void kfvs_residual_fp32(cgks_ctx *c, int level, const double *W, double *R)
     hipLaunchKernelGGL((k_convert<float, double>), G1(n5), dim3(256), 0, c->stream, n5, L->Rf.p, R);
 }
 
-template <class T> static void coarse_dt_impl(cgks_ctx *c, int level, const T *W, T *dt)
+template <class T> static void coarse_dt_impl(cgks_ctx *c, int level, const T *W, T *dt, double cfl = -1.0)
 {
     Level *L = level_of(c, level);
-    hipLaunchKernelGGL((k_coarse_dt<T>), GR(L->n), dim3(256), 0, c->stream, L->n, L->m, L->nb, c->prm.gamma, c->prm.cfl,
-                       c->prm.mu, c->prm.viscous, W, L->cf_ptr.p, L->cf_item.p, L->S.p, L->A.p, L->bA.p, L->V.p, dt);
+    hipLaunchKernelGGL((k_coarse_dt<T>), GR(L->n), dim3(256), 0, c->stream, L->n, L->m, L->nb, c->prm.gamma,
+                       cfl > 0.0 ? cfl : c->prm.cfl, c->prm.mu, c->prm.viscous, W, L->cf_ptr.p, L->cf_item.p, L->S.p,
+                       L->A.p, L->bA.p, L->V.p, dt);
 }
 
 void coarse_dt_level(cgks_ctx *c, int level, const double *W, double *dt) { coarse_dt_impl<double>(c, level, W, dt); }
@@ -908,6 +910,247 @@ void prolong_level(cgks_ctx *c, int level, const double *dWc, double *Wf)
     Level *L = level_of(c, level);
     hipLaunchKernelGGL((k_prolong<double, double>), G1(L->nfine), dim3(256), 0, c->stream, L->nfine, L->n, L->f2c.p,
                        dWc, (const double *)nullptr, Wf);
+}
+
+// ---------------------------------------------------------------- implicit coarse smoother
+// Backward Euler on a coarse level (paper Sec. 4.3), linearised with the Jacobian of a
+// first-order Lax-Friedrichs flux, A+- = (A +- lambda I)/2, lambda = max(lambda_i, lambda_p),
+// lambda = |U.n| + c + 2 mu S/(rho |Omega|).  The outward area vectors of a closed cell sum to
+// zero, so the diagonal is |Omega_i|/dt_i + sum_p lambda_p S_p / 2; the neighbour products are
+// formed without a matrix as F-(U_p + dU_p) - F-(U_p), F- = (F_n - lambda U)/2 with F_n the Euler
+// flux along cell i's outward normal.  The system is solved by point relaxation: dU = rhs/D, then
+// each sweep recomputes every cell from the previous sweep's neighbour increments (Jacobi order,
+// so every cell of a sweep is independent and the result does not depend on the schedule).
+// S is the coarse face's |A|, the factor of its KFVS flux.  A boundary face adds lambda S/2 with
+// lambda the larger radius of owner and ghost state; its ghost increment is zero.
+// One row of the cell -> face list per RG lanes, as in the KFVS gather.
+template <class T> __device__ __forceinline__ void euler_flux_n(const T U[5], const double n[3], double gam, T F[5])
+{
+    const T ir = T(1) / U[0];
+    const T un = (U[1] * T(n[0]) + U[2] * T(n[1]) + U[3] * T(n[2])) * ir;
+    const T pr = T(gam - 1.0) * (U[4] - T(0.5) * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * ir);
+    F[0] = U[0] * un;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) F[1 + d] = U[1 + d] * un + pr * T(n[d]);
+    F[4] = (U[4] + pr) * un;
+}
+
+template <class T>
+__device__ __forceinline__ T spec_radius(const T U[5], const double n[3], double S, double V, double gam, double mu,
+                                         int viscous)
+{
+    const T ir = T(1) / U[0];
+    const T un = (U[1] * T(n[0]) + U[2] * T(n[1]) + U[3] * T(n[2])) * ir;
+    const T pr = T(gam - 1.0) * (U[4] - T(0.5) * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * ir);
+    const T c = Fp<T>::sqrt_(T(gam) * pr * ir);
+    return abs_(un) + c + (viscous ? T(2.0 * mu * S / V) * ir : T(0));
+}
+
+template <class T> struct ImpArgs {
+    int64_t n, m, nb;
+    double gam, mu;
+    int viscous;
+    const T *W, *rhs, *dt;
+    const int32_t *ptr, *item, *pa, *pb, *btag;
+    const double *A, *bA, *V;  // pair area vectors [3][m], boundary area vectors [3][nb], volumes
+    const BcTable *bc;
+    T *lamS;       // per cell-face entry: lambda S / 2 (0 for a face of zero area)
+    T *dg;         // diagonal per cell
+    const T *din;  // previous iterate (sweeps)
+    T *dout;       // increment written, or added when acc = 1
+    int acc;
+};
+
+template <class T> __device__ __forceinline__ void load5(const T *W, int64_t n, int64_t i, T u[5])
+{
+#pragma unroll
+    for (int q = 0; q < 5; ++q) u[q] = W[q * n + i];
+}
+
+// Diagonal, lambda S / 2 per entry and the first iterate dU = rhs / D.
+template <class T> __global__ __launch_bounds__(256) void k_imp_diag(ImpArgs<T> a)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / RG;
+    const int g = (int)(t % RG);
+    if (i >= a.n) return;  // whole row groups leave together
+    const int64_t n = a.n;
+    T Ui[5];
+    load5(a.W, n, i, Ui);
+    const double Vi = a.V[i];
+    T sum = T(0);
+    for (int k = a.ptr[i] + g; k < a.ptr[i + 1]; k += RG) {
+        const int it = a.item[k];
+        double av[3];
+        if (it >= 0) {
+            const int j = it >> 1;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) av[d] = a.A[d * a.m + j];
+        } else {
+            const int q = -it - 1;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) av[d] = a.bA[d * a.nb + q];
+        }
+        const double S = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
+        T h = T(0);
+        if (S > 0.0) {
+            const double nv[3] = {av[0] / S, av[1] / S, av[2] / S};
+            T Up[5];
+            double Vp = Vi;
+            if (it >= 0) {
+                const int j = it >> 1;
+                const int p = (it & 1) ? a.pa[j] : a.pb[j];
+                load5(a.W, n, p, Up);
+                Vp = a.V[p];
+            } else {
+                ghost_state(*a.bc, a.btag[-it - 1], nv, Ui, a.gam, Up);
+            }
+            const T li = spec_radius(Ui, nv, S, Vi, a.gam, a.mu, a.viscous);
+            const T lp = spec_radius(Up, nv, S, Vp, a.gam, a.mu, a.viscous);
+            h = T(0.5) * (li > lp ? li : lp) * T(S);
+        }
+        a.lamS[k] = h;
+        sum += h;
+    }
+    sum = row_sum(sum);
+    if (g == 0) {
+        const T d = T(Vi) / a.dt[i] + sum;
+        a.dg[i] = d;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const T v = a.rhs[q * n + i] / d;
+            a.dout[q * n + i] = a.acc ? a.dout[q * n + i] + v : v;
+        }
+    }
+}
+
+// One point-relaxation sweep: dU_i = (rhs_i - sum_p [F-(U_p + dU_p) - F-(U_p)] S_p) / D_i.
+template <class T> __global__ __launch_bounds__(256) void k_imp_sweep(ImpArgs<T> a)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / RG;
+    const int g = (int)(t % RG);
+    if (i >= a.n) return;  // whole row groups leave together
+    const int64_t n = a.n;
+    T r[5] = {T(0), T(0), T(0), T(0), T(0)};
+    for (int k = a.ptr[i] + g; k < a.ptr[i + 1]; k += RG) {
+        const int it = a.item[k];
+        if (it < 0) continue;  // boundary: zero ghost increment
+        const T h = a.lamS[k];
+        if (h == T(0)) continue;  // face of zero area
+        const int j = it >> 1;
+        const int p = (it & 1) ? a.pa[j] : a.pb[j];
+        const double sg = (it & 1) ? -1.0 : 1.0;  // outward normal of cell i
+        double av[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) av[d] = a.A[d * a.m + j];
+        const double S = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
+        const double nv[3] = {sg * av[0] / S, sg * av[1] / S, sg * av[2] / S};
+        T Up[5], dp[5], Un[5], F1[5], F0[5];
+        load5(a.W, n, p, Up);
+        load5(a.din, n, p, dp);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) Un[q] = Up[q] + dp[q];
+        euler_flux_n(Un, nv, a.gam, F1);
+        euler_flux_n(Up, nv, a.gam, F0);
+        const T hS = T(0.5 * S);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) r[q] += hS * (F1[q] - F0[q]) - h * dp[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) r[q] = row_sum(r[q]);
+    if (g == 0) {
+        const T d = a.dg[i];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const T v = (a.rhs[q * n + i] - r[q]) / d;
+            a.dout[q * n + i] = a.acc ? a.dout[q * n + i] + v : v;
+        }
+    }
+}
+
+template <class T> struct ImpBufs {
+    T *lamS, *dg, *dUa, *dUb, *dt;
+};
+template <class T> static ImpBufs<T> imp_bufs(Level *L);
+template <> ImpBufs<double> imp_bufs<double>(Level *L)
+{
+    L->lamS.ensure(L->nnz + 1);
+    L->dg.ensure(L->n);
+    L->dUa.ensure(5 * L->n);
+    L->dUb.ensure(5 * L->n);
+    L->dt.ensure(L->n);
+    return {L->lamS.p, L->dg.p, L->dUa.p, L->dUb.p, L->dt.p};
+}
+template <> ImpBufs<float> imp_bufs<float>(Level *L)
+{
+    L->lamSf.ensure(L->nnz + 1);
+    L->dgf.ensure(L->n);
+    L->dUaf.ensure(5 * L->n);
+    L->dUbf.ensure(5 * L->n);
+    L->dtf.ensure(L->n);
+    return {L->lamSf.p, L->dgf.p, L->dUaf.p, L->dUbf.p, L->dtf.p};
+}
+
+// out = dU (acc = false) or out += dU (acc = true), dU the implicit increment at state W for rhs.
+template <class T> static void implicit_solve(cgks_ctx *c, int l, const T *W, const T *rhs, T *out, bool acc)
+{
+    Level *L = level_of(c, l);
+    ImpBufs<T> b = imp_bufs<T>(L);
+    coarse_dt_impl<T>(c, l, W, b.dt, c->prm.cfl_implicit);
+    ImpArgs<T> a;
+    a.n = L->n;
+    a.m = L->m;
+    a.nb = L->nb;
+    a.gam = c->prm.gamma;
+    a.mu = c->prm.mu;
+    a.viscous = c->prm.viscous;
+    a.W = W;
+    a.rhs = rhs;
+    a.dt = b.dt;
+    a.ptr = L->cf_ptr.p;
+    a.item = L->cf_item.p;
+    a.pa = L->pa.p;
+    a.pb = L->pb.p;
+    a.btag = L->btag.p;
+    a.A = L->A.p;
+    a.bA = L->bA.p;
+    a.V = L->V.p;
+    a.bc = c->bc.p;
+    a.lamS = b.lamS;
+    a.dg = b.dg;
+    const int sweeps = c->prm.relax_sweeps;
+    T *cur = b.dUa, *nxt = b.dUb;
+    a.din = nullptr;
+    a.dout = sweeps == 0 ? out : cur;
+    a.acc = sweeps == 0 && acc;
+    hipLaunchKernelGGL((k_imp_diag<T>), GR(L->n), dim3(256), 0, c->stream, a);
+    for (int s = 1; s <= sweeps; ++s) {
+        a.din = cur;
+        a.dout = s == sweeps ? out : nxt;
+        a.acc = s == sweeps && acc;
+        hipLaunchKernelGGL((k_imp_sweep<T>), GR(L->n), dim3(256), 0, c->stream, a);
+        std::swap(cur, nxt);
+    }
+}
+
+void coarse_implicit(cgks_ctx *c, int level, const double *W, const double *rhs, double *dU)
+{
+    implicit_solve<double>(c, level, W, rhs, dU, false);
+}
+
+// FP32 implicit increment of FP64 inputs, returned in FP64 (the mixed-precision coarse smoother)
+void coarse_implicit_fp32(cgks_ctx *c, int level, const double *W, const double *rhs, double *dU)
+{
+    Level *L = level_of(c, level);
+    const int64_t n5 = 5 * L->n;
+    L->Wf.ensure(n5);
+    L->Rf.ensure(n5);
+    L->Df.ensure(n5);
+    hipLaunchKernelGGL((k_convert<double, float>), G1(n5), dim3(256), 0, c->stream, n5, W, L->Wf.p);
+    hipLaunchKernelGGL((k_convert<double, float>), G1(n5), dim3(256), 0, c->stream, n5, rhs, L->Rf.p);
+    implicit_solve<float>(c, level, L->Wf.p, L->Rf.p, L->Df.p, false);
+    hipLaunchKernelGGL((k_convert<float, double>), G1(n5), dim3(256), 0, c->stream, n5, L->Df.p, dU);
 }
 
 // ---------------------------------------------------------------- V-cycle (FP64 and mixed)
@@ -995,19 +1238,29 @@ template <class T> static void coarse_visit(cgks_ctx *c, int l)
     // forcing F = Res* - Res_2h(W0)
     kfvs_impl<T>(c, l, b.W0, b.R, b.ff);
     const int npre = c->prm.nu_pre[l];
-    if (npre > 0) {
+    const bool implicit = c->prm.coarse_smoother == 1;
+    if (npre > 0 && !implicit) {
         coarse_dt_impl<T>(c, l, b.W0, b.dt);
         hipLaunchKernelGGL((k_forcing_first<T>), G1(n), dim3(256), 0, st, n, b.Rs, b.R, b.dt, L->V.p, b.F, b.D);
     } else {
         hipLaunchKernelGGL((k_coarse_forcing<T>), G1(n5), dim3(256), 0, st, n5, b.Rs, b.R, b.F);
-        CGKS_HIP(hipMemsetAsync(b.D, 0, sizeof(T) * n5, st));
+        // the first implicit sweep has W = W0 and right-hand side Res_2h(W0) + F = Res*
+        if (npre > 0) implicit_solve<T>(c, l, b.W0, b.Rs, b.D, false);
+        else CGKS_HIP(hipMemsetAsync(b.D, 0, sizeof(T) * n5, st));
     }
-    for (int s = 1; s < npre; ++s) {
+    // a later sweep at W = W0 + D: forward Euler D += dt/V (Res_2h(W) + F), or D += dU
+    auto sweep = [&]() {
         hipLaunchKernelGGL((k_sum_state<T>), G1(n5), dim3(256), 0, st, n5, b.W0, b.D, b.W);
-        kfvs_impl<T>(c, l, b.W, b.R, b.ff);
-        coarse_dt_impl<T>(c, l, b.W, b.dt);
-        hipLaunchKernelGGL((k_delta_update<T>), G1(n), dim3(256), 0, st, n, b.dt, L->V.p, b.R, b.F, b.D);
-    }
+        if (implicit) {
+            kfvs_impl<T>(c, l, b.W, b.R, b.ff, b.F);
+            implicit_solve<T>(c, l, b.W, b.R, b.D, true);
+        } else {
+            kfvs_impl<T>(c, l, b.W, b.R, b.ff);
+            coarse_dt_impl<T>(c, l, b.W, b.dt);
+            hipLaunchKernelGGL((k_delta_update<T>), G1(n), dim3(256), 0, st, n, b.dt, L->V.p, b.R, b.F, b.D);
+        }
+    };
+    for (int s = 1; s < npre; ++s) sweep();
     if (l + 1 < (int)c->lev.size()) {
         Level *C = c->lev[l + 1];
         LevelBufs<T> cb = bufs<T>(C);
@@ -1019,12 +1272,7 @@ template <class T> static void coarse_visit(cgks_ctx *c, int l)
         hipLaunchKernelGGL((k_prolong<T, T>), G1(C->nfine), dim3(256), 0, st, C->nfine, C->n, C->f2c.p, cb.D,
                            (const T *)nullptr, b.D);
     }
-    for (int s = 0; s < c->prm.nu_post[l]; ++s) {
-        hipLaunchKernelGGL((k_sum_state<T>), G1(n5), dim3(256), 0, st, n5, b.W0, b.D, b.W);
-        kfvs_impl<T>(c, l, b.W, b.R, b.ff);
-        coarse_dt_impl<T>(c, l, b.W, b.dt);
-        hipLaunchKernelGGL((k_delta_update<T>), G1(n), dim3(256), 0, st, n, b.dt, L->V.p, b.R, b.F, b.D);
-    }
+    for (int s = 0; s < c->prm.nu_post[l]; ++s) sweep();
 }
 
 // One V-cycle on the fine state; the norm of the smoothing residual is left in c->scal[0].

@@ -72,6 +72,7 @@ struct BcTable {
 // One coarse level (l >= 1) of the hierarchy.
 struct Level {
     int64_t n = 0, m = 0, nb = 0, nfine = 0;
+    int64_t nnz = 0;                 // entries of the cell -> face list
     DBuf<int32_t> f2c;               // [nfine] from level l-1
     DBuf<int32_t> c2f_ptr, c2f_idx;  // CSR coarse -> fine, fine ids ascending
     DBuf<double> V;                  // [n]
@@ -86,6 +87,9 @@ struct Level {
     DBuf<double> W0, W, D, R, F, Rs, dt, fflux;
     // FP32 work buffers (mixed precision)
     DBuf<float> W0f, Wf, Df, Rf, Ff, Rsf, dtf, ffluxf;
+    // implicit smoother: lambda S / 2 per cell-face entry, diagonal, two relaxation iterates
+    DBuf<double> lamS, dg, dUa, dUb;
+    DBuf<float> lamSf, dgf, dUaf, dUbf;
 };
 
 // Linearisation of the fine operator at one state, kept for repeated
@@ -209,6 +213,8 @@ void build_hierarchy(cgks_ctx *c);
 void kfvs_residual(cgks_ctx *c, int level, const double *W, double *R);
 void kfvs_residual32(cgks_ctx *c, int level, const float *W, float *R);
 void kfvs_residual_fp32(cgks_ctx *c, int level, const double *W, double *R);
+void coarse_implicit(cgks_ctx *c, int level, const double *W, const double *rhs, double *dU);
+void coarse_implicit_fp32(cgks_ctx *c, int level, const double *W, const double *rhs, double *dU);
 void restrict_level(cgks_ctx *c, int level, const double *Wf, const double *Rf, double *Wc, double *Rc);
 void prolong_level(cgks_ctx *c, int level, const double *dWc, double *Wf);
 void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flux, bool fp32_coarse);
