@@ -72,7 +72,7 @@ typedef struct {
     int32_t coarse_smoother; /* coarse levels: 0 forward Euler (default), 1 implicit backward Euler
                                 with point relaxation (paper Sec. 4.3) */
     int32_t relax_sweeps;    /* relaxation sweeps of the implicit coarse smoother (2) */
-    double cfl_implicit;     /* CFL number of the implicit coarse smoother's local step (2.0) */
+    double cfl_implicit;     /* CFL number of the implicit coarse smoother's local step (0.25) */
 } cgks_params;
 
 /* Fill *p with the defaults above. */

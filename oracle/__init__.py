@@ -28,7 +28,7 @@ class OmParams(C.Structure):
 
 
 def params(gamma=1.4, mu=0.0, prandtl=1.0, cfl=0.5, eps_tau=0.01, c_tau=1.0, weno_eps=1e-5, gamma_lin=0.5,
-           viscous=False, coarse_smoother=0, relax_sweeps=2, cfl_implicit=2.0) -> OmParams:
+           viscous=False, coarse_smoother=0, relax_sweeps=2, cfl_implicit=0.25) -> OmParams:
     """coarse_smoother 0: forward Euler on the coarse levels; 1: the implicit smoother of Sec. 4.3."""
     return OmParams(gamma, mu, prandtl, cfl, eps_tau, c_tau, weno_eps, gamma_lin, int(bool(viscous)),
                     int(coarse_smoother), int(relax_sweeps), float(cfl_implicit))

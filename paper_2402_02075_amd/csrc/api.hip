@@ -95,7 +95,7 @@ cgks_status cgks_default_params(cgks_params *p)
     p->seed = 1;
     p->coarse_smoother = 0;
     p->relax_sweeps = 2;
-    p->cfl_implicit = 2.0;
+    p->cfl_implicit = 0.25;
     return CGKS_OK;
 }
 
