@@ -137,6 +137,41 @@ def hex_convergence(cg, mg, max_cycles):
     return res
 
 
+def shock_regime(cg, mg, cycles):
+    """Viscous sphere at Re 300 (on D = 1), Mach 1.2 (bow shock) and 0.95, adiabatic no-slip wall,
+    Riemann far field at r = 20: V-cycles from the free stream on a synthetic 286,720-cell
+    prism/tet sphere (first layer 0.023 D); drop reached, cost per cycle and drag coefficient, with
+    the paper's drag coefficients on its own 665,914-cell meshes as context."""
+    import torch
+    m = mg.sphere_shell(level=4, n_layers=24, n_prism=8, first_h=0.023)
+    res = {"cells": m.n_cells, "mesh": "sphere shell, icosphere level 4, 24 layers (8 prism), r 0.5..20"}
+    paper_cd = {1.2: 1.296, 0.95: 0.963}
+    for mach in (1.2, 0.95):
+        S = cg.Solver(viscous=1, mu=mach / 300.0, prandtl=0.72)
+        S.set_mesh(m)
+        S.set_bc(mg.TAG_SPHERE, cg.BC_NOSLIP_ADIABATIC)
+        S.set_bc(mg.TAG_FARFIELD, cg.BC_FARFIELD, np.array([1.0, mach, 0.0, 0.0, 1.0 / 1.4]))
+        S.agglomerate()
+        W0, G0 = mg.uniform_state(m.n_cells, vel=(mach, 0.0, 0.0))
+        W = torch.from_numpy(W0).cuda()
+        G = torch.from_numpy(G0).cuda()
+        al = torch.ones(m.n_cells, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h, ok = S.vcycle(W, G, al, cycles, 1e-10)
+        torch.cuda.synchronize()
+        dt_c = time.perf_counter() - t0
+        F = S.wall_force(W, G, al, mg.TAG_SPHERE).cpu().numpy()
+        cd = float(F[0] / (0.5 * mach * mach * np.pi / 4.0))
+        res[f"mach_{mach}"] = {"cycles": int(len(h)), "seconds": dt_c, "ms_per_cycle": 1e3 * dt_c / max(len(h), 1),
+                               "final_drop": float(h[-1] / h[0]), "min_drop": float(h.min() / h[0]),
+                               "reached_1e-10": bool(ok), "Cd": cd, "Cd_paper": paper_cd[mach],
+                               "min_alpha": float(al.min())}
+        log(f"sphere Mach {mach}: {len(h)} cycles {dt_c:.2f}s drop {h[-1] / h[0]:.2e} Cd {cd:.4f}")
+        S.close()
+    return res
+
+
 def adjoint_measurements(cg, mg, S, W, G, al):
     """Linearisation and vector-Jacobian-product timings on the benchmark state, and the
     adjoint gradients of the lower-wall x-force against converged finite differences on a
@@ -210,6 +245,8 @@ def main():
     ap.add_argument("--converge", type=int, default=4000, help="max cycles for the time-to-1e-10 runs (0: skip)")
     ap.add_argument("--converge-hex", type=int, default=60000,
                     help="max cycles for the time-to-1e-10 runs on the all-hexahedral channel (0: skip)")
+    ap.add_argument("--shock-cycles", type=int, default=8000,
+                    help="V-cycles of the Mach 1.2 / 0.95 viscous sphere runs (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timings and gradient check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true", help="run a plain 1 GiB copy first (counter scaling)")
@@ -322,6 +359,8 @@ def main():
         out["adjoint"] = adjoint_measurements(cg, mg, S, W, G, al)
     if args.converge_hex:
         out["time_to_1e-10_hex_channel"] = hex_convergence(cg, mg, args.converge_hex)
+    if args.shock_cycles:
+        out["shock_regime_sphere"] = shock_regime(cg, mg, args.shock_cycles)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mg)
     print(json.dumps(out))

@@ -598,6 +598,45 @@ def smooth_state_and_gradients(x: np.ndarray, seed=3, amp=0.05, gamma=1.4):
     return W, G
 
 
+def bow_shock_state(x: np.ndarray, mach=1.2, gamma=1.4, r_shock=1.2, width=0.05, r_wall=0.5, delta=0.05):
+    """Synthetic shock-regime input around a sphere at the origin in a free stream along +x
+    (density 1, sound speed 1): inside r < r_shock on the upstream side the post-shock state of a
+    normal shock at `mach` (Rankine-Hugoniot), outside the free stream, joined by a tanh layer of
+    `width`; the velocity is damped to zero at the wall r = r_wall over `delta`.  Returns W (5, N)
+    and G (15, N), the gradients by central differences of this closed-form field (inputs only)."""
+    m2 = mach * mach
+    rho2 = (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    p2 = (1.0 + 2.0 * gamma / (gamma + 1.0) * (m2 - 1.0)) / gamma
+    u2 = mach / rho2
+
+    def prim(y):
+        r = np.linalg.norm(y, axis=1)
+        up = y[:, 0] < 0.0
+        s = np.where(up, 0.5 * (1.0 - np.tanh((r - r_shock) / width)), 0.0)
+        # downstream of the sphere: the post-shock state relaxes back over the same layer
+        s = np.maximum(s, 0.5 * (1.0 - np.tanh((r - r_shock) / width)) * np.exp(-np.maximum(y[:, 0], 0.0) / 0.5))
+        rho = 1.0 + s * (rho2 - 1.0)
+        p = 1.0 / gamma + s * (p2 - 1.0 / gamma)
+        damp = np.tanh(np.maximum(r - r_wall, 0.0) / delta)
+        u = (mach + s * (u2 - mach)) * damp
+        return rho, u, p
+
+    def cons(y):
+        rho, u, p = prim(y)
+        return np.stack([rho, rho * u, np.zeros_like(u), np.zeros_like(u), p / (gamma - 1.0) + 0.5 * rho * u * u])
+
+    W = cons(x)
+    G = np.zeros((15, x.shape[0]))
+    h = 1e-6
+    for d in range(3):
+        e = np.zeros(3)
+        e[d] = h
+        dW = (cons(x + e) - cons(x - e)) / (2.0 * h)
+        for c in range(5):
+            G[3 * c + d] = dW[c]
+    return W, G
+
+
 def cell_node_mean(m: Mesh) -> np.ndarray:
     """Mean of each cell's node coordinates (a point inside the cell; used only to
     place analytic input fields, not a geometric quantity of the scheme)."""
