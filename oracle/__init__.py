@@ -24,14 +24,15 @@ class OmParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double), ("cfl", C.c_double),
                 ("eps_tau", C.c_double), ("c_tau", C.c_double), ("weno_eps", C.c_double),
                 ("gamma_lin", C.c_double), ("viscous", C.c_int), ("coarse_smoother", C.c_int),
-                ("relax_sweeps", C.c_int), ("cfl_implicit", C.c_double)]
+                ("relax_sweeps", C.c_int), ("cfl_implicit", C.c_double), ("cycle_gamma", C.c_int)]
 
 
 def params(gamma=1.4, mu=0.0, prandtl=1.0, cfl=0.5, eps_tau=0.01, c_tau=1.0, weno_eps=1e-5, gamma_lin=0.5,
-           viscous=False, coarse_smoother=0, relax_sweeps=2, cfl_implicit=0.25) -> OmParams:
-    """coarse_smoother 0: forward Euler on the coarse levels; 1: the implicit smoother of Sec. 4.3."""
+           viscous=False, coarse_smoother=0, relax_sweeps=2, cfl_implicit=0.25, cycle_gamma=1) -> OmParams:
+    """coarse_smoother 0: forward Euler on the coarse levels; 1: the implicit smoother of Sec. 4.3.
+    cycle_gamma 1: V-cycle; 2: W-cycle (each coarser level visited twice per parent visit)."""
     return OmParams(gamma, mu, prandtl, cfl, eps_tau, c_tau, weno_eps, gamma_lin, int(bool(viscous)),
-                    int(coarse_smoother), int(relax_sweeps), float(cfl_implicit))
+                    int(coarse_smoother), int(relax_sweeps), float(cfl_implicit), int(cycle_gamma))
 
 
 def lib():

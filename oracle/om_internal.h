@@ -27,6 +27,7 @@ typedef struct {
     int coarse_smoother;
     int relax_sweeps;    /* point-relaxation sweeps of the implicit smoother */
     double cfl_implicit; /* CFL number of the implicit smoother's local time step */
+    int cycle_gamma;     /* visits of each coarser level per visit of its parent: 1 V-cycle, 2 W-cycle */
 } om_params;
 
 typedef struct {

@@ -13,7 +13,9 @@
  *    and local time steps (Secs. 1, 4.2, 6);
  *  - correction W_h* = W_h^{n+1} + (W_2h^{k+1} - W_2h^0), averages only;
  *  - three-level V-cycle, one pre-smoothing and no post-smoothing by default;
- *  - optionally the implicit coarse smoother of Sec. 4.3 (om_coarse_implicit).
+ *  - optionally the implicit coarse smoother of Sec. 4.3 (om_coarse_implicit);
+ *  - optionally gamma > 1 visits of each coarser level per visit of its parent
+ *    (gamma = 2: W-cycle), each continuing from the level's state with its forcing.
  * Readings: coarse faces carry the summed fine area vectors (n = A/|A|,
  * S = |A|); coarse boundary faces are the fine boundary faces with the coarse
  * owner's ghost state; the coarse operator is inviscid KFVS, its local time
@@ -520,17 +522,20 @@ typedef struct {
 } om_cycle;
 
 static void coarse_visit(const om_hier *h, int l, const om_params *p, const om_cycle *cy, const double *W0,
-                         const double *Rs, double *W)
+                         const double *Rs, double *W);
+
+/*
+ * FAS cycle on level l >= 1 with forcing F, state W in place: pre-sweeps, then (below the
+ * coarsest level) the next level's forcing from the restricted state and residual, gamma visits
+ * of the next level that continue from its state with that forcing, the correction, post-sweeps.
+ */
+static void fas_level(const om_hier *h, int l, const om_params *p, const om_cycle *cy, const double *F, double *W)
 {
     const int64_t N = h->lev[l].n;
-    double *R0 = malloc(sizeof(double) * 5 * N), *F = malloc(sizeof(double) * 5 * N);
-    double *R = malloc(sizeof(double) * 5 * N);
-    om_kfvs_residual(h, l, p, W0, R0);
-    for (int64_t i = 0; i < 5 * N; ++i) F[i] = Rs[i] - R0[i];
-    memcpy(W, W0, sizeof(double) * 5 * N);
     for (int s = 0; s < cy->nu_pre[l]; ++s) coarse_sweep(h, l, p, F, W);
     if (l + 1 < h->nlev) {
         const int64_t Nc = h->lev[l + 1].n;
+        double *R = malloc(sizeof(double) * 5 * N);
         om_kfvs_residual(h, l, p, W, R);
         for (int64_t i = 0; i < 5 * N; ++i) R[i] += F[i];
         double *Wc0 = malloc(sizeof(double) * 5 * Nc), *Rc = malloc(sizeof(double) * 5 * Nc),
@@ -539,14 +544,27 @@ static void coarse_visit(const om_hier *h, int l, const om_params *p, const om_c
         coarse_visit(h, l + 1, p, cy, Wc0, Rc, Wc);
         for (int64_t i = 0; i < 5 * Nc; ++i) Wc[i] -= Wc0[i];
         om_prolong(h, l + 1, Wc, W);
+        free(R);
         free(Wc0);
         free(Rc);
         free(Wc);
     }
     for (int s = 0; s < cy->nu_post[l]; ++s) coarse_sweep(h, l, p, F, W);
+}
+
+/* visit of level l from its parent: forcing F = Res* - Res_2h(W0), W = W0, gamma FAS cycles */
+static void coarse_visit(const om_hier *h, int l, const om_params *p, const om_cycle *cy, const double *W0,
+                         const double *Rs, double *W)
+{
+    const int64_t N = h->lev[l].n;
+    double *R0 = malloc(sizeof(double) * 5 * N), *F = malloc(sizeof(double) * 5 * N);
+    om_kfvs_residual(h, l, p, W0, R0);
+    for (int64_t i = 0; i < 5 * N; ++i) F[i] = Rs[i] - R0[i];
+    memcpy(W, W0, sizeof(double) * 5 * N);
+    const int gamma = p->cycle_gamma > 1 ? p->cycle_gamma : 1;
+    for (int k = 0; k < gamma; ++k) fas_level(h, l, p, cy, F, W);
     free(R0);
     free(F);
-    free(R);
 }
 
 /*
