@@ -172,6 +172,42 @@ def shock_regime(cg, mg, cycles):
     return res
 
 
+def hierarchy_study(cg, mg, max_cycles):
+    """Cycle and coarsening variants on the hexahedral channel (48 x 16 x 8 = 6,144 cells): time and
+    cycles to a 1e-10 drop for the 3-level V-cycle, the W-cycle, 2/4/5 levels, 2 and 4 agglomeration
+    passes, one post-sweep per level, and skewness thresholds delta 0.1 and 0.5."""
+    import torch
+    m = mg.bump_channel(48, 16, 8, n_prism=0, n_pyr=0)
+    variants = [("v3", {}), ("w3", {"cycle_gamma": 2}), ("v2", {"levels": 2}), ("v4", {"levels": 4}),
+                ("v5", {"levels": 5}), ("w4", {"levels": 4, "cycle_gamma": 2}), ("passes2", {"passes": 2}),
+                ("passes4", {"passes": 4}), ("post1", {"nu_post": [1] * 8}),
+                ("skew_delta_0.1", {"skew_delta": 0.1}), ("skew_delta_0.5", {"skew_delta": 0.5})]
+    res = {"cells": m.n_cells, "mesh": "bump channel 48x16x8, hexahedra only"}
+    for key, kw in variants:
+        S = cg.Solver(**kw)
+        S.set_mesh(m)
+        prim = np.array([1.0, 0.5, 0.0, 0.0, 1.0 / 1.4])
+        for tag in (mg.TAG_INLET, mg.TAG_OUTLET):
+            S.set_bc(tag, cg.BC_FARFIELD, prim)
+        for tag in (mg.TAG_WALL_BOTTOM, mg.TAG_WALL_TOP, mg.TAG_WALL_SIDE):
+            S.set_bc(tag, cg.BC_SLIP)
+        sizes = S.agglomerate()
+        W0, G0 = mg.uniform_state(m.n_cells)
+        W = torch.from_numpy(W0).cuda()
+        G = torch.from_numpy(G0).cuda()
+        al = torch.ones(m.n_cells, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h, ok = S.vcycle(W, G, al, max_cycles, 1e-10)
+        torch.cuda.synchronize()
+        dt_c = time.perf_counter() - t0
+        res[key] = {"levels": [int(x) for x in sizes], "cycles": int(len(h)), "seconds": dt_c, "reached": bool(ok),
+                    "final_drop": float(h[-1] / h[0]), "ms_per_cycle": 1e3 * dt_c / max(len(h), 1)}
+        log(f"hierarchy {key}: levels {list(sizes)} {len(h)} cycles {dt_c:.2f}s drop {h[-1] / h[0]:.2e}")
+        S.close()
+    return res
+
+
 def adjoint_measurements(cg, mg, S, W, G, al):
     """Linearisation and vector-Jacobian-product timings on the benchmark state, and the
     adjoint gradients of the lower-wall x-force against converged finite differences on a
@@ -247,6 +283,8 @@ def main():
                     help="max cycles for the time-to-1e-10 runs on the all-hexahedral channel (0: skip)")
     ap.add_argument("--shock-cycles", type=int, default=8000,
                     help="V-cycles of the Mach 1.2 / 0.95 viscous sphere runs (0: skip)")
+    ap.add_argument("--hierarchy-study", type=int, default=0,
+                    help="max cycles of the cycle/coarsening variant study on a 6,144-cell channel (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timings and gradient check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true", help="run a plain 1 GiB copy first (counter scaling)")
@@ -359,6 +397,8 @@ def main():
         out["adjoint"] = adjoint_measurements(cg, mg, S, W, G, al)
     if args.converge_hex:
         out["time_to_1e-10_hex_channel"] = hex_convergence(cg, mg, args.converge_hex)
+    if args.hierarchy_study:
+        out["hierarchy_study"] = hierarchy_study(cg, mg, args.hierarchy_study)
     if args.shock_cycles:
         out["shock_regime_sphere"] = shock_regime(cg, mg, args.shock_cycles)
     if not args.no_cpu_baseline:

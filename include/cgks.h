@@ -73,6 +73,8 @@ typedef struct {
                                 with point relaxation (paper Sec. 4.3) */
     int32_t relax_sweeps;    /* relaxation sweeps of the implicit coarse smoother (2) */
     double cfl_implicit;     /* CFL number of the implicit coarse smoother's local step (0.25) */
+    int32_t cycle_gamma;     /* visits of each coarser level per visit of its parent, each continuing
+                                with the same forcing: 1 V-cycle (default), 2 W-cycle (1..3) */
 } cgks_params;
 
 /* Fill *p with the defaults above. */
@@ -272,7 +274,8 @@ cgks_status cgks_prolong(cgks_ctx *ctx, int32_t level, const double *dWc, double
 /*
  * V-cycles (paper Sec. 4.2, Fig. Procedure): fine smoothing (nu_pre[0]), fine residual at the
  * smoothed state restricted with the volume-weighted state, forcing term, coarse
- * KFVS sweeps, recursion, correction; repeated until the residual drops by tol_drop
+ * KFVS sweeps (or the implicit smoother, params.coarse_smoother), recursion with
+ * params.cycle_gamma visits per coarser level (2: W-cycle), correction; repeated until the residual drops by tol_drop
  * relative to the first cycle or max_cycles.  In place on device W, G, alpha.
  * hist (host, nullable, max_cycles) receives the residual norm of each cycle;
  * *n_done the cycles run.  Reads one scalar per cycle (synchronises each cycle).

@@ -32,7 +32,8 @@ class Params(C.Structure):
                 ("skew_delta", C.c_double), ("skew_sin", C.c_double), ("viscous", C.c_int32), ("levels", C.c_int32),
                 ("passes", C.c_int32), ("precision", C.c_int32), ("nu_pre", C.c_int32 * 8),
                 ("nu_post", C.c_int32 * 8), ("mixed_switch", C.c_double), ("seed", C.c_uint64),
-                ("coarse_smoother", C.c_int32), ("relax_sweeps", C.c_int32), ("cfl_implicit", C.c_double)]
+                ("coarse_smoother", C.c_int32), ("relax_sweeps", C.c_int32), ("cfl_implicit", C.c_double),
+                ("cycle_gamma", C.c_int32)]
 
 
 class CgksError(RuntimeError):

@@ -931,6 +931,7 @@ int adj_solve(cgks_ctx *c, int32_t tag, const double e[3], int max_iter, double 
     const cgks_params &p = c->prm;
     if (p.precision != 0) throw Error{CGKS_E_STATE, "the adjoint runs in FP64 (precision 0)"};
     if (p.coarse_smoother != 0) throw Error{CGKS_E_STATE, "the adjoint transposes the forward-Euler coarse smoother"};
+    if (p.cycle_gamma != 1) throw Error{CGKS_E_STATE, "the adjoint transposes the V-cycle (cycle_gamma 1)"};
     const int nl = (int)c->lev.size();
     if (std::max(1, p.nu_pre[0]) != 1) throw Error{CGKS_E_STATE, "the adjoint supports one fine pre-sweep"};
     for (int l = 0; l < std::max(nl, 1); ++l)

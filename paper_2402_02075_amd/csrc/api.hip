@@ -52,6 +52,7 @@ static void check_params(const cgks_params *p)
     if (p->coarse_smoother != 0 && p->coarse_smoother != 1) throw Error{CGKS_E_ARG, "coarse_smoother must be 0 or 1"};
     if (p->relax_sweeps < 0 || p->relax_sweeps > 64) throw Error{CGKS_E_ARG, "relax_sweeps must be in 0..64"};
     if (p->coarse_smoother == 1 && !(p->cfl_implicit > 0.0)) throw Error{CGKS_E_ARG, "cfl_implicit must be positive"};
+    if (p->cycle_gamma < 1 || p->cycle_gamma > 3) throw Error{CGKS_E_ARG, "cycle_gamma must be in 1..3"};
 }
 
 static void check_bad(cgks_ctx *c)
@@ -96,6 +97,7 @@ cgks_status cgks_default_params(cgks_params *p)
     p->coarse_smoother = 0;
     p->relax_sweeps = 2;
     p->cfl_implicit = 0.25;
+    p->cycle_gamma = 1;
     return CGKS_OK;
 }
 

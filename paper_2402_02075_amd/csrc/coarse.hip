@@ -1228,39 +1228,37 @@ template <> LevelBufs<float> bufs<float>(Level *L)
     return {L->W0f.p, L->Wf.p, L->Df.p, L->Rf.p, L->Ff.p, L->Rsf.p, L->dtf.p, L->ffluxf.p};
 }
 
-// Visit level l (>= 1) with W0 and Rs set; leaves the correction in D.
-template <class T> static void coarse_visit(cgks_ctx *c, int l)
+// A coarse sweep at W = W0 + D: forward Euler D += dt/V (Res_2h(W) + F), or D += dU of the
+// implicit smoother with right-hand side Res_2h(W) + F.
+template <class T> static void coarse_sweep(cgks_ctx *c, int l)
 {
     Level *L = c->lev[l];
     LevelBufs<T> b = bufs<T>(L);
     hipStream_t st = c->stream;
     const int64_t n = L->n, n5 = 5 * n;
-    // forcing F = Res* - Res_2h(W0)
-    kfvs_impl<T>(c, l, b.W0, b.R, b.ff);
-    const int npre = c->prm.nu_pre[l];
-    const bool implicit = c->prm.coarse_smoother == 1;
-    if (npre > 0 && !implicit) {
-        coarse_dt_impl<T>(c, l, b.W0, b.dt);
-        hipLaunchKernelGGL((k_forcing_first<T>), G1(n), dim3(256), 0, st, n, b.Rs, b.R, b.dt, L->V.p, b.F, b.D);
+    hipLaunchKernelGGL((k_sum_state<T>), G1(n5), dim3(256), 0, st, n5, b.W0, b.D, b.W);
+    if (c->prm.coarse_smoother == 1) {
+        kfvs_impl<T>(c, l, b.W, b.R, b.ff, b.F);
+        implicit_solve<T>(c, l, b.W, b.R, b.D, true);
     } else {
-        hipLaunchKernelGGL((k_coarse_forcing<T>), G1(n5), dim3(256), 0, st, n5, b.Rs, b.R, b.F);
-        // the first implicit sweep has W = W0 and right-hand side Res_2h(W0) + F = Res*
-        if (npre > 0) implicit_solve<T>(c, l, b.W0, b.Rs, b.D, false);
-        else CGKS_HIP(hipMemsetAsync(b.D, 0, sizeof(T) * n5, st));
+        kfvs_impl<T>(c, l, b.W, b.R, b.ff);
+        coarse_dt_impl<T>(c, l, b.W, b.dt);
+        hipLaunchKernelGGL((k_delta_update<T>), G1(n), dim3(256), 0, st, n, b.dt, L->V.p, b.R, b.F, b.D);
     }
-    // a later sweep at W = W0 + D: forward Euler D += dt/V (Res_2h(W) + F), or D += dU
-    auto sweep = [&]() {
-        hipLaunchKernelGGL((k_sum_state<T>), G1(n5), dim3(256), 0, st, n5, b.W0, b.D, b.W);
-        if (implicit) {
-            kfvs_impl<T>(c, l, b.W, b.R, b.ff, b.F);
-            implicit_solve<T>(c, l, b.W, b.R, b.D, true);
-        } else {
-            kfvs_impl<T>(c, l, b.W, b.R, b.ff);
-            coarse_dt_impl<T>(c, l, b.W, b.dt);
-            hipLaunchKernelGGL((k_delta_update<T>), G1(n), dim3(256), 0, st, n, b.dt, L->V.p, b.R, b.F, b.D);
-        }
-    };
-    for (int s = 1; s < npre; ++s) sweep();
+}
+
+template <class T> static void coarse_visit(cgks_ctx *c, int l);
+
+// One FAS cycle on level l (>= 1) with its forcing F and correction D set: the pre-sweeps not
+// yet applied, then (above the coarsest level) a visit of level l + 1 from the restricted state
+// and residual, the prolonged correction, and the post-sweeps.
+template <class T> static void fas_level(cgks_ctx *c, int l, int pre_done)
+{
+    Level *L = c->lev[l];
+    LevelBufs<T> b = bufs<T>(L);
+    hipStream_t st = c->stream;
+    const int64_t n5 = 5 * L->n;
+    for (int s = pre_done; s < c->prm.nu_pre[l]; ++s) coarse_sweep<T>(c, l);
     if (l + 1 < (int)c->lev.size()) {
         Level *C = c->lev[l + 1];
         LevelBufs<T> cb = bufs<T>(C);
@@ -1272,7 +1270,32 @@ template <class T> static void coarse_visit(cgks_ctx *c, int l)
         hipLaunchKernelGGL((k_prolong<T, T>), G1(C->nfine), dim3(256), 0, st, C->nfine, C->n, C->f2c.p, cb.D,
                            (const T *)nullptr, b.D);
     }
-    for (int s = 0; s < c->prm.nu_post[l]; ++s) sweep();
+    for (int s = 0; s < c->prm.nu_post[l]; ++s) coarse_sweep<T>(c, l);
+}
+
+// Visit of level l (>= 1) from its parent, with W0 and Rs set: forcing F = Res* - Res_2h(W0),
+// then cycle_gamma FAS cycles (1: V-cycle, 2: W-cycle), each continuing from W0 + D with the
+// same forcing; leaves the correction in D.
+template <class T> static void coarse_visit(cgks_ctx *c, int l)
+{
+    Level *L = c->lev[l];
+    LevelBufs<T> b = bufs<T>(L);
+    hipStream_t st = c->stream;
+    const int64_t n = L->n, n5 = 5 * n;
+    kfvs_impl<T>(c, l, b.W0, b.R, b.ff);
+    const int npre = c->prm.nu_pre[l];
+    const bool implicit = c->prm.coarse_smoother == 1;
+    // the first sweep at W = W0 has right-hand side Res_2h(W0) + F = Res* exactly
+    if (npre > 0 && !implicit) {
+        coarse_dt_impl<T>(c, l, b.W0, b.dt);
+        hipLaunchKernelGGL((k_forcing_first<T>), G1(n), dim3(256), 0, st, n, b.Rs, b.R, b.dt, L->V.p, b.F, b.D);
+    } else {
+        hipLaunchKernelGGL((k_coarse_forcing<T>), G1(n5), dim3(256), 0, st, n5, b.Rs, b.R, b.F);
+        if (npre > 0) implicit_solve<T>(c, l, b.W0, b.Rs, b.D, false);
+        else CGKS_HIP(hipMemsetAsync(b.D, 0, sizeof(T) * n5, st));
+    }
+    const int gamma = std::max(1, c->prm.cycle_gamma);
+    for (int k = 0; k < gamma; ++k) fas_level<T>(c, l, k == 0 && npre > 0 ? 1 : 0);
 }
 
 // One V-cycle on the fine state; the norm of the smoothing residual is left in c->scal[0].
