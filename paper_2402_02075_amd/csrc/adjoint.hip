@@ -719,7 +719,7 @@ static AdjTape &tape(cgks_ctx *c)
 
 static ReconArgs recon_args(cgks_ctx *c, const double *W, const double *G, const double *al)
 {
-    ReconArgs A;
+    ReconArgs A{};
     A.N = c->N;
     A.F = c->F;
     A.gam = c->prm.gamma;

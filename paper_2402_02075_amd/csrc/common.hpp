@@ -160,6 +160,7 @@ struct cgks_ctx {
     cgks::DBuf<int32_t> op_gmax;   // [ceil(N/64)] largest interior-neighbour count of the group
     cgks::DBuf<double> iav;        // [6*3][N] area vector / |Omega| of the interior faces, in that order
     cgks::DBuf<uint8_t> nface;     // [N] faces of the cell
+    cgks::DBuf<double> bgq;        // [5][Fb] ghost states of the boundary faces (reconstruction work)
     // boundary conditions
     cgks::BcTable bc_host{};
     cgks::DBuf<cgks::BcTable> bc;

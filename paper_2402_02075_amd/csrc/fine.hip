@@ -49,7 +49,30 @@ __global__ void k_local_dt(int64_t N, int64_t F, double gam, double cfl, double 
 // (39 x 64 doubles) are staged in LDS once per block and shared by the five waves, so every
 // operator byte crosses the memory hierarchy once.
 
-// Green-Gauss contributions of the boundary faces of component C (the ghost of the own average).
+// Ghost states of the boundary faces at the current state, one thread per boundary face, for
+// the reconstruction's Green-Gauss term (each face's ghost is computed once, not per component).
+__global__ void k_bnd_ghost(int64_t N, int64_t F, int64_t Fi, const double *__restrict__ W,
+                            const int32_t *__restrict__ fl, const int32_t *__restrict__ ftag,
+                            const double *__restrict__ favec, const BcTable *__restrict__ bc, double gam,
+                            double *__restrict__ bgq)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t Fb = F - Fi;
+    if (b >= Fb) return;
+    const int64_t f = Fi + b;
+    const int o = fl[f];
+    const double av[3] = {favec[f], favec[F + f], favec[2 * F + f]};
+    const double na = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
+    const double n[3] = {av[0] / na, av[1] / na, av[2] / na};
+    double Q0[5], Qg[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Q0[c] = W[c * N + o];
+    ghost_state(*bc, ftag[f], n, Q0, gam, Qg);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) bgq[c * Fb + b] = Qg[c];
+}
+
+// Green-Gauss contribution of a cell's boundary faces to component C, ghost states precomputed.
 template <int C>
 __device__ __forceinline__ void recon_gg_boundary(const ReconArgs &A, int64_t i, double q0, double gg[3])
 {
@@ -59,14 +82,8 @@ __device__ __forceinline__ void recon_gg_boundary(const ReconArgs &A, int64_t i,
         if (nbv == INT32_MIN) break;
         if (nbv >= 0) continue;
         const double av[3] = {A.slot_av[(3 * s) * N + i], A.slot_av[(3 * s + 1) * N + i], A.slot_av[(3 * s + 2) * N + i]};
-        const int f = -nbv - 1;
-        const double na = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
-        const double n[3] = {av[0] / na, av[1] / na, av[2] / na};
-        double Q0[5], Qg[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) Q0[c] = A.W[c * N + i];
-        ghost_state(*A.bc, A.ftag[f], n, Q0, A.gam, Qg);
-        const double qm = Qg[C];
+        const int64_t f = -(int64_t)nbv - 1;
+        const double qm = A.bgq[C * A.Fb + (f - A.Fi)];
 #pragma unroll
         for (int d = 0; d < 3; ++d) gg[d] += 0.5 * (qm + q0) * av[d];
     }
@@ -633,7 +650,7 @@ void launch_local_dt(cgks_ctx *c, const double *W, double *dt)
 
 void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef, bool cell_major)
 {
-    ReconArgs A;
+    ReconArgs A{};
     A.N = c->N;
     A.F = c->F;
     A.gam = c->prm.gamma;
@@ -658,6 +675,12 @@ void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *a
     A.iav = c->iav.p;
     A.n_int = c->n_int.p;
     A.nface = c->nface.p;
+    A.Fi = c->Fi;
+    A.Fb = c->F - c->Fi;
+    A.bgq = c->bgq.p;
+    if (A.Fb > 0)
+        hipLaunchKernelGGL(k_bnd_ghost, dim3(blocks_for(A.Fb, 256)), dim3(256), 0, c->stream, c->N, c->F, c->Fi, W,
+                           c->fl.p, c->ftag.p, c->favec.p, c->bc.p, c->prm.gamma, c->bgq.p);
     const dim3 grid(blocks_for(c->N, OP_GROUP)), blk(5 * OP_GROUP);
     if (cell_major) hipLaunchKernelGGL((k_recon<true>), grid, blk, 0, c->stream, A);
     else hipLaunchKernelGGL((k_recon<false>), grid, blk, 0, c->stream, A);

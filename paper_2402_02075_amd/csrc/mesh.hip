@@ -673,6 +673,7 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
     hipLaunchKernelGGL(k_slots, dim3(blocks_for(N, bs)), dim3(bs), 0, s, N, F, c->cf_ptr.p, c->cf_face.p, c->fl.p,
                        c->fr.p, c->favec.p, c->vol.p, c->slot_nb.p, c->slot_av.p);
     c->iav.alloc(18 * N);
+    c->bgq.alloc(5 * (F > Fi ? F - Fi : 1));
     hipLaunchKernelGGL(k_iav, dim3(blocks_for(N, bs)), dim3(bs), 0, s, N, c->slot_nb.p, c->slot_av.p, c->iav.p);
     hipLaunchKernelGGL(k_op_build, dim3(blocks_for(N, 64)), dim3(64), 0, s, N, F, c->cf_ptr.p, c->cf_face.p, c->fl.p,
                        c->fr.p, c->fshift.p, c->vol.p, c->cen.p, c->mom2.p, c->op_off.p, c->op.p, c->bad.p);

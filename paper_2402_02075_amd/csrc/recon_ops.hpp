@@ -27,6 +27,8 @@ struct ReconArgs {
     const double *iav;      // [6*3][N] outward area vector / |Omega| of those faces
     const uint8_t *n_int;   // [N] interior neighbours
     const uint8_t *nface;   // [N] faces
+    const double *bgq;      // [5][Fb] ghost states of the boundary faces at W (face ids Fi..F-1)
+    int64_t Fi, Fb;
     double *coef;
 };
 
