@@ -271,7 +271,7 @@ __device__ __forceinline__ double face_prod(double v, int ln, int ngp)
 // One lane per face Gauss point, faces packed into waves with 3 or 4 lanes each (lane map
 // built at set-up), face sums by lane shuffles.
 // The work of one lane: its face's Gauss point k, given the lane's indices and geometry.
-template <class T, int MODE, bool VAL>
+template <class T, int MODE, bool VAL, bool INV>
 __device__ __forceinline__ void face_lane(const FaceArgs &A, const int4 id, const double g[10], int ln)
 {
     const int64_t N = A.N;
@@ -308,6 +308,29 @@ __device__ __forceinline__ void face_lane(const FaceArgs &A, const int4 id, cons
         T wl[5], wr[5], gl[3][5], gr[3][5];
         to_local(WL, GL, n, t1, t2, wl, gl);
         to_local(WR, GR, n, t1, t2, wr, gr);
+        if constexpr (INV) {
+            // inviscid residual modes: time coefficients folded into the moment sums
+            T Fl[5], Wt[5], pl, pr;
+            if (!gks_flux_inviscid<T, MODE == MODE_RES>(wl, gl, wr, gr, T(A.cfg.gamma), T(A.cfg.K), T(dtf), A.cfg, Fl,
+                                                       Wt, pl, pr)) {
+                atomicMin(A.bad, L);
+            } else {
+                double Fg[5];
+                to_global(Fl, n, t1, t2, Fg);
+                const double s = wS / dtf;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) acc[q] = s * Fg[q];
+                if (MODE == MODE_RES) {
+                    double Wg[5];
+                    to_global(Wt, n, t1, t2, Wg);
+#pragma unroll
+                    for (int q = 0; q < 5; ++q)
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) acc[5 + 3 * q + d] = wS * Wg[q] * n[d];
+                    if (R >= 0) alpha_k = cf_factor(wl, wr, double(pl), double(pr), A.cfg.gamma);
+                }
+            }
+        } else {
         GksMoments<T> mo;
         if (!gks_moments<T>(wl, gl, wr, gr, T(A.cfg.gamma), T(A.cfg.K), mo, VAL)) {
             atomicMin(A.bad, L);
@@ -372,6 +395,7 @@ __device__ __forceinline__ void face_lane(const FaceArgs &A, const int4 id, cons
             if (MODE != MODE_RESONLY && R >= 0)
                 alpha_k = cf_factor(wl, wr, double(mo.pl), double(mo.pr), A.cfg.gamma);
         }
+        }
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = face_sum(acc[q], ln, ngp);
@@ -388,7 +412,7 @@ __device__ __forceinline__ void face_lane(const FaceArgs &A, const int4 id, cons
 
 // One lane per face Gauss point, faces packed into waves with 3 or 4 lanes each (lane map
 // built at set-up), face sums by lane shuffles.
-template <class T, int MODE, bool VAL> __global__ __launch_bounds__(256) void k_face(FaceArgs A)
+template <class T, int MODE, bool VAL, bool INV = false> __global__ __launch_bounds__(256) void k_face(FaceArgs A)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t NL = A.NL;
@@ -396,7 +420,7 @@ template <class T, int MODE, bool VAL> __global__ __launch_bounds__(256) void k_
     double g[10];
 #pragma unroll
     for (int q = 0; q < 10; ++q) g[q] = A.lgeo[q * NL + gid];
-    face_lane<T, MODE, VAL>(A, id, g, (int)(threadIdx.x & 63));
+    face_lane<T, MODE, VAL, INV>(A, id, g, (int)(threadIdx.x & 63));
 }
 
 // ---------------------------------------------------------------- gathers
@@ -715,20 +739,30 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
         e1 = c->ev_pool[c->ev_used++];
         CGKS_HIP(hipEventRecord(e0, c->stream));
     }
+    // inviscid steady modes: the time coefficients are known before the moments (tau = 0)
+    const bool inv = !c->prm.viscous;
     if (fp32) {
         switch (mode) {
-        case MODE_RES: hipLaunchKernelGGL((k_face<float, MODE_RES, true>), grid, blk, 0, c->stream, A); break;
+        case MODE_RES:
+            if (inv) hipLaunchKernelGGL((k_face<float, MODE_RES, true, true>), grid, blk, 0, c->stream, A);
+            else hipLaunchKernelGGL((k_face<float, MODE_RES, true>), grid, blk, 0, c->stream, A);
+            break;
         case MODE_RESONLY:
-            if (prfix) hipLaunchKernelGGL((k_face<float, MODE_RESONLY, true>), grid, blk, 0, c->stream, A);
+            if (inv) hipLaunchKernelGGL((k_face<float, MODE_RESONLY, false, true>), grid, blk, 0, c->stream, A);
+            else if (prfix) hipLaunchKernelGGL((k_face<float, MODE_RESONLY, true>), grid, blk, 0, c->stream, A);
             else hipLaunchKernelGGL((k_face<float, MODE_RESONLY, false>), grid, blk, 0, c->stream, A);
             break;
         default: throw Error{CGKS_E_ARG, "FP32 flux supports the steady modes only"};
         }
     } else {
         switch (mode) {
-        case MODE_RES: hipLaunchKernelGGL((k_face<double, MODE_RES, true>), grid, blk, 0, c->stream, A); break;
+        case MODE_RES:
+            if (inv) hipLaunchKernelGGL((k_face<double, MODE_RES, true, true>), grid, blk, 0, c->stream, A);
+            else hipLaunchKernelGGL((k_face<double, MODE_RES, true>), grid, blk, 0, c->stream, A);
+            break;
         case MODE_RESONLY:
-            if (prfix) hipLaunchKernelGGL((k_face<double, MODE_RESONLY, true>), grid, blk, 0, c->stream, A);
+            if (inv) hipLaunchKernelGGL((k_face<double, MODE_RESONLY, false, true>), grid, blk, 0, c->stream, A);
+            else if (prfix) hipLaunchKernelGGL((k_face<double, MODE_RESONLY, true>), grid, blk, 0, c->stream, A);
             else hipLaunchKernelGGL((k_face<double, MODE_RESONLY, false>), grid, blk, 0, c->stream, A);
             break;
         case MODE_S1: hipLaunchKernelGGL((k_face<double, MODE_S1, true>), grid, blk, 0, c->stream, A); break;

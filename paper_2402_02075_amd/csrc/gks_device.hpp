@@ -422,6 +422,97 @@ template <class T> CGKS_HD void value_at(const GksMoments<T> &m, T t, T tau, T t
     combine(c, m.Vc, m.Vk, Wt);
 }
 
+// Inviscid flux over [0, dt] and interface value at dt of one Gauss point with the time
+// coefficients applied while the moments accumulate.  Without viscosity the collision times
+// depend only on the two side pressures (tau = 0, tau_n from the pressure jump), so the
+// coefficients are known before the moment loops, and each kinetic and central moment vector
+// enters the result directly instead of being kept for a final combination: the same sums as
+// gks_moments + flux_integrated + value_at, with 30 fewer live values.
+// VAL = false skips the interface value.
+template <class T, bool VAL>
+CGKS_HD bool gks_flux_inviscid(const T wl[5], const T gl[3][5], const T wr[5], const T gr[3][5], T gam, T K, T dt,
+                               const GksCfg &cfg, T F[5], T Wt[5], T &pl, T &pr)
+{
+    const Side<T> sl = side_of(wl, gam), sr = side_of(wr, gam);
+    if (!(sl.rho > T(0) && sr.rho > T(0) && sl.lam > T(0) && sr.lam > T(0))) return false;
+    pl = sl.p;
+    pr = sr.p;
+    const T taun = T(cfg.eps_tau) * dt + T(cfg.c_tau) * abs_((pl - pr) / (pl + pr)) * dt;
+    const TimeCoef<T> cf = coef_integrated(dt, T(0), taun);
+    TimeCoef<T> cw;
+    if (VAL) cw = coef_at(dt, T(0), taun);
+    const T iK3 = T(1) / (K + T(3));
+    T Wc[5] = {T(0), T(0), T(0), T(0), T(0)};
+    T dWc[3][5];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int c = 0; c < 5; ++c) dWc[j][c] = T(0);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) F[c] = Wt[c] = T(0);
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const Side<T> &s = side == 0 ? sl : sr;
+        const T(*g)[5] = side == 0 ? gl : gr;
+        Tab<T> t;
+        tab_vw(t, s, K);
+        tab_u_full(t, s);
+        T a[3][5], A[5], tr[5];
+        slopes(s, t, K, iK3, g, a, A, tr);
+        tab_u_half(t, s, side == 0 ? T(1) : T(-1));
+        const T rho = s.rho;
+        T m[15];
+        mmat<0, 0, 0>(t, m);  // <psi psi>_half
+        mcol0_acc(m, rho, Wc);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) msym_acc(m, a[j], rho, dWc[j]);
+        if (VAL) {
+            mcol0_acc(m, cw.e * rho, Wt);
+            msym_acc(m, A, -cw.k2 * rho, Wt);
+        }
+        mmat<1, 0, 0>(t, m);  // <u psi psi>_half
+        mcol0_acc(m, cf.e * rho, F);
+        msym_acc(m, A, -cf.k2 * rho, F);
+        if (VAL) {
+            msym_acc(m, a[0], -cw.k1 * rho, Wt);
+            mmat<0, 1, 0>(t, m);
+            msym_acc(m, a[1], -cw.k1 * rho, Wt);
+            mmat<0, 0, 1>(t, m);
+            msym_acc(m, a[2], -cw.k1 * rho, Wt);
+        }
+        mmat<2, 0, 0>(t, m);
+        msym_acc(m, a[0], -cf.k1 * rho, F);
+        mmat<1, 1, 0>(t, m);
+        msym_acc(m, a[1], -cf.k1 * rho, F);
+        mmat<1, 0, 1>(t, m);
+        msym_acc(m, a[2], -cf.k1 * rho, F);
+    }
+    const Side<T> sc = side_of(Wc, gam);
+    if (!(sc.rho > T(0) && sc.lam > T(0))) return false;
+    Tab<T> t;
+    tab_vw(t, sc, K);
+    tab_u_full(t, sc);
+    T a[3][5], A[5], tr[5];
+    slopes(sc, t, K, iK3, dWc, a, A, tr);
+    const T rho = sc.rho;
+    if (VAL) {
+        // rho_c <psi {1, a_c.u, A_c}> = {W_c, rho tr, -rho tr}
+#pragma unroll
+        for (int c = 0; c < 5; ++c) Wt[c] += cw.c1 * Wc[c] + (cw.c2 - cw.c3) * (rho * tr[c]);
+    }
+    T m[15];
+    mmat<1, 0, 0>(t, m);
+    mcol0_acc(m, cf.c1 * rho, F);
+    msym_acc(m, A, cf.c3 * rho, F);
+    mmat<2, 0, 0>(t, m);
+    msym_acc(m, a[0], cf.c2 * rho, F);
+    mmat<1, 1, 0>(t, m);
+    msym_acc(m, a[1], cf.c2 * rho, F);
+    mmat<1, 0, 1>(t, m);
+    msym_acc(m, a[2], cf.c2 * rho, F);
+    return true;
+}
+
 // First-order kinetic flux vector splitting in the face frame (coarse levels, Sec. 4.2):
 // F = rho_l <u psi>_{u>0} + rho_r <u psi>_{u<0}.
 template <class T> CGKS_HD void kfvs_local(const T wl[5], const T wr[5], T gam, T K, T F[5])
