@@ -625,11 +625,10 @@ template <class T> struct CoarseArgs {
     T *fflux;  // [5][m + nb], S n . F
 };
 
-template <class T> __global__ __launch_bounds__(256) void k_kfvs_face(CoarseArgs<T> A)
+// S n . F of coarse face j (pairs j < m, then boundary faces) at the state W, or at W + D when D
+// is given (the sum taken in T, as the state-sum kernel takes it).
+template <class T> __device__ __forceinline__ void kfvs_face_flux(const CoarseArgs<T> &A, int64_t j, const T *D, T ff[5])
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t tot = A.m + A.nb;
-    if (j >= tot) return;
     double av[3];
     double wa[5], wb[5];
     if (j < A.m) {
@@ -637,20 +636,20 @@ template <class T> __global__ __launch_bounds__(256) void k_kfvs_face(CoarseArgs
         const int a = A.pa[j], b = A.pb[j];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            wa[q] = double(A.W[q * A.n + a]);
-            wb[q] = double(A.W[q * A.n + b]);
+            wa[q] = double(D ? T(A.W[q * A.n + a] + D[q * A.n + a]) : A.W[q * A.n + a]);
+            wb[q] = double(D ? T(A.W[q * A.n + b] + D[q * A.n + b]) : A.W[q * A.n + b]);
         }
     } else {
         const int64_t k = j - A.m;
         for (int d = 0; d < 3; ++d) av[d] = A.bA[d * A.nb + k];
         const int o = A.bown[k];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) wa[q] = double(A.W[q * A.n + o]);
+        for (int q = 0; q < 5; ++q) wa[q] = double(D ? T(A.W[q * A.n + o] + D[q * A.n + o]) : A.W[q * A.n + o]);
     }
     const double S = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
     if (S == 0.0) {
 #pragma unroll
-        for (int q = 0; q < 5; ++q) A.fflux[q * tot + j] = T(0);
+        for (int q = 0; q < 5; ++q) ff[q] = T(0);
         return;
     }
     const double n[3] = {av[0] / S, av[1] / S, av[2] / S};
@@ -670,11 +669,108 @@ template <class T> __global__ __launch_bounds__(256) void k_kfvs_face(CoarseArgs
     lb[4] = T(wb[4]);
     T Fl[5];
     kfvs_local(la, lb, T(A.gam), T(A.K), Fl);
-    A.fflux[0 * tot + j] = T(S * double(Fl[0]));
+    ff[0] = T(S * double(Fl[0]));
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-        A.fflux[(1 + d) * tot + j] = T(S * (double(Fl[1]) * n[d] + double(Fl[2]) * t1[d] + double(Fl[3]) * t2[d]));
-    A.fflux[4 * tot + j] = T(S * double(Fl[4]));
+    for (int d = 0; d < 3; ++d) ff[1 + d] = T(S * (double(Fl[1]) * n[d] + double(Fl[2]) * t1[d] + double(Fl[3]) * t2[d]));
+    ff[4] = T(S * double(Fl[4]));
+}
+
+// one thread per coarse face; the state is W, or W + D when D is given
+template <class T> __global__ __launch_bounds__(256) void k_kfvs_face(CoarseArgs<T> A, const T *D)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = A.m + A.nb;
+    if (j >= tot) return;
+    T ff[5];
+    kfvs_face_flux(A, j, D, ff);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) A.fflux[q * tot + j] = ff[q];
+}
+
+// Row kernels of a coarse level's first sweep and of its restriction input: the face-flux
+// gather of the KFVS residual (same lanes and order as k_kfvs_gather) fused with the per-cell
+// work that follows it.
+//  FIRST: residual R0 at W0 (A.W), the local step at W0 (as k_coarse_dt), the forcing
+//         F = Rs - R0 and the first delta-form sweep D = dt/V Rs.
+//  else:  fluxes taken at W0 + D; writes that state (Wout) and Res_2h(W0 + D) + F (Rout).
+template <class T, bool FIRST>
+__global__ __launch_bounds__(256) void k_kfvs_rows(CoarseArgs<T> A, const T *__restrict__ ff,
+                                                   const int32_t *__restrict__ ptr, const int32_t *__restrict__ item,
+                                                   const double *__restrict__ Ssum, const double *__restrict__ V,
+                                                   double cfl, double mu, int viscous, const T *__restrict__ Rs,
+                                                   const T *__restrict__ D, T *__restrict__ F, T *__restrict__ Dout,
+                                                   T *__restrict__ Wout, T *__restrict__ Rout)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / RG;
+    const int g = (int)(t % RG);
+    const int64_t n = A.n, tot = A.m + A.nb;
+    if (i >= n) return;  // whole row groups leave together
+    double u = 0, v = 0, w = 0, cs = 0, rho = 1, Vi = 0;
+    if (FIRST) {
+        rho = double(A.W[i]);
+        const double ir = 1.0 / rho;
+        u = double(A.W[n + i]) * ir;
+        v = double(A.W[2 * n + i]) * ir;
+        w = double(A.W[3 * n + i]) * ir;
+        const double p = (A.gam - 1.0) * (double(A.W[4 * n + i]) - 0.5 * rho * (u * u + v * v + w * w));
+        cs = sqrt(A.gam * p * ir);
+        Vi = V[i];
+    }
+    T r[5] = {T(0), T(0), T(0), T(0), T(0)};
+    double sum = 0.0;
+    for (int k = ptr[i] + g; k < ptr[i + 1]; k += RG) {
+        const int it = item[k];
+        if (it >= 0) {
+            const int j = it >> 1;
+            const T s = (it & 1) ? T(1) : T(-1);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) r[q] += s * ff[q * tot + j];
+        } else {
+            const int64_t j = A.m + (-it - 1);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) r[q] -= ff[q * tot + j];
+        }
+        if (FIRST) {
+            double ax, ay, az, sa;
+            if (it >= 0) {
+                const int j = it >> 1;
+                ax = A.A[j];
+                ay = A.A[A.m + j];
+                az = A.A[2 * A.m + j];
+                sa = Ssum[j];
+            } else {
+                const int q = -it - 1;
+                ax = A.bA[q];
+                ay = A.bA[A.nb + q];
+                az = A.bA[2 * A.nb + q];
+                sa = sqrt(ax * ax + ay * ay + az * az);
+            }
+            const double uA = fabs(u * ax + v * ay + w * az);
+            const double lam = cs + (viscous ? 2.0 * mu * sa / (rho * Vi) : 0.0);
+            sum += uA + lam * sa;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) r[q] = row_sum(r[q]);
+    if (FIRST) sum = row_sum(sum);
+    if (g != 0) return;
+    if (FIRST) {
+        const T dti = T(cfl * Vi / sum);
+        const T h = dti / T(Vi);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const T rs = Rs[q * n + i];
+            F[q * n + i] = rs - r[q];
+            Dout[q * n + i] = h * rs;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            Wout[q * n + i] = A.W[q * n + i] + D[q * n + i];
+            Rout[q * n + i] = r[q] + F[q * n + i];
+        }
+    }
 }
 
 template <class T>
@@ -829,6 +925,27 @@ static Level *level_of(cgks_ctx *c, int level)
 }
 
 // R = KFVS residual of W (+ add when given)
+template <class T> static CoarseArgs<T> coarse_args(cgks_ctx *c, int level, const T *W, T *ff)
+{
+    Level *L = level_of(c, level);
+    CoarseArgs<T> A;
+    A.n = L->n;
+    A.m = L->m;
+    A.nb = L->nb;
+    A.gam = c->prm.gamma;
+    A.K = (5.0 - 3.0 * c->prm.gamma) / (c->prm.gamma - 1.0);
+    A.W = W;
+    A.pa = L->pa.p;
+    A.pb = L->pb.p;
+    A.bown = L->bown.p;
+    A.btag = L->btag.p;
+    A.A = L->A.p;
+    A.bA = L->bA.p;
+    A.bc = c->bc.p;
+    A.fflux = ff;
+    return A;
+}
+
 template <class T> static void kfvs_impl(cgks_ctx *c, int level, const T *W, T *R, T *ff, const T *add = nullptr)
 {
     Level *L = level_of(c, level);
@@ -848,7 +965,7 @@ template <class T> static void kfvs_impl(cgks_ctx *c, int level, const T *W, T *
     A.bc = c->bc.p;
     A.fflux = ff;
     const int64_t tot = L->m + L->nb;
-    hipLaunchKernelGGL((k_kfvs_face<T>), G1(tot), dim3(256), 0, c->stream, A);
+    hipLaunchKernelGGL((k_kfvs_face<T>), G1(tot), dim3(256), 0, c->stream, A, (const T *)nullptr);
     hipLaunchKernelGGL((k_kfvs_gather<T>), GR(L->n), dim3(256), 0, c->stream, L->n, tot, L->m, L->cf_ptr.p,
                        L->cf_item.p, ff, add, R);
 }
@@ -1159,34 +1276,6 @@ void coarse_implicit_fp32(cgks_ctx *c, int level, const double *W, const double 
 // is D = dt/V Res* exactly; the correction therefore vanishes with the fine
 // residual in any precision, and no bits of W0 are lost when it is prolonged.
 template <class T>
-__global__ void k_delta_first(int64_t n, const T *__restrict__ dt, const double *__restrict__ V, const T *__restrict__ Rs,
-                              T *__restrict__ D)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const T h = dt[i] / T(V[i]);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) D[q * n + i] = h * Rs[q * n + i];
-}
-
-// F = Res* - Res_2h(W0) and the first delta-form sweep D = dt/V Res* in one pass
-template <class T>
-__global__ void k_forcing_first(int64_t n, const T *__restrict__ Rs, const T *__restrict__ R0,
-                                const T *__restrict__ dt, const double *__restrict__ V, T *__restrict__ F,
-                                T *__restrict__ D)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const T h = dt[i] / T(V[i]);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        const T rs = Rs[q * n + i];
-        F[q * n + i] = rs - R0[q * n + i];
-        D[q * n + i] = h * rs;
-    }
-}
-
-template <class T>
 __global__ void k_delta_update(int64_t n, const T *__restrict__ dt, const double *__restrict__ V, const T *__restrict__ R,
                                const T *__restrict__ F, T *__restrict__ D)
 {
@@ -1257,13 +1346,16 @@ template <class T> static void fas_level(cgks_ctx *c, int l, int pre_done)
     Level *L = c->lev[l];
     LevelBufs<T> b = bufs<T>(L);
     hipStream_t st = c->stream;
-    const int64_t n5 = 5 * L->n;
     for (int s = pre_done; s < c->prm.nu_pre[l]; ++s) coarse_sweep<T>(c, l);
     if (l + 1 < (int)c->lev.size()) {
         Level *C = c->lev[l + 1];
         LevelBufs<T> cb = bufs<T>(C);
-        hipLaunchKernelGGL((k_sum_state<T>), G1(n5), dim3(256), 0, st, n5, b.W0, b.D, b.W);
-        kfvs_impl<T>(c, l, b.W, b.R, b.ff, b.F);  // Res_2h(W0 + D) + F
+        // fluxes at W0 + D, then W = W0 + D and Res_2h(W) + F in the gather
+        const CoarseArgs<T> ca = coarse_args<T>(c, l, b.W0, b.ff);
+        hipLaunchKernelGGL((k_kfvs_face<T>), G1(L->m + L->nb), dim3(256), 0, st, ca, (const T *)b.D);
+        hipLaunchKernelGGL((k_kfvs_rows<T, false>), GR(L->n), dim3(256), 0, st, ca, (const T *)b.ff, L->cf_ptr.p,
+                           L->cf_item.p, L->S.p, L->V.p, 0.0, 0.0, 0, (const T *)nullptr, (const T *)b.D, b.F,
+                           (T *)nullptr, b.W, b.R);
         hipLaunchKernelGGL((k_restrict<T, T>), GR(C->n), dim3(256), 0, st, C->n, C->nfine, C->c2f_ptr.p, C->c2f_idx.p,
                            L->V.p, C->V.p, b.W, b.R, cb.W0, cb.Rs);
         coarse_visit<T>(c, l + 1);
@@ -1282,14 +1374,18 @@ template <class T> static void coarse_visit(cgks_ctx *c, int l)
     LevelBufs<T> b = bufs<T>(L);
     hipStream_t st = c->stream;
     const int64_t n = L->n, n5 = 5 * n;
-    kfvs_impl<T>(c, l, b.W0, b.R, b.ff);
     const int npre = c->prm.nu_pre[l];
     const bool implicit = c->prm.coarse_smoother == 1;
     // the first sweep at W = W0 has right-hand side Res_2h(W0) + F = Res* exactly
     if (npre > 0 && !implicit) {
-        coarse_dt_impl<T>(c, l, b.W0, b.dt);
-        hipLaunchKernelGGL((k_forcing_first<T>), G1(n), dim3(256), 0, st, n, b.Rs, b.R, b.dt, L->V.p, b.F, b.D);
+        // face fluxes at W0, then the gather with the local step, forcing and first sweep
+        const CoarseArgs<T> ca = coarse_args<T>(c, l, b.W0, b.ff);
+        hipLaunchKernelGGL((k_kfvs_face<T>), G1(L->m + L->nb), dim3(256), 0, st, ca, (const T *)nullptr);
+        hipLaunchKernelGGL((k_kfvs_rows<T, true>), GR(n), dim3(256), 0, st, ca, (const T *)b.ff, L->cf_ptr.p,
+                           L->cf_item.p, L->S.p, L->V.p, c->prm.cfl, c->prm.mu, c->prm.viscous, (const T *)b.Rs,
+                           (const T *)nullptr, b.F, b.D, (T *)nullptr, (T *)nullptr);
     } else {
+        kfvs_impl<T>(c, l, b.W0, b.R, b.ff);
         hipLaunchKernelGGL((k_coarse_forcing<T>), G1(n5), dim3(256), 0, st, n5, b.Rs, b.R, b.F);
         if (npre > 0) implicit_solve<T>(c, l, b.W0, b.Rs, b.D, false);
         else CGKS_HIP(hipMemsetAsync(b.D, 0, sizeof(T) * n5, st));
