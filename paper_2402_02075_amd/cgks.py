@@ -129,14 +129,17 @@ class Solver:
         self._check(lib().cgks_set_stream(self.h, C.c_void_p(s)))
 
     def set_params(self, **kw):
+        """Change parameters; on an error from the library the previous parameters stay in force."""
+        p = Params.from_buffer_copy(self.params)
         for k, v in kw.items():
             if k in ("nu_pre", "nu_post"):
-                arr = getattr(self.params, k)
+                arr = getattr(p, k)
                 for i, x in enumerate(v):
                     arr[i] = int(x)
             else:
-                setattr(self.params, k, v)
-        self._check(lib().cgks_set_params(self.h, C.byref(self.params)))
+                setattr(p, k, v)
+        self._check(lib().cgks_set_params(self.h, C.byref(p)))
+        self.params = p
 
     def close(self):
         if getattr(self, "h", None):
@@ -291,7 +294,8 @@ class Solver:
 
     def coarse_implicit(self, level, W, rhs):
         """Increment of the implicit coarse smoother (Sec. 4.3) on `level` at state W for rhs."""
-        dU = self.empty(5, self.level_sizes[level])
+        n = self.level_sizes[level] if 0 <= level < len(self.level_sizes) else 1  # the library rejects bad levels
+        dU = self.empty(5, n)
         self._check(lib().cgks_coarse_implicit(self.h, int(level), _ptr(W), _ptr(rhs), _ptr(dU)))
         return dU
 

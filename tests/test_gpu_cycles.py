@@ -69,3 +69,31 @@ def test_cycle_variant_matches_oracle(oracle, cg, torch, mesh, variant):
     say(f"    levels {list(sizes)}; max state error per quantity " + " ".join(f"{e:.1e}" for e in err.max(axis=1)))
     assert err.max() < 1e-12
     np.testing.assert_allclose(ad.cpu().numpy(), al, rtol=1e-9)
+
+
+def test_cycle_parameters_and_implicit_entry_point_errors(cg, torch, mesh):
+    """Out-of-range cycle parameters and coarse levels are rejected with an error, not run."""
+    S = cg.Solver()
+    with pytest.raises(cg.CgksError):
+        S.set_params(cycle_gamma=4)
+    with pytest.raises(cg.CgksError):
+        S.set_params(coarse_smoother=2)
+    with pytest.raises(cg.CgksError):
+        S.set_params(relax_sweeps=65)
+    with pytest.raises(cg.CgksError):
+        S.set_params(coarse_smoother=1, cfl_implicit=0.0)
+    S.set_params(coarse_smoother=0, cfl_implicit=0.25, relax_sweeps=2, cycle_gamma=1)
+    S.set_mesh(mesh)
+    for tag, kind, prim in _bcs():
+        S.set_bc(tag, kind, prim)
+    sizes = S.agglomerate()
+    W = to_dev(torch, mg.uniform_state(mesh.n_cells)[0])
+    Wc, _ = S.restrict(1, W, torch.zeros_like(W))
+    with pytest.raises(cg.CgksError):
+        S.coarse_implicit(len(sizes), Wc, Wc)  # no such level
+    with pytest.raises(cg.CgksError):
+        S.coarse_implicit(0, W, W)  # the fine level has no coarse smoother
+    # zero right-hand side: zero increment up to rounding (the flux differences F(U + 0) - F(U) are
+    # formed with fused multiply-adds, so they need not cancel to the last bit)
+    dU = S.coarse_implicit(1, Wc, torch.zeros_like(Wc))
+    assert float(dU.abs().max()) < 1e-15
