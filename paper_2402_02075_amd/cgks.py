@@ -49,7 +49,7 @@ def lib():
     global _LIB
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} not built: run __graft_entry__.build() (hipcc, gfx950)")
+            raise ImportError(f"{LIB_PATH} not built: run python -m paper_2402_02075_amd.build (hipcc, gfx950)")
         L = C.CDLL(LIB_PATH)
         P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int32, C.c_double
         sig = {
