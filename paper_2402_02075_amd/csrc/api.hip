@@ -39,6 +39,18 @@ static void need_mesh(const cgks_ctx *c)
     if (!c->has_mesh) throw Error{CGKS_E_STATE, "no mesh: call cgks_set_mesh first"};
 }
 
+// evaluations that reach boundary faces need a condition for every tag the mesh uses
+static void need_bc(const cgks_ctx *c)
+{
+    need_mesh(c);
+    const uint64_t missing = c->tags_used & ~c->tags_set;
+    if (missing) {
+        int t = 0;
+        while (!((missing >> t) & 1)) ++t;
+        throw Error{CGKS_E_STATE, "boundary tag " + std::to_string(t) + " has no boundary condition: call cgks_set_bc"};
+    }
+}
+
 static void check_params(const cgks_params *p)
 {
     if (!(p->gamma > 1.0 && p->gamma < 5.0 / 3.0 + 1e-12)) throw Error{CGKS_E_ARG, "gamma must be in (1, 5/3]"};
@@ -186,6 +198,7 @@ cgks_status cgks_set_bc(cgks_ctx *c, int32_t tag, int32_t kind, const double *pr
     if (kind == CGKS_BC_FARFIELD && (!prim || !(prim[0] > 0.0) || !(prim[4] > 0.0)))
         throw Error{CGKS_E_ARG, "far field needs rho > 0 and p > 0"};
     c->bc_host.kind[tag] = kind;
+    c->tags_set |= uint64_t(1) << tag;
     for (int k = 0; k < 5; ++k) c->bc_host.prim[tag][k] = prim ? prim[k] : 0.0;
     CGKS_HIP(hipMemcpyAsync(c->bc.p, &c->bc_host, sizeof(BcTable), hipMemcpyHostToDevice, c->stream));
     CGKS_HIP(hipStreamSynchronize(c->stream));
@@ -231,7 +244,7 @@ cgks_status cgks_local_dt(cgks_ctx *c, const double *W, double *dt)
 cgks_status cgks_reconstruct(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef)
 {
     API_BEGIN(c)
-    need_mesh(c);
+    need_bc(c);
     if (!W || !G || !coef) throw Error{CGKS_E_ARG, "null pointer"};
     launch_recon(c, W, G, alpha, coef, false);
     CGKS_HIP(hipGetLastError());
@@ -242,7 +255,7 @@ cgks_status cgks_residual(cgks_ctx *c, const double *W, const double *G, const d
                           double *alpha_new)
 {
     API_BEGIN(c)
-    need_mesh(c);
+    need_bc(c);
     if (!W || !G || !R || (G_new == nullptr) != (alpha_new == nullptr))
         throw Error{CGKS_E_ARG, "W, G, R required; G_new and alpha_new both or neither"};
     launch_local_dt(c, W, c->dtc.p);
@@ -257,7 +270,7 @@ cgks_status cgks_residual(cgks_ctx *c, const double *W, const double *G, const d
 cgks_status cgks_wall_force(cgks_ctx *c, const double *W, const double *G, const double *alpha, int32_t tag, double *F)
 {
     API_BEGIN(c)
-    need_mesh(c);
+    need_bc(c);
     if (!W || !G || !F) throw Error{CGKS_E_ARG, "W, G and F required"};
     if (tag < 1 || tag > 63) throw Error{CGKS_E_ARG, "tag must be in 1..63"};
     launch_local_dt(c, W, c->dtc.p);
@@ -271,7 +284,7 @@ cgks_status cgks_wall_force(cgks_ctx *c, const double *W, const double *G, const
 cgks_status cgks_linearize(cgks_ctx *c, const double *W, const double *G, const double *alpha)
 {
     API_BEGIN(c)
-    need_mesh(c);
+    need_bc(c);
     if (!W || !G) throw Error{CGKS_E_ARG, "W and G required"};
     adj_linearize(c, W, G, alpha);
     API_END(c)
@@ -281,7 +294,7 @@ cgks_status cgks_vjp_residual(cgks_ctx *c, const double *barR, const double *bar
                               double *barW, double *barG, double *barAlpha)
 {
     API_BEGIN(c)
-    need_mesh(c);
+    need_bc(c);
     if (!barR || !barW || !barG) throw Error{CGKS_E_ARG, "barR, barW and barG required"};
     adj_vjp_residual(c, barR, barGnew, barAnew, barW, barG, barAlpha, false);
     CGKS_HIP(hipGetLastError());
@@ -292,7 +305,7 @@ cgks_status cgks_vjp_wall_force(cgks_ctx *c, int32_t tag, const double *e, doubl
                                 double *barAlpha)
 {
     API_BEGIN(c)
-    need_mesh(c);
+    need_bc(c);
     if (!e || !barW || !barG) throw Error{CGKS_E_ARG, "e, barW and barG required"};
     if (tag < 1 || tag > 63) throw Error{CGKS_E_ARG, "tag must be in 1..63"};
     adj_vjp_wall(c, tag, e, barW, barG, barAlpha, false);
@@ -303,7 +316,7 @@ cgks_status cgks_vjp_wall_force(cgks_ctx *c, int32_t tag, const double *e, doubl
 cgks_status cgks_vjp_kfvs(cgks_ctx *c, int32_t level, const double *Wc, const double *barRc, double *barWc)
 {
     API_BEGIN(c)
-    need_mesh(c);
+    need_bc(c);
     if (!Wc || !barRc || !barWc) throw Error{CGKS_E_ARG, "null pointer"};
     adj_vjp_kfvs(c, level, Wc, barRc, barWc, false);
     CGKS_HIP(hipGetLastError());
@@ -315,7 +328,7 @@ cgks_status cgks_adjoint_solve(cgks_ctx *c, int32_t tag, const double *e, int32_
                                double *hist, int32_t *n_done)
 {
     API_BEGIN(c)
-    need_mesh(c);
+    need_bc(c);
     if (!e || !n_done || max_iter < 1) throw Error{CGKS_E_ARG, "e, n_done and max_iter >= 1 required"};
     if (tag < 1 || tag > 63) throw Error{CGKS_E_ARG, "tag must be in 1..63"};
     *n_done = adj_solve(c, tag, e, max_iter, tol, lamW, lamG, lamA, cR, cG, cA, hist);
@@ -325,7 +338,7 @@ cgks_status cgks_adjoint_solve(cgks_ctx *c, int32_t tag, const double *e, int32_
 cgks_status cgks_step(cgks_ctx *c, double *W, double *G, double *alpha, double dt_global, double *resnorm)
 {
     API_BEGIN(c)
-    need_mesh(c);
+    need_bc(c);
     if (!W || !G || !alpha) throw Error{CGKS_E_ARG, "null pointer"};
     if (dt_global <= 0.0) {
         launch_local_dt(c, W, c->dtc.p);
@@ -408,7 +421,7 @@ cgks_status cgks_level_map(cgks_ctx *c, int32_t level, int32_t *f2c)
 cgks_status cgks_kfvs_residual(cgks_ctx *c, int32_t level, const double *W, double *R)
 {
     API_BEGIN(c)
-    need_mesh(c);
+    need_bc(c);
     level_at(c, level);
     if (!W || !R) throw Error{CGKS_E_ARG, "null pointer"};
     if (c->prm.precision == 1) kfvs_residual_fp32(c, level, W, R);
@@ -420,7 +433,7 @@ cgks_status cgks_kfvs_residual(cgks_ctx *c, int32_t level, const double *W, doub
 cgks_status cgks_coarse_implicit(cgks_ctx *c, int32_t level, const double *W, const double *rhs, double *dU)
 {
     API_BEGIN(c)
-    need_mesh(c);
+    need_bc(c);
     level_at(c, level);
     if (!W || !rhs || !dU) throw Error{CGKS_E_ARG, "null pointer"};
     if (!(c->prm.cfl_implicit > 0.0)) throw Error{CGKS_E_ARG, "cfl_implicit must be positive"};
@@ -457,7 +470,7 @@ cgks_status cgks_vcycle(cgks_ctx *c, double *W, double *G, double *alpha, int32_
                         double *hist, int32_t *n_done)
 {
     API_BEGIN(c)
-    need_mesh(c);
+    need_bc(c);
     if (!W || !G || !alpha || max_cycles < 0) throw Error{CGKS_E_ARG, "bad arguments"};
     if (c->prm.levels > 1 && (int)c->lev.size() != c->prm.levels) build_hierarchy(c);
     if (n_done) *n_done = 0;

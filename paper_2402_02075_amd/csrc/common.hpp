@@ -136,6 +136,8 @@ struct cgks_ctx {
     // fine mesh sizes
     int64_t N = 0, F = 0, Fi = 0, Fb = 0, NGP = 0;
     bool has_mesh = false;
+    uint64_t tags_used = 0;  // bit t: the mesh has boundary faces with tag t
+    uint64_t tags_set = 0;   // bit t: a boundary condition was given for tag t
 
     // fine geometry (internal order = caller order for cells)
     cgks::DBuf<double> vol, cen, mom2;  // [N], [3][N], [6][N]

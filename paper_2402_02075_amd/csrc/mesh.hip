@@ -629,6 +629,8 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
     c->fl.upload(hfl, s);
     c->fr.upload(hfr, s);
     c->ftag.upload(htag, s);
+    c->tags_used = 0;
+    for (int64_t f = Fi; f < F; ++f) c->tags_used |= uint64_t(1) << (htag[f] & 63);
     c->cf_ptr.upload(cfp, s);
     c->cf_face.upload(cff, s);
     c->n_int.upload(nint, s);
