@@ -5,8 +5,9 @@
  * hybrid tet/pyramid/prism/hex meshes, arXiv 2402.02075 (Liu, Ji, Mao, Ding,
  * Xu).  Fine level: third-order CGKS (HWENO reconstruction, BGK interface
  * solution at face Gauss points, Gauss-Green update of cell-averaged
- * gradients); coarse levels: first-order KFVS with forward Euler, on meshes
- * built by two-step random-hash agglomeration; three-level V-cycle.
+ * gradients); coarse levels: first-order KFVS with forward Euler (or the
+ * implicit smoother of Sec. 4.3), on meshes built by two-step random-hash
+ * agglomeration; three-level V-cycle (levels, sweeps and W-cycles configurable).
  *
  * Conventions for every call:
  *  - Return value: CGKS_OK (0) or a negative cgks_status; cgks_last_error()
@@ -22,6 +23,9 @@
  *  - No call synchronises the device except where stated (mesh set-up,
  *    agglomeration, and the once-per-cycle residual read of cgks_vcycle).
  *  - One context per host thread; contexts are independent.
+ *  - Calls that evaluate boundary faces (reconstruction, residual, step, wall force, the
+ *    adjoint calls, coarse KFVS and implicit smoother, V-cycle) return CGKS_E_STATE while a
+ *    boundary tag used by the mesh has no condition from cgks_set_bc.
  */
 #ifndef CGKS_H
 #define CGKS_H
