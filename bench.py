@@ -172,6 +172,67 @@ def shock_regime(cg, mg, cycles):
     return res
 
 
+def sphere_throughput(cg, mg, levels):
+    """Throughput on the larger synthetic meshes: the viscous sphere (Mach 0.2, Re 100 on D, Pr 0.72,
+    adiabatic no-slip wall, Riemann far field at r = 20) on the icosphere-level-5 mesh (1.47M cells)
+    and level 6 (6.14M cells): isolated residual evaluations in FP64 and with the FP32 Gauss-point
+    flux, and V-cycles, on a state developed by 200 V-cycles."""
+    import torch
+    res = {}
+    shape = {5: (32, 12), 6: (33, 12)}
+    for lev in levels:
+        nl, npr = shape[lev]
+        m = mg.sphere_shell(level=lev, n_layers=nl, n_prism=npr)
+        S = cg.Solver(viscous=1, mu=2e-3, prandtl=0.72)
+        t0 = time.perf_counter()
+        S.set_mesh(m)
+        t_mesh = time.perf_counter() - t0
+        S.set_bc(mg.TAG_SPHERE, cg.BC_NOSLIP_ADIABATIC)
+        S.set_bc(mg.TAG_FARFIELD, cg.BC_FARFIELD, np.array([1.0, 0.2, 0.0, 0.0, 1.0 / 1.4]))
+        t0 = time.perf_counter()
+        sizes = S.agglomerate()
+        t_agg = time.perf_counter() - t0
+        W0, G0 = mg.uniform_state(m.n_cells, vel=(0.2, 0.0, 0.0))
+        W = torch.from_numpy(W0).cuda()
+        G = torch.from_numpy(G0).cuda()
+        al = torch.ones(m.n_cells, dtype=torch.float64, device="cuda")
+        S.vcycle(W, G, al, 200, 0.0)
+        out = {"cells": m.n_cells, "faces": S.n_faces, "gauss_points": S.n_gp, "level_cells": [int(x) for x in sizes],
+               "setup_s": {"mesh_and_geometry": t_mesh, "agglomeration": t_agg}}
+        for prec, key in ((0, "fp64"), (1, "fp32_flux")):
+            S.set_params(precision=prec)
+            for _ in range(3):
+                S.residual(W, G, al)
+            torch.cuda.synchronize()
+            S.timing_start()
+            t0 = time.perf_counter()
+            n_iso = 20
+            for _ in range(n_iso):
+                S.residual(W, G, al)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / n_iso
+            face_ms, face_n = S.timing_stop()
+            out[f"residual_evals_per_s_{key}"] = 1.0 / dt
+            out[f"face_kernel_ms_{key}"] = face_ms / max(face_n, 1)
+        S.set_params(precision=0)
+        S.check()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.vcycle(W, G, al, 20, 0.0)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / 20
+        out["vcycle_ms"] = ms
+        out["residual_evals_per_s_in_vcycles"] = 2.0 / (ms * 1e-3)
+        out["cells_evals_per_s"] = out["residual_evals_per_s_in_vcycles"] * m.n_cells
+        res[f"icosphere_level_{lev}"] = out
+        log(f"sphere level {lev}: {m.n_cells} cells, residual {1e3 / out['residual_evals_per_s_fp64']:.2f} ms "
+            f"(FP32 flux {1e3 / out['residual_evals_per_s_fp32_flux']:.2f} ms), V-cycle {ms:.2f} ms")
+        S.close()
+        del W, G, al
+        torch.cuda.empty_cache()
+    return res
+
+
 def explicit_vs_vcycle(cg, mg, cap):
     """The paper's multigrid comparison (single-level explicit CGKS against the 3-level V-cycle):
     iterations and time to residual drops of 1e-4 ... 1e-10 on the hexahedral channel
@@ -325,6 +386,8 @@ def main():
                     help="max cycles for the time-to-1e-10 runs on the all-hexahedral channel (0: skip)")
     ap.add_argument("--shock-cycles", type=int, default=8000,
                     help="V-cycles of the Mach 1.2 / 0.95 viscous sphere runs (0: skip)")
+    ap.add_argument("--sphere-levels", default="5,6",
+                    help="icosphere levels of the viscous-sphere throughput runs (5: 1.47M, 6: 6.14M cells; 0 skips)")
     ap.add_argument("--explicit-cap", type=int, default=200000,
                     help="max iterations of the explicit vs V-cycle comparison on a 6,144-cell channel (0: skip)")
     ap.add_argument("--hierarchy-study", type=int, default=0,
@@ -441,6 +504,8 @@ def main():
         out["adjoint"] = adjoint_measurements(cg, mg, S, W, G, al)
     if args.converge_hex:
         out["time_to_1e-10_hex_channel"] = hex_convergence(cg, mg, args.converge_hex)
+    if args.sphere_levels not in ("", "0"):
+        out["sphere_throughput"] = sphere_throughput(cg, mg, [int(x) for x in args.sphere_levels.split(",")])
     if args.explicit_cap:
         out["explicit_vs_vcycle"] = explicit_vs_vcycle(cg, mg, args.explicit_cap)
     if args.hierarchy_study:
