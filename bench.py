@@ -78,22 +78,38 @@ def cpu_baseline(mg, budget_s=15.0):
     G = np.zeros((15, m.n_cells))
     al = np.ones(m.n_cells)
     par = om.params()
-    rng = np.random.default_rng(0)
-    n_sub = 256
-    elapsed, done = 0.0, 0
-    while elapsed < budget_s and done < m.n_cells:
-        sub = rng.choice(m.n_cells, n_sub, replace=False)
-        t0 = time.perf_counter()
-        M.residual(par, W, G, al, sub=sub)
-        elapsed += time.perf_counter() - t0
-        done += n_sub
-        if elapsed < 1.0:
-            n_sub *= 2
-    cells_per_s = done / elapsed
+
+    def rate(budget):
+        rng = np.random.default_rng(0)
+        n_sub = 256
+        elapsed, done = 0.0, 0
+        while elapsed < budget and done < m.n_cells:
+            sub = rng.choice(m.n_cells, n_sub, replace=False)
+            t0 = time.perf_counter()
+            M.residual(par, W, G, al, sub=sub)
+            elapsed += time.perf_counter() - t0
+            done += n_sub
+            if elapsed < 1.0:
+                n_sub *= 2
+        return done / elapsed, done, elapsed
+
+    cells_per_s, done, elapsed = rate(budget_s)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": cells_per_s / m.n_cells, "unit": "residual evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} randomly chosen cells of the {m.n_cells}-cell bump channel (oracle residual on a cell "
-                      f"subset, {elapsed:.1f} s), scaled to whole-mesh evaluations"}
+    out = {"value": cells_per_s / m.n_cells, "unit": "residual evals/s", "cores": threads, "kind": "oracle",
+           "sample": f"{done} randomly chosen cells of the {m.n_cells}-cell bump channel (oracle residual on a cell "
+                     f"subset, {elapsed:.1f} s), scaled to whole-mesh evaluations"}
+    # the same oracle on one core (its OpenMP loop limited to one thread)
+    try:
+        import ctypes
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        c1, d1, e1 = rate(budget_s / 3)
+        gomp.omp_set_num_threads(threads)
+        out["single_core"] = {"value": c1 / m.n_cells, "cores": 1,
+                              "sample": f"{d1} cells, {e1:.1f} s, scaled to whole-mesh evaluations"}
+    except OSError:
+        pass
+    return out
 
 
 def hex_convergence(cg, mg, max_cycles):
