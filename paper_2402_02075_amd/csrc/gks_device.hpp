@@ -205,10 +205,38 @@ template <class T> CGKS_HD void mcol0_acc(const T m[15], T s, T y[5])
     y[4] += s * m[4];
 }
 
+// Transport moment tr = sum_j <u_j psi psi^T> a_j of a full-space Maxwellian (the term the
+// compatibility condition, Eq. (co), balances against the time slope), with its micro-slopes
+// a_j fixed by rho <psi psi^T> a_j = dW_j.  Because g_x = g (a.psi) and the Maxwellian's moments
+// rho <u_j psi> are the Euler fluxes F_j(W) (K internal degrees of freedom: gamma - 1 = 2/(K + 3)),
+// rho tr = sum_j d/dx_j F_j = sum_j A_j(W) dW_j: the Euler flux Jacobians applied to the gradients,
+// formed here directly instead of from three moment matrices.
+template <class T> CGKS_HD void euler_divergence(const Side<T> &s, T K, T iK3, const T g[3][5], T tr[5])
+{
+    const T U[3] = {s.U, s.V, s.W};
+    const T gm1 = T(2) * iK3;
+    const T q2h = T(0.5) * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+    const T Ep = s.p * (T(0.5) * K + T(2.5)) + s.rho * q2h;  // E + p
+    T r[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const T *d = g[j];
+        const T dp = gm1 * (d[4] - (U[0] * d[1] + U[1] * d[2] + U[2] * d[3]) + q2h * d[0]);
+        const T rdu = d[1 + j] - U[j] * d[0];  // rho du_j
+        r[0] += d[1 + j];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) r[1 + i] += d[1 + i] * U[j] + U[i] * rdu + (i == j ? dp : T(0));
+        r[4] += (d[4] + dp) * U[j] + Ep * rdu * s.ir;
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) tr[c] = r[c] * s.ir;
+}
+
 // Space slopes a_j from local-frame gradients g[j][c], and the full-space transport moment
-// tr = sum_j <u_j a_j psi> (so that the time slope solves M A = -tr).
+// tr = sum_j <u_j a_j psi> (so that the time slope solves M A = -tr), the latter in its
+// closed form as the divergence of the Euler fluxes.
 template <class T>
-CGKS_HD void slopes(const Side<T> &s, const Tab<T> &full, T K, T iK3, const T g[3][5], T a[3][5], T A[5], T tr[5])
+CGKS_HD void slopes(const Side<T> &s, T K, T iK3, const T g[3][5], T a[3][5], T A[5], T tr[5])
 {
     const SlopeK<T> k = slope_k(s, K, iK3);
 #pragma unroll
@@ -218,15 +246,7 @@ CGKS_HD void slopes(const Side<T> &s, const Tab<T> &full, T K, T iK3, const T g[
         for (int c = 0; c < 5; ++c) b[c] = g[j][c] * s.ir;
         slope_solve(s, k, b, a[j]);
     }
-#pragma unroll
-    for (int c = 0; c < 5; ++c) tr[c] = T(0);
-    T m[15];
-    mmat<1, 0, 0>(full, m);
-    msym_acc(m, a[0], T(1), tr);
-    mmat<0, 1, 0>(full, m);
-    msym_acc(m, a[1], T(1), tr);
-    mmat<0, 0, 1>(full, m);
-    msym_acc(m, a[2], T(1), tr);
+    euler_divergence(s, K, iK3, g, tr);
     T b[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) b[c] = -tr[c];
@@ -274,9 +294,8 @@ CGKS_HD bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T
         const T(*g)[5] = side == 0 ? gl : gr;
         Tab<T> t;
         tab_vw(t, s, K);
-        tab_u_full(t, s);
         T a[3][5], A[5], tr[5];
-        slopes(s, t, K, iK3, g, a, A, tr);
+        slopes(s, K, iK3, g, a, A, tr);
         tab_u_half(t, s, side == 0 ? T(1) : T(-1));
         const T rho = s.rho;
         T m[15];
@@ -310,7 +329,7 @@ CGKS_HD bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T
         tab_vw(t, sc, K);
         tab_u_full(t, sc);
         T a[3][5], A[5], tr[5];
-        slopes(sc, t, K, iK3, dWc, a, A, tr);
+        slopes(sc, K, iK3, dWc, a, A, tr);
         const T rho = sc.rho;
         T m[15];
 #pragma unroll
@@ -456,9 +475,8 @@ CGKS_HD bool gks_flux_inviscid(const T wl[5], const T gl[3][5], const T wr[5], c
         const T(*g)[5] = side == 0 ? gl : gr;
         Tab<T> t;
         tab_vw(t, s, K);
-        tab_u_full(t, s);
         T a[3][5], A[5], tr[5];
-        slopes(s, t, K, iK3, g, a, A, tr);
+        slopes(s, K, iK3, g, a, A, tr);
         tab_u_half(t, s, side == 0 ? T(1) : T(-1));
         const T rho = s.rho;
         T m[15];
@@ -493,7 +511,7 @@ CGKS_HD bool gks_flux_inviscid(const T wl[5], const T gl[3][5], const T wr[5], c
     tab_vw(t, sc, K);
     tab_u_full(t, sc);
     T a[3][5], A[5], tr[5];
-    slopes(sc, t, K, iK3, dWc, a, A, tr);
+    slopes(sc, K, iK3, dWc, a, A, tr);
     const T rho = sc.rho;
     if (VAL) {
         // rho_c <psi {1, a_c.u, A_c}> = {W_c, rho tr, -rho tr}
