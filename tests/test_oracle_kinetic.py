@@ -101,6 +101,39 @@ def test_micro_slopes_satisfy_moment_equations(oracle):
     np.testing.assert_allclose(res, 0.0, atol=1e-11)
 
 
+def _euler_flux_dir(W, j, gamma=GAMMA):
+    """Euler flux along axis j (works on complex W for complex-step derivatives)."""
+    rho, m, E = W[0], W[1:4], W[4]
+    u = m / rho
+    p = (gamma - 1) * (E - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]))
+    e = np.zeros(3)
+    e[j] = 1.0
+    return np.concatenate([[m[j]], m * u[j] + p * e, [u[j] * (E + p)]])
+
+
+def test_time_slope_is_euler_time_derivative(oracle):
+    """The time slope A of the compatibility condition, Eq. (co), moves the conserved variables at
+    the rate the Euler equations give: rho <A psi> = -sum_j (dF_j/dW) dW_j.  The flux Jacobians here
+    are complex-step derivatives of the Euler fluxes, so the pin is independent of the moment
+    algebra; it fails for a wrong K, a wrong moment of order three or four, or a sign slip."""
+    rng = np.random.default_rng(4)
+    for _ in range(4):
+        rho, lam = rng.uniform(0.5, 2.0), rng.uniform(0.4, 2.5)
+        U = rng.normal(scale=0.6, size=3)
+        W = cons(rho, U, rho / (2 * lam))
+        dW = rng.normal(size=(3, 5))
+        a, A = oracle.slopes(rho, U, lam, K, dW)
+        ref = np.zeros(5)
+        h = 1e-30
+        for j in range(3):
+            jac = np.stack([_euler_flux_dir(W + 1j * h * e, j).imag / h for e in np.eye(5)], axis=1)
+            ref -= jac @ dW[j]
+        psi, wts, _ = _psi_grid(U, lam)
+        s = np.tensordot(A, psi, axes=1)
+        got = rho * np.array([np.sum(wts * psi[al] * s) for al in range(5)])
+        np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("viscous", [False, True])
 @pytest.mark.parametrize("dt", [1e-3, 0.05])
 def test_uniform_state_gives_euler_flux(oracle, viscous, dt):
