@@ -205,40 +205,51 @@ template <class T> CGKS_HD void mcol0_acc(const T m[15], T s, T y[5])
     y[4] += s * m[4];
 }
 
-// Transport moment tr = sum_j <u_j psi psi^T> a_j of a full-space Maxwellian (the term the
-// compatibility condition, Eq. (co), balances against the time slope), with its micro-slopes
-// a_j fixed by rho <psi psi^T> a_j = dW_j.  Because g_x = g (a.psi) and the Maxwellian's moments
-// rho <u_j psi> are the Euler fluxes F_j(W) (K internal degrees of freedom: gamma - 1 = 2/(K + 3)),
-// rho tr = sum_j d/dx_j F_j = sum_j A_j(W) dW_j: the Euler flux Jacobians applied to the gradients,
-// formed here directly instead of from three moment matrices.
-template <class T> CGKS_HD void euler_divergence(const Side<T> &s, T K, T iK3, const T g[3][5], T tr[5])
+// The full-space Maxwellian family g = exp(theta . psi) has the Euler fluxes as its moments
+// rho <u_j psi> = F_j(W) (K internal degrees of freedom: gamma - 1 = 2/(K + 3)).  A change of
+// theta along a vector b moves g by g (b . psi), so rho <u_j psi psi^T> b = A_j(W) rho <psi psi^T> b
+// with A_j = dF_j/dW, the Euler flux Jacobian.  Two uses: the transport moment of the
+// compatibility condition, Eq. (co), rho sum_j <u_j psi psi^T> a_j = sum_j A_j dW_j (the micro-slopes
+// are fixed by rho <psi psi^T> a_j = dW_j), and the interface Maxwellian's flux and time-slope
+// moments rho <u psi> = F_x and rho <u psi psi^T> A = A_x (rho <psi psi^T> A).  Both are formed here
+// from the closed forms instead of from moment matrices.
+template <class T> struct EulerLin {
+    T U[3], q2h, Ep, gm1, ir;  // velocity, |U|^2/2, E + p, gamma - 1, 1/rho
+};
+template <class T> CGKS_HD EulerLin<T> euler_lin(const Side<T> &s, T K, T iK3)
 {
-    const T U[3] = {s.U, s.V, s.W};
-    const T gm1 = T(2) * iK3;
-    const T q2h = T(0.5) * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
-    const T Ep = s.p * (T(0.5) * K + T(2.5)) + s.rho * q2h;  // E + p
-    T r[5] = {T(0), T(0), T(0), T(0), T(0)};
+    EulerLin<T> e;
+    e.U[0] = s.U;
+    e.U[1] = s.V;
+    e.U[2] = s.W;
+    e.q2h = T(0.5) * (s.U * s.U + s.V * s.V + s.W * s.W);
+    e.Ep = s.p * (T(0.5) * K + T(2.5)) + s.rho * e.q2h;
+    e.gm1 = T(2) * iK3;
+    e.ir = s.ir;
+    return e;
+}
+// r += A_j(W) d
+template <class T> CGKS_HD void euler_jvp_acc(const EulerLin<T> &e, int j, const T d[5], T r[5])
+{
+    const T dp = e.gm1 * (d[4] - (e.U[0] * d[1] + e.U[1] * d[2] + e.U[2] * d[3]) + e.q2h * d[0]);
+    const T rdu = d[1 + j] - e.U[j] * d[0];  // rho du_j
+    r[0] += d[1 + j];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const T *d = g[j];
-        const T dp = gm1 * (d[4] - (U[0] * d[1] + U[1] * d[2] + U[2] * d[3]) + q2h * d[0]);
-        const T rdu = d[1 + j] - U[j] * d[0];  // rho du_j
-        r[0] += d[1 + j];
+    for (int i = 0; i < 3; ++i) r[1 + i] += d[1 + i] * e.U[j] + e.U[i] * rdu + (i == j ? dp : T(0));
+    r[4] += (d[4] + dp) * e.U[j] + e.Ep * rdu * e.ir;
+}
+// rho tr = sum_j A_j(W) dW_j
+template <class T> CGKS_HD void euler_divergence(const EulerLin<T> &e, const T g[3][5], T r[5])
+{
 #pragma unroll
-        for (int i = 0; i < 3; ++i) r[1 + i] += d[1 + i] * U[j] + U[i] * rdu + (i == j ? dp : T(0));
-        r[4] += (d[4] + dp) * U[j] + Ep * rdu * s.ir;
-    }
+    for (int c = 0; c < 5; ++c) r[c] = T(0);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) tr[c] = r[c] * s.ir;
+    for (int j = 0; j < 3; ++j) euler_jvp_acc(e, j, g[j], r);
 }
 
-// Space slopes a_j from local-frame gradients g[j][c], and the full-space transport moment
-// tr = sum_j <u_j a_j psi> (so that the time slope solves M A = -tr), the latter in its
-// closed form as the divergence of the Euler fluxes.
-template <class T>
-CGKS_HD void slopes(const Side<T> &s, T K, T iK3, const T g[3][5], T a[3][5], T A[5], T tr[5])
+// Space slopes a_j from local-frame gradients g[j][c].
+template <class T> CGKS_HD void space_slopes(const Side<T> &s, const SlopeK<T> &k, const T g[3][5], T a[3][5])
 {
-    const SlopeK<T> k = slope_k(s, K, iK3);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         T b[5];
@@ -246,11 +257,40 @@ CGKS_HD void slopes(const Side<T> &s, T K, T iK3, const T g[3][5], T a[3][5], T 
         for (int c = 0; c < 5; ++c) b[c] = g[j][c] * s.ir;
         slope_solve(s, k, b, a[j]);
     }
-    euler_divergence(s, K, iK3, g, tr);
+}
+
+// Space slopes a_j and the time slope A of a side Maxwellian: M A = -tr with
+// tr = sum_j <u_j a_j psi> from its closed form.
+template <class T>
+CGKS_HD void slopes(const Side<T> &s, T K, T iK3, const T g[3][5], T a[3][5], T A[5])
+{
+    const SlopeK<T> k = slope_k(s, K, iK3);
+    space_slopes(s, k, g, a);
+    T r[5];
+    euler_divergence(euler_lin(s, K, iK3), g, r);
     T b[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) b[c] = -tr[c];
+    for (int c = 0; c < 5; ++c) b[c] = -r[c] * s.ir;
     slope_solve(s, k, b, A);
+}
+
+// Interface Maxwellian (local frame): space slopes a_j, rho tr = sum_j A_j dW_j (= -rho <A psi>),
+// its Euler flux F_x(W) = rho <u psi> and A_x (rho tr) = -rho <u psi psi^T> A.
+template <class T>
+CGKS_HD void center_terms(const Side<T> &s, const T W[5], T K, T iK3, const T g[3][5], T a[3][5], T rtr[5],
+                          T fx[5], T jt[5])
+{
+    space_slopes(s, slope_k(s, K, iK3), g, a);
+    const EulerLin<T> e = euler_lin(s, K, iK3);
+    euler_divergence(e, g, rtr);
+    fx[0] = W[1];
+    fx[1] = W[1] * s.U + s.p;
+    fx[2] = W[1] * s.V;
+    fx[3] = W[1] * s.W;
+    fx[4] = e.Ep * s.U;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) jt[c] = T(0);
+    euler_jvp_acc(e, 0, rtr, jt);
 }
 
 struct GksCfg {
@@ -294,8 +334,8 @@ CGKS_HD bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T
         const T(*g)[5] = side == 0 ? gl : gr;
         Tab<T> t;
         tab_vw(t, s, K);
-        T a[3][5], A[5], tr[5];
-        slopes(s, K, iK3, g, a, A, tr);
+        T a[3][5], A[5];
+        slopes(s, K, iK3, g, a, A);
         tab_u_half(t, s, side == 0 ? T(1) : T(-1));
         const T rho = s.rho;
         T m[15];
@@ -325,23 +365,25 @@ CGKS_HD bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T
     const Side<T> sc = side_of(Wc, gam);
     if (!(sc.rho > T(0) && sc.lam > T(0))) return false;
     {
+        T a[3][5];
+        {
+            T rtr[5], fx[5], jt[5];
+            center_terms(sc, Wc, K, iK3, dWc, a, rtr, fx, jt);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                o.Vc[0][c] = Wc[c];
+                o.Vc[1][c] = rtr[c];   // rho_c <(a_c.u) psi>
+                o.Vc[2][c] = -rtr[c];  // compatibility: <A_c psi> = -<(a_c.u) psi>
+                o.Mc[0][c] = fx[c];    // rho_c <u psi>
+                o.Mc[2][c] = -jt[c];   // rho_c <u A_c psi>
+                o.Mc[1][c] = T(0);
+            }
+        }
+        const T rho = sc.rho;
         Tab<T> t;
         tab_vw(t, sc, K);
         tab_u_full(t, sc);
-        T a[3][5], A[5], tr[5];
-        slopes(sc, K, iK3, dWc, a, A, tr);
-        const T rho = sc.rho;
         T m[15];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            o.Vc[0][c] = Wc[c];
-            o.Vc[1][c] = rho * tr[c];   // rho_c <(a_c.u) psi>
-            o.Vc[2][c] = -rho * tr[c];  // compatibility: <A_c psi> = -<(a_c.u) psi>
-            o.Mc[0][c] = o.Mc[1][c] = o.Mc[2][c] = T(0);
-        }
-        mmat<1, 0, 0>(t, m);
-        mcol0_acc(m, rho, o.Mc[0]);
-        msym_acc(m, A, rho, o.Mc[2]);
         mmat<2, 0, 0>(t, m);
         msym_acc(m, a[0], rho, o.Mc[1]);
         mmat<1, 1, 0>(t, m);
@@ -475,8 +517,8 @@ CGKS_HD bool gks_flux_inviscid(const T wl[5], const T gl[3][5], const T wr[5], c
         const T(*g)[5] = side == 0 ? gl : gr;
         Tab<T> t;
         tab_vw(t, s, K);
-        T a[3][5], A[5], tr[5];
-        slopes(s, K, iK3, g, a, A, tr);
+        T a[3][5], A[5];
+        slopes(s, K, iK3, g, a, A);
         tab_u_half(t, s, side == 0 ? T(1) : T(-1));
         const T rho = s.rho;
         T m[15];
@@ -507,21 +549,24 @@ CGKS_HD bool gks_flux_inviscid(const T wl[5], const T gl[3][5], const T wr[5], c
     }
     const Side<T> sc = side_of(Wc, gam);
     if (!(sc.rho > T(0) && sc.lam > T(0))) return false;
+    T a[3][5];
+    {
+        T rtr[5], fx[5], jt[5];
+        center_terms(sc, Wc, K, iK3, dWc, a, rtr, fx, jt);
+        if (VAL) {
+            // rho_c <psi {1, a_c.u, A_c}> = {W_c, rho tr, -rho tr}
+#pragma unroll
+            for (int c = 0; c < 5; ++c) Wt[c] += cw.c1 * Wc[c] + (cw.c2 - cw.c3) * rtr[c];
+        }
+        // rho_c <u psi {1, A_c}> = {F_x(W_c), -A_x rho tr}
+#pragma unroll
+        for (int c = 0; c < 5; ++c) F[c] += cf.c1 * fx[c] - cf.c3 * jt[c];
+    }
+    const T rho = sc.rho;
     Tab<T> t;
     tab_vw(t, sc, K);
     tab_u_full(t, sc);
-    T a[3][5], A[5], tr[5];
-    slopes(sc, K, iK3, dWc, a, A, tr);
-    const T rho = sc.rho;
-    if (VAL) {
-        // rho_c <psi {1, a_c.u, A_c}> = {W_c, rho tr, -rho tr}
-#pragma unroll
-        for (int c = 0; c < 5; ++c) Wt[c] += cw.c1 * Wc[c] + (cw.c2 - cw.c3) * (rho * tr[c]);
-    }
     T m[15];
-    mmat<1, 0, 0>(t, m);
-    mcol0_acc(m, cf.c1 * rho, F);
-    msym_acc(m, A, cf.c3 * rho, F);
     mmat<2, 0, 0>(t, m);
     msym_acc(m, a[0], cf.c2 * rho, F);
     mmat<1, 1, 0>(t, m);
