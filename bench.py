@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the same face kernel on this workload, from two rocprofv3 counter passes
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors read off a 1 GiB copy and fill in the same runs).
 # Set to None whenever the face kernel changes until the counters are taken again.
-FACE_HBM_BYTES_PER_LAUNCH = 452.8e6
+FACE_HBM_BYTES_PER_LAUNCH = 452.9e6
 
 
 def log(*a):
