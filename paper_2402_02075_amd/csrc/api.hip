@@ -258,8 +258,7 @@ cgks_status cgks_residual(cgks_ctx *c, const double *W, const double *G, const d
     need_bc(c);
     if (!W || !G || !R || (G_new == nullptr) != (alpha_new == nullptr))
         throw Error{CGKS_E_ARG, "W, G, R required; G_new and alpha_new both or neither"};
-    launch_local_dt(c, W, c->dtc.p);
-    launch_recon(c, W, G, alpha, c->coef.p);
+    launch_local_dt_recon(c, W, G, alpha, c->dtc.p, c->coef.p);
     const int mode = G_new ? MODE_RES : MODE_RESONLY;
     launch_face(c, mode, c->coef.p, c->dtc.p, -1.0, c->prm.precision == 1);
     launch_gather_res(c, R, G_new, alpha_new, mode);
@@ -273,8 +272,7 @@ cgks_status cgks_wall_force(cgks_ctx *c, const double *W, const double *G, const
     need_bc(c);
     if (!W || !G || !F) throw Error{CGKS_E_ARG, "W, G and F required"};
     if (tag < 1 || tag > 63) throw Error{CGKS_E_ARG, "tag must be in 1..63"};
-    launch_local_dt(c, W, c->dtc.p);
-    launch_recon(c, W, G, alpha, c->coef.p);
+    launch_local_dt_recon(c, W, G, alpha, c->dtc.p, c->coef.p);
     launch_face(c, MODE_RESONLY, c->coef.p, c->dtc.p, -1.0, false);
     launch_wall_force(c, tag, F);
     CGKS_HIP(hipGetLastError());
@@ -341,8 +339,7 @@ cgks_status cgks_step(cgks_ctx *c, double *W, double *G, double *alpha, double d
     need_bc(c);
     if (!W || !G || !alpha) throw Error{CGKS_E_ARG, "null pointer"};
     if (dt_global <= 0.0) {
-        launch_local_dt(c, W, c->dtc.p);
-        launch_recon(c, W, G, alpha, c->coef.p);
+        launch_local_dt_recon(c, W, G, alpha, c->dtc.p, c->coef.p);
         launch_face(c, MODE_RES, c->coef.p, c->dtc.p, -1.0, false);
         const int nb = gather_blocks(c->N);
         c->partial.ensure(nb);

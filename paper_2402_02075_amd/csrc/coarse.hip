@@ -1402,15 +1402,13 @@ void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flu
     c->partial.ensure(nb);
     const int npre = std::max(1, c->prm.nu_pre[0]);
     for (int s = 0; s < npre; ++s) {
-        launch_local_dt(c, W, c->dtc.p);
-        launch_recon(c, W, G, alpha, c->coef.p);
+        launch_local_dt_recon(c, W, G, alpha, c->dtc.p, c->coef.p);
         launch_face(c, MODE_RES, c->coef.p, c->dtc.p, -1.0, fp32_flux);
         launch_gather_fe(c, W, G, alpha, c->dtc.p, c->Rw.p, s == 0 ? c->partial.p : nullptr);
         if (s == 0) finish_norm(c, c->partial.p, nb, c->N, c->scal.p);
     }
     if (c->lev.size() > 1) {
-        launch_local_dt(c, W, c->dtc.p);
-        launch_recon(c, W, G, alpha, c->coef.p);
+        launch_local_dt_recon(c, W, G, alpha, c->dtc.p, c->coef.p);
         launch_face(c, MODE_RESONLY, c->coef.p, c->dtc.p, -1.0, fp32_flux);
         launch_gather_res(c, c->Rw.p, nullptr, nullptr, MODE_RESONLY);
         Level *L = c->lev[1];
@@ -1431,8 +1429,7 @@ void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flu
         }
     }
     for (int s = 0; s < c->prm.nu_post[0]; ++s) {
-        launch_local_dt(c, W, c->dtc.p);
-        launch_recon(c, W, G, alpha, c->coef.p);
+        launch_local_dt_recon(c, W, G, alpha, c->dtc.p, c->coef.p);
         launch_face(c, MODE_RES, c->coef.p, c->dtc.p, -1.0, fp32_flux);
         launch_gather_fe(c, W, G, alpha, c->dtc.p, c->Rw.p, nullptr);
     }

@@ -192,8 +192,13 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_cells
                 const int64_t *cptr, const int64_t *cnode, int64_t n_bf, const int64_t *bptr, const int64_t *bnode,
                 const int32_t *btag, const int64_t *canon);
 void launch_local_dt(cgks_ctx *c, const double *W, double *dt);
+// cell-major: coef[50 i + 10 c + k], else coef[(10 c + k) N + i]; ghosts_ready: the boundary
+// ghost states at W are already in bgq
 void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef,
-                  bool cell_major = true);  // cell-major: coef[50 i + 10 c + k], else coef[(10 c + k) N + i]
+                  bool cell_major = true, bool ghosts_ready = false);
+// launch_local_dt + launch_recon (cell-major) with the ghost states formed in the local-step launch
+void launch_local_dt_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *dt,
+                           double *coef);
 enum FaceMode { MODE_RES = 0, MODE_RESONLY = 1, MODE_S1 = 2, MODE_S2 = 3 };
 void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cell, double dt_global, bool fp32);
 void launch_gather_res(cgks_ctx *c, double *R, double *Gn, double *an, int mode);

@@ -18,13 +18,12 @@
 namespace cgks {
 
 // ---------------------------------------------------------------- local time step
-__global__ void k_local_dt(int64_t N, int64_t F, double gam, double cfl, double mu, int viscous,
-                           const double *__restrict__ W, const int32_t *__restrict__ cf_ptr,
-                           const int32_t *__restrict__ cf_face, const double *__restrict__ favec,
-                           const double *__restrict__ farea, const double *__restrict__ vol, double *__restrict__ dt)
+__device__ __forceinline__ void local_dt_one(int64_t i, int64_t N, int64_t F, double gam, double cfl, double mu,
+                                             int viscous, const double *__restrict__ W,
+                                             const int32_t *__restrict__ cf_ptr, const int32_t *__restrict__ cf_face,
+                                             const double *__restrict__ favec, const double *__restrict__ farea,
+                                             const double *__restrict__ vol, double *__restrict__ dt)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
     const double rho = W[i], ir = 1.0 / rho;
     const double u = W[N + i] * ir, v = W[2 * N + i] * ir, w = W[3 * N + i] * ir;
     const double p = (gam - 1.0) * (W[4 * N + i] - 0.5 * rho * (u * u + v * v + w * w));
@@ -42,6 +41,16 @@ __global__ void k_local_dt(int64_t N, int64_t F, double gam, double cfl, double 
     dt[i] = cfl * V / sum;
 }
 
+__global__ void k_local_dt(int64_t N, int64_t F, double gam, double cfl, double mu, int viscous,
+                           const double *__restrict__ W, const int32_t *__restrict__ cf_ptr,
+                           const int32_t *__restrict__ cf_face, const double *__restrict__ favec,
+                           const double *__restrict__ farea, const double *__restrict__ vol, double *__restrict__ dt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    local_dt_one(i, N, F, gam, cfl, mu, viscous, W, cf_ptr, cf_face, favec, farea, vol, dt);
+}
+
 // ---------------------------------------------------------------- reconstruction
 // One thread per (cell, conservative component): the reconstruction acts on each
 // component separately, so a block holds 64 consecutive cells (one operator group) and five
@@ -49,16 +58,14 @@ __global__ void k_local_dt(int64_t N, int64_t F, double gam, double cfl, double 
 // (39 x 64 doubles) are staged in LDS once per block and shared by the five waves, so every
 // operator byte crosses the memory hierarchy once.
 
-// Ghost states of the boundary faces at the current state, one thread per boundary face, for
-// the reconstruction's Green-Gauss term (each face's ghost is computed once, not per component).
-__global__ void k_bnd_ghost(int64_t N, int64_t F, int64_t Fi, const double *__restrict__ W,
-                            const int32_t *__restrict__ fl, const int32_t *__restrict__ ftag,
-                            const double *__restrict__ favec, const BcTable *__restrict__ bc, double gam,
-                            double *__restrict__ bgq)
+// Ghost state of boundary face Fi + b at the current state, for the reconstruction's
+// Green-Gauss term (each face's ghost is computed once, not per component).
+__device__ __forceinline__ void bnd_ghost_one(int64_t b, int64_t N, int64_t F, int64_t Fi, const double *__restrict__ W,
+                                              const int32_t *__restrict__ fl, const int32_t *__restrict__ ftag,
+                                              const double *__restrict__ favec, const BcTable *__restrict__ bc,
+                                              double gam, double *__restrict__ bgq)
 {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t Fb = F - Fi;
-    if (b >= Fb) return;
     const int64_t f = Fi + b;
     const int o = fl[f];
     const double av[3] = {favec[f], favec[F + f], favec[2 * F + f]};
@@ -70,6 +77,32 @@ __global__ void k_bnd_ghost(int64_t N, int64_t F, int64_t Fi, const double *__re
     ghost_state(*bc, ftag[f], n, Q0, gam, Qg);
 #pragma unroll
     for (int c = 0; c < 5; ++c) bgq[c * Fb + b] = Qg[c];
+}
+
+// One thread per boundary face.
+__global__ void k_bnd_ghost(int64_t N, int64_t F, int64_t Fi, const double *__restrict__ W,
+                            const int32_t *__restrict__ fl, const int32_t *__restrict__ ftag,
+                            const double *__restrict__ favec, const BcTable *__restrict__ bc, double gam,
+                            double *__restrict__ bgq)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= F - Fi) return;
+    bnd_ghost_one(b, N, F, Fi, W, fl, ftag, favec, bc, gam, bgq);
+}
+
+// The local steps of the cells and, in threads N.., the boundary ghost states at the same W
+// (both read only W and geometry): one launch before the reconstruction instead of two.
+__global__ void k_local_dt_ghost(int64_t N, int64_t F, int64_t Fi, double gam, double cfl, double mu, int viscous,
+                                 const double *__restrict__ W, const int32_t *__restrict__ cf_ptr,
+                                 const int32_t *__restrict__ cf_face, const double *__restrict__ favec,
+                                 const double *__restrict__ farea, const double *__restrict__ vol,
+                                 double *__restrict__ dt, const int32_t *__restrict__ fl,
+                                 const int32_t *__restrict__ ftag, const BcTable *__restrict__ bc,
+                                 double *__restrict__ bgq)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < N) local_dt_one(t, N, F, gam, cfl, mu, viscous, W, cf_ptr, cf_face, favec, farea, vol, dt);
+    else if (t - N < F - Fi) bnd_ghost_one(t - N, N, F, Fi, W, fl, ftag, favec, bc, gam, bgq);
 }
 
 // Green-Gauss contribution of a cell's boundary faces to component C, ghost states precomputed.
@@ -672,7 +705,18 @@ void launch_local_dt(cgks_ctx *c, const double *W, double *dt)
                        c->vol.p, dt);
 }
 
-void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef, bool cell_major)
+void launch_local_dt_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *dt,
+                           double *coef)
+{
+    const int64_t Fb = c->F - c->Fi;
+    hipLaunchKernelGGL(k_local_dt_ghost, dim3(blocks_for(c->N + Fb, 256)), dim3(256), 0, c->stream, c->N, c->F, c->Fi,
+                       c->prm.gamma, c->prm.cfl, c->prm.mu, c->prm.viscous, W, c->cf_ptr.p, c->cf_face.p, c->favec.p,
+                       c->farea.p, c->vol.p, dt, c->fl.p, c->ftag.p, c->bc.p, c->bgq.p);
+    launch_recon(c, W, G, alpha, coef, true, true);
+}
+
+void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef, bool cell_major,
+                  bool ghosts_ready)
 {
     ReconArgs A{};
     A.N = c->N;
@@ -702,7 +746,7 @@ void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *a
     A.Fi = c->Fi;
     A.Fb = c->F - c->Fi;
     A.bgq = c->bgq.p;
-    if (A.Fb > 0)
+    if (A.Fb > 0 && !ghosts_ready)
         hipLaunchKernelGGL(k_bnd_ghost, dim3(blocks_for(A.Fb, 256)), dim3(256), 0, c->stream, c->N, c->F, c->Fi, W,
                            c->fl.p, c->ftag.p, c->favec.p, c->bc.p, c->prm.gamma, c->bgq.p);
     const dim3 grid(blocks_for(c->N, OP_GROUP)), blk(5 * OP_GROUP);
