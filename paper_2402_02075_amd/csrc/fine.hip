@@ -304,7 +304,9 @@ __device__ __forceinline__ double face_prod(double v, int ln, int ngp)
 // One lane per face Gauss point, faces packed into waves with 3 or 4 lanes each (lane map
 // built at set-up), face sums by lane shuffles.
 // The work of one lane: its face's Gauss point k, given the lane's indices and geometry.
-template <class T, int MODE, bool VAL, bool INV>
+// FOLD: 0 = moment vectors then combination (all modes), 1 = time coefficients folded into the
+// moment sums, inviscid, 2 = folded, viscous (steady modes only).
+template <class T, int MODE, bool VAL, int FOLD>
 __device__ __forceinline__ void face_lane(const FaceArgs &A, const int4 id, const double g[10], int ln)
 {
     const int64_t N = A.N;
@@ -341,11 +343,11 @@ __device__ __forceinline__ void face_lane(const FaceArgs &A, const int4 id, cons
         T wl[5], wr[5], gl[3][5], gr[3][5];
         to_local(WL, GL, n, t1, t2, wl, gl);
         to_local(WR, GR, n, t1, t2, wr, gr);
-        if constexpr (INV) {
-            // inviscid residual modes: time coefficients folded into the moment sums
+        if constexpr (FOLD > 0) {
+            // steady residual modes: time coefficients folded into the moment sums
             T Fl[5], Wt[5], pl, pr;
-            if (!gks_flux_inviscid<T, MODE == MODE_RES>(wl, gl, wr, gr, T(A.cfg.gamma), T(A.cfg.K), T(dtf), A.cfg, Fl,
-                                                       Wt, pl, pr)) {
+            if (!gks_flux_folded<T, MODE == MODE_RES, FOLD == 2>(wl, gl, wr, gr, T(A.cfg.gamma), T(A.cfg.K), T(dtf),
+                                                                A.cfg, Fl, Wt, pl, pr)) {
                 atomicMin(A.bad, L);
             } else {
                 double Fg[5];
@@ -445,7 +447,7 @@ __device__ __forceinline__ void face_lane(const FaceArgs &A, const int4 id, cons
 
 // One lane per face Gauss point, faces packed into waves with 3 or 4 lanes each (lane map
 // built at set-up), face sums by lane shuffles.
-template <class T, int MODE, bool VAL, bool INV = false> __global__ __launch_bounds__(256) void k_face(FaceArgs A)
+template <class T, int MODE, bool VAL, int FOLD = 0> __global__ __launch_bounds__(256) void k_face(FaceArgs A)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t NL = A.NL;
@@ -453,7 +455,7 @@ template <class T, int MODE, bool VAL, bool INV = false> __global__ __launch_bou
     double g[10];
 #pragma unroll
     for (int q = 0; q < 10; ++q) g[q] = A.lgeo[q * NL + gid];
-    face_lane<T, MODE, VAL, INV>(A, id, g, (int)(threadIdx.x & 63));
+    face_lane<T, MODE, VAL, FOLD>(A, id, g, (int)(threadIdx.x & 63));
 }
 
 // ---------------------------------------------------------------- gathers
@@ -770,7 +772,6 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
     A.out = c->fout.p;
     A.bad = c->bad.p;
     const dim3 grid(blocks_for(c->NL, 256)), blk(256);
-    const bool prfix = c->prm.viscous && c->prm.prandtl != 1.0;  // heat-flux correction needs the value moments
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool timed = c->timing && mode == MODE_RES;
     if (timed) {
@@ -783,31 +784,30 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
         e1 = c->ev_pool[c->ev_used++];
         CGKS_HIP(hipEventRecord(e0, c->stream));
     }
-    // inviscid steady modes: the time coefficients are known before the moments (tau = 0)
+    // steady modes: time coefficients folded into the moment sums (inviscid: known before the
+    // moments; viscous: after a first pass for the interface state)
     const bool inv = !c->prm.viscous;
     if (fp32) {
         switch (mode) {
         case MODE_RES:
-            if (inv) hipLaunchKernelGGL((k_face<float, MODE_RES, true, true>), grid, blk, 0, c->stream, A);
-            else hipLaunchKernelGGL((k_face<float, MODE_RES, true>), grid, blk, 0, c->stream, A);
+            if (inv) hipLaunchKernelGGL((k_face<float, MODE_RES, true, 1>), grid, blk, 0, c->stream, A);
+            else hipLaunchKernelGGL((k_face<float, MODE_RES, true, 2>), grid, blk, 0, c->stream, A);
             break;
         case MODE_RESONLY:
-            if (inv) hipLaunchKernelGGL((k_face<float, MODE_RESONLY, false, true>), grid, blk, 0, c->stream, A);
-            else if (prfix) hipLaunchKernelGGL((k_face<float, MODE_RESONLY, true>), grid, blk, 0, c->stream, A);
-            else hipLaunchKernelGGL((k_face<float, MODE_RESONLY, false>), grid, blk, 0, c->stream, A);
+            if (inv) hipLaunchKernelGGL((k_face<float, MODE_RESONLY, false, 1>), grid, blk, 0, c->stream, A);
+            else hipLaunchKernelGGL((k_face<float, MODE_RESONLY, false, 2>), grid, blk, 0, c->stream, A);
             break;
         default: throw Error{CGKS_E_ARG, "FP32 flux supports the steady modes only"};
         }
     } else {
         switch (mode) {
         case MODE_RES:
-            if (inv) hipLaunchKernelGGL((k_face<double, MODE_RES, true, true>), grid, blk, 0, c->stream, A);
-            else hipLaunchKernelGGL((k_face<double, MODE_RES, true>), grid, blk, 0, c->stream, A);
+            if (inv) hipLaunchKernelGGL((k_face<double, MODE_RES, true, 1>), grid, blk, 0, c->stream, A);
+            else hipLaunchKernelGGL((k_face<double, MODE_RES, true, 2>), grid, blk, 0, c->stream, A);
             break;
         case MODE_RESONLY:
-            if (inv) hipLaunchKernelGGL((k_face<double, MODE_RESONLY, false, true>), grid, blk, 0, c->stream, A);
-            else if (prfix) hipLaunchKernelGGL((k_face<double, MODE_RESONLY, true>), grid, blk, 0, c->stream, A);
-            else hipLaunchKernelGGL((k_face<double, MODE_RESONLY, false>), grid, blk, 0, c->stream, A);
+            if (inv) hipLaunchKernelGGL((k_face<double, MODE_RESONLY, false, 1>), grid, blk, 0, c->stream, A);
+            else hipLaunchKernelGGL((k_face<double, MODE_RESONLY, false, 2>), grid, blk, 0, c->stream, A);
             break;
         case MODE_S1: hipLaunchKernelGGL((k_face<double, MODE_S1, true>), grid, blk, 0, c->stream, A); break;
         default: hipLaunchKernelGGL((k_face<double, MODE_S2, true>), grid, blk, 0, c->stream, A); break;

@@ -82,7 +82,7 @@ int main(int argc, char **argv)
     const Tally t_rot = g;
     // the inviscid steady path of the kernel: moments with the time coefficients folded in
     Cnt Fl[5], Fg[5], Wt[5], pl, pr;
-    gks_flux_inviscid<Cnt, true>(wl, gl, wr, gr, Cnt(gam), Cnt(cfg.K), dtf, cfg, Fl, Wt, pl, pr);
+    gks_flux_folded<Cnt, true, false>(wl, gl, wr, gr, Cnt(gam), Cnt(cfg.K), dtf, cfg, Fl, Wt, pl, pr);
     const Tally t_mom = g;
     to_global(Fl, n, t1, t2, Fg);
     const Cnt s = wS / dtf;

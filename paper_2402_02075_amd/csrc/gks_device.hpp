@@ -483,34 +483,63 @@ template <class T> CGKS_HD void value_at(const GksMoments<T> &m, T t, T tau, T t
     combine(c, m.Vc, m.Vk, Wt);
 }
 
-// Inviscid flux over [0, dt] and interface value at dt of one Gauss point with the time
-// coefficients applied while the moments accumulate.  Without viscosity the collision times
-// depend only on the two side pressures (tau = 0, tau_n from the pressure jump), so the
-// coefficients are known before the moment loops, and each kinetic and central moment vector
-// enters the result directly instead of being kept for a final combination: the same sums as
-// gks_moments + flux_integrated + value_at, with 30 fewer live values.
+// Flux over [0, dt] and interface value at dt of one Gauss point with the time coefficients
+// applied while the moments accumulate: the same sums as gks_moments + flux_integrated + value_at
+// without keeping the twelve moment vectors for a final combination.
+//  - Inviscid (VISC = false): tau = 0 and tau_n depends only on the two side pressures, so the
+//    coefficients are known before the moment loops.
+//  - Viscous (VISC = true): tau = mu/p_c needs the interface state first, so W_c is formed in a
+//    first pass over the two half-space Maxwellians (zeroth moments only); the flux moments are
+//    then folded as in the inviscid case.  The value moments rho <psi {1, a.u, A}> of the two
+//    sides are kept (15 values) because the interface value (coefficients at dt) and the Prandtl
+//    correction (coefficients integrated over [0, dt]) each combine them with their own set.
 // VAL = false skips the interface value.
-template <class T, bool VAL>
-CGKS_HD bool gks_flux_inviscid(const T wl[5], const T gl[3][5], const T wr[5], const T gr[3][5], T gam, T K, T dt,
-                               const GksCfg &cfg, T F[5], T Wt[5], T &pl, T &pr)
+template <class T, bool VAL, bool VISC>
+CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], const T gr[3][5], T gam, T K, T dt,
+                             const GksCfg &cfg, T F[5], T Wt[5], T &pl, T &pr)
 {
     const Side<T> sl = side_of(wl, gam), sr = side_of(wr, gam);
     if (!(sl.rho > T(0) && sr.rho > T(0) && sl.lam > T(0) && sr.lam > T(0))) return false;
     pl = sl.p;
     pr = sr.p;
-    const T taun = T(cfg.eps_tau) * dt + T(cfg.c_tau) * abs_((pl - pr) / (pl + pr)) * dt;
-    const TimeCoef<T> cf = coef_integrated(dt, T(0), taun);
-    TimeCoef<T> cw;
-    if (VAL) cw = coef_at(dt, T(0), taun);
-    const T iK3 = T(1) / (K + T(3));
+    const T jump = abs_((pl - pr) / (pl + pr));
     T Wc[5] = {T(0), T(0), T(0), T(0), T(0)};
+    T tau = T(0), taun;
+    if (VISC) {
+        // W_c = rho_l <psi>_{u>0} + rho_r <psi>_{u<0}, Eq. (compatibility2)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const Side<T> &s = side == 0 ? sl : sr;
+            Tab<T> t;
+            tab_vw(t, s, K);
+            tab_u_half(t, s, side == 0 ? T(1) : T(-1));
+            T q[5];
+            mpsi<0, 0, 0>(t, q);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) Wc[c] += s.rho * q[c];
+        }
+        const Side<T> s0 = side_of(Wc, gam);
+        if (!(s0.rho > T(0) && s0.lam > T(0))) return false;
+        tau = T(cfg.mu) / s0.p;
+        taun = tau + T(cfg.c_tau) * jump * dt;
+    } else {
+        taun = T(cfg.eps_tau) * dt + T(cfg.c_tau) * jump * dt;
+    }
+    const TimeCoef<T> cf = coef_integrated(dt, tau, taun);
+    TimeCoef<T> cw;
+    if (VAL) cw = coef_at(dt, tau, taun);
+    const T iK3 = T(1) / (K + T(3));
     T dWc[3][5];
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
         for (int c = 0; c < 5; ++c) dWc[j][c] = T(0);
+    T Vk[3][5];  // viscous: rho <psi {-, a.u, A}>_half summed over the sides (Vk[0] is W_c)
 #pragma unroll
-    for (int c = 0; c < 5; ++c) F[c] = Wt[c] = T(0);
+    for (int c = 0; c < 5; ++c) {
+        F[c] = Wt[c] = T(0);
+        Vk[1][c] = Vk[2][c] = T(0);
+    }
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         const Side<T> &s = side == 0 ? sl : sr;
@@ -523,22 +552,26 @@ CGKS_HD bool gks_flux_inviscid(const T wl[5], const T gl[3][5], const T wr[5], c
         const T rho = s.rho;
         T m[15];
         mmat<0, 0, 0>(t, m);  // <psi psi>_half
-        mcol0_acc(m, rho, Wc);
+        if (!VISC) mcol0_acc(m, rho, Wc);
 #pragma unroll
         for (int j = 0; j < 3; ++j) msym_acc(m, a[j], rho, dWc[j]);
-        if (VAL) {
+        if (VISC) {
+            msym_acc(m, A, rho, Vk[2]);
+        } else if (VAL) {
             mcol0_acc(m, cw.e * rho, Wt);
             msym_acc(m, A, -cw.k2 * rho, Wt);
         }
         mmat<1, 0, 0>(t, m);  // <u psi psi>_half
         mcol0_acc(m, cf.e * rho, F);
         msym_acc(m, A, -cf.k2 * rho, F);
-        if (VAL) {
-            msym_acc(m, a[0], -cw.k1 * rho, Wt);
+        if (VISC || VAL) {
+            const T sv = VISC ? rho : -cw.k1 * rho;
+            T *dst = VISC ? Vk[1] : Wt;
+            msym_acc(m, a[0], sv, dst);
             mmat<0, 1, 0>(t, m);
-            msym_acc(m, a[1], -cw.k1 * rho, Wt);
+            msym_acc(m, a[1], sv, dst);
             mmat<0, 0, 1>(t, m);
-            msym_acc(m, a[2], -cw.k1 * rho, Wt);
+            msym_acc(m, a[2], sv, dst);
         }
         mmat<2, 0, 0>(t, m);
         msym_acc(m, a[0], -cf.k1 * rho, F);
@@ -550,11 +583,21 @@ CGKS_HD bool gks_flux_inviscid(const T wl[5], const T gl[3][5], const T wr[5], c
     const Side<T> sc = side_of(Wc, gam);
     if (!(sc.rho > T(0) && sc.lam > T(0))) return false;
     T a[3][5];
+    T Q[5];  // viscous: time-integrated conserved variables for the Prandtl correction
     {
         T rtr[5], fx[5], jt[5];
         center_terms(sc, Wc, K, iK3, dWc, a, rtr, fx, jt);
-        if (VAL) {
-            // rho_c <psi {1, a_c.u, A_c}> = {W_c, rho tr, -rho tr}
+        // rho_c <psi {1, a_c.u, A_c}> = {W_c, rho tr, -rho tr}
+        if (VISC) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                const T vc = (cf.c2 - cf.c3) * rtr[c] + cf.c1 * Wc[c];
+                Q[c] = vc + cf.e * Wc[c] - cf.k1 * Vk[1][c] - cf.k2 * Vk[2][c];
+                if (VAL)
+                    Wt[c] = cw.c1 * Wc[c] + (cw.c2 - cw.c3) * rtr[c] + cw.e * Wc[c] - cw.k1 * Vk[1][c] -
+                            cw.k2 * Vk[2][c];
+            }
+        } else if (VAL) {
 #pragma unroll
             for (int c = 0; c < 5; ++c) Wt[c] += cw.c1 * Wc[c] + (cw.c2 - cw.c3) * rtr[c];
         }
@@ -562,17 +605,23 @@ CGKS_HD bool gks_flux_inviscid(const T wl[5], const T gl[3][5], const T wr[5], c
 #pragma unroll
         for (int c = 0; c < 5; ++c) F[c] += cf.c1 * fx[c] - cf.c3 * jt[c];
     }
-    const T rho = sc.rho;
-    Tab<T> t;
-    tab_vw(t, sc, K);
-    tab_u_full(t, sc);
-    T m[15];
-    mmat<2, 0, 0>(t, m);
-    msym_acc(m, a[0], cf.c2 * rho, F);
-    mmat<1, 1, 0>(t, m);
-    msym_acc(m, a[1], cf.c2 * rho, F);
-    mmat<1, 0, 1>(t, m);
-    msym_acc(m, a[2], cf.c2 * rho, F);
+    {
+        const T rho = sc.rho;
+        Tab<T> t;
+        tab_vw(t, sc, K);
+        tab_u_full(t, sc);
+        T m[15];
+        mmat<2, 0, 0>(t, m);
+        msym_acc(m, a[0], cf.c2 * rho, F);
+        mmat<1, 1, 0>(t, m);
+        msym_acc(m, a[1], cf.c2 * rho, F);
+        mmat<1, 0, 1>(t, m);
+        msym_acc(m, a[2], cf.c2 * rho, F);
+    }
+    if (VISC && cfg.prandtl != 1.0) {
+        const T Uc[3] = {sc.U, sc.V, sc.W};
+        F[4] += (T(1) / T(cfg.prandtl) - T(1)) * heat_flux(F, Q, Uc);
+    }
     return true;
 }
 
