@@ -106,6 +106,7 @@ def test_reconstruction(oracle, cg, torch, name):
 
 CASES = [
     ("periodic_mixed", None, dict()),
+    ("periodic_mixed", None, dict(viscous=1, mu=0.01)),  # viscous without the Prandtl correction
     ("bump", 1, dict()),
     ("bump", 2, dict(viscous=1, mu=0.01, prandtl=0.72)),
 ]
@@ -126,6 +127,10 @@ def test_residual(oracle, cg, torch, name, wall, par):
     surf = cell_surface(F, M.n_cells)
     fs = flux_scale(W)
     assert_residual_close(R, oR, surf, fs, what="R")
+    # the residual-only kernels (no interface values, no compression factor) give the same R
+    R1, _, _ = S.residual(to_dev(torch, W), to_dev(torch, G), to_dev(torch, alpha), grad=False)
+    S.check()
+    assert_residual_close(R1.cpu().numpy(), oR, surf, fs, what="R (residual only)")
     vol = M.cells()[0]
     # gradients: sum of interface values times n S over |Omega|; bound by |W| S / V
     wscale = np.abs(W).max(axis=1)
