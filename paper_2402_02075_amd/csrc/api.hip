@@ -474,8 +474,34 @@ cgks_status cgks_vcycle(cgks_ctx *c, double *W, double *G, double *alpha, int32_
     double r0 = 0.0, best = 0.0;
     int best_at = 0;
     bool mixed = c->prm.precision == 1;
+    if (tol_drop <= 0.0 && !mixed && max_cycles > 0 && max_cycles <= (1 << 22)) {
+        // No tolerance to test and no precision switch to decide: every cycle runs, so the cycles
+        // are queued back to back, each writing its norm into a device history that is read once
+        // (no host round trip and no copy per cycle).  Results are those of the checked loop
+        // below: a zero residual stops it early, and the cycles queued after it change nothing.
+        c->hist_dev.ensure((size_t)max_cycles);
+        for (int32_t k = 0; k < max_cycles; ++k) {
+            vcycle_once(c, W, G, alpha, false, false, c->hist_dev.p + k);
+            CGKS_HIP(hipGetLastError());
+        }
+        const std::vector<double> h = c->hist_dev.download((size_t)max_cycles, c->stream);
+        check_bad(c);
+        for (int32_t k = 0; k < max_cycles; ++k) {
+            const double r = h[k];
+            if (!std::isfinite(r)) throw Error{CGKS_E_NONFINITE, "non-finite residual in cycle " + std::to_string(k)};
+            if (hist) hist[k] = r;
+            if (n_done) *n_done = k + 1;
+            if (k == 0) {
+                r0 = r;
+                if (r == 0.0) return CGKS_OK;
+            }
+            if (r / r0 <= tol_drop) return CGKS_OK;
+        }
+        c->err = "residual drop not reached in max_cycles";
+        return CGKS_E_NOCONV;
+    }
     for (int32_t k = 0; k < max_cycles; ++k) {
-        vcycle_once(c, W, G, alpha, mixed, mixed);
+        vcycle_once(c, W, G, alpha, mixed, mixed, c->scal.p);
         CGKS_HIP(hipGetLastError());
         CGKS_HIP(hipMemcpyAsync(c->pinned, c->scal.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         CGKS_HIP(hipMemcpyAsync(c->pinned_i, c->bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));

@@ -1395,7 +1395,8 @@ template <class T> static void coarse_visit(cgks_ctx *c, int l)
 }
 
 // One V-cycle on the fine state; the norm of the smoothing residual is left in c->scal[0].
-void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flux, bool fp32_coarse)
+void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flux, bool fp32_coarse,
+                 double *norm_out)
 {
     hipStream_t st = c->stream;
     const int nb = gather_blocks(c->N);
@@ -1405,7 +1406,7 @@ void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flu
         launch_local_dt_recon(c, W, G, alpha, c->dtc.p, c->coef.p);
         launch_face(c, MODE_RES, c->coef.p, c->dtc.p, -1.0, fp32_flux);
         launch_gather_fe(c, W, G, alpha, c->dtc.p, c->Rw.p, s == 0 ? c->partial.p : nullptr);
-        if (s == 0) finish_norm(c, c->partial.p, nb, c->N, c->scal.p);
+        if (s == 0) finish_norm(c, c->partial.p, nb, c->N, norm_out);
     }
     if (c->lev.size() > 1) {
         launch_local_dt_recon(c, W, G, alpha, c->dtc.p, c->coef.p);

@@ -180,6 +180,7 @@ struct cgks_ctx {
     cgks::AdjTape *adj = nullptr;
     // host pinned scalar for per-cycle reads
     double *pinned = nullptr;
+    cgks::DBuf<double> hist_dev;  // per-cycle residual norms of a V-cycle run without a tolerance
     int32_t *pinned_i = nullptr;
 
     ~cgks_ctx();
@@ -225,7 +226,9 @@ void coarse_implicit(cgks_ctx *c, int level, const double *W, const double *rhs,
 void coarse_implicit_fp32(cgks_ctx *c, int level, const double *W, const double *rhs, double *dU);
 void restrict_level(cgks_ctx *c, int level, const double *Wf, const double *Rf, double *Wc, double *Rc);
 void prolong_level(cgks_ctx *c, int level, const double *dWc, double *Wf);
-void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flux, bool fp32_coarse);
+// norm_out: where the first smoothing sweep's residual norm goes (one double on the device)
+void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flux, bool fp32_coarse,
+                 double *norm_out);
 struct GksCfg;
 GksCfg cfg_of(const cgks_ctx *c);
 void coarse_dt_level(cgks_ctx *c, int level, const double *W, double *dt);

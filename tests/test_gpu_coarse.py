@@ -157,6 +157,29 @@ def test_vcycle_matches_oracle(oracle, torch, hier):
     np.testing.assert_allclose(ad.cpu().numpy(), al, rtol=1e-9)
 
 
+def test_vcycle_queued_equals_checked(oracle, torch, hier):
+    """Without a tolerance the cycles are queued with their norms kept on the device: the state
+    and the history must be those of the loop that reads every norm, and the oracle's."""
+    m, M, S, H, sizes = hier
+    x = mg.cell_node_mean(m)
+    W = mg.random_smooth_state(x, seed=21, amp=0.05)
+    G = np.zeros((15, m.n_cells))
+    al = np.ones(m.n_cells)
+    out = {}
+    for tol in (1e-300, 0.0):
+        Wd, Gd, ad = to_dev(torch, W), to_dev(torch, G), to_dev(torch, al)
+        say(f"[gpu] vcycle x4 tol={tol}")
+        hist, conv = S.vcycle(Wd, Gd, ad, 4, tol)
+        assert not conv and len(hist) == 4
+        out[tol] = (hist, Wd.cpu().numpy(), Gd.cpu().numpy(), ad.cpu().numpy())
+    for a, b in zip(out[1e-300], out[0.0]):
+        np.testing.assert_array_equal(a, b)
+    par = oracle.params()
+    Wo, Go, ao = W.copy(), G.copy(), al.copy()
+    ohist = [H.vcycle(par, Wo, Go, ao) for _ in range(4)]
+    np.testing.assert_allclose(out[0.0][0], ohist, rtol=1e-10)
+
+
 def test_vcycle_converges_faster_than_explicit(cg, torch, hier):
     m, M, S, H, sizes = hier
     W, G = mg.uniform_state(m.n_cells)
