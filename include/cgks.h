@@ -282,10 +282,11 @@ cgks_status cgks_prolong(cgks_ctx *ctx, int32_t level, const double *dWc, double
  * params.cycle_gamma visits per coarser level (2: W-cycle), correction; repeated until the residual drops by tol_drop
  * relative to the first cycle or max_cycles.  In place on device W, G, alpha.
  * hist (host, nullable, max_cycles) receives the residual norm of each cycle;
- * *n_done the cycles run.  Reads one scalar per cycle (synchronises each cycle), except with
- * tol_drop <= 0, precision 0 and max_cycles <= 2^22: then every cycle runs, the cycles are queued
- * back to back with their norms kept on the device and read once at the end, and a non-physical
- * state (CGKS_E_PHYS) or a non-finite norm is reported after the last cycle.
+ * *n_done the cycles run.  Cycles are queued in batches (16; all cycles, up to 2^22, when
+ * tol_drop <= 0 in FP64) with their norms kept on the device and read once per batch; the state at
+ * a batch's start is kept (21 N doubles of device memory), so that a stop, a precision switch or a
+ * non-physical state before the batch's end is reproduced by re-running from it: the results are
+ * those of a loop that checks after every cycle (the kernels are deterministic).
  * Returns CGKS_E_NOCONV if the drop was not reached (state and history valid).
  */
 cgks_status cgks_vcycle(cgks_ctx *ctx, double *W, double *G, double *alpha, int32_t max_cycles, double tol_drop,

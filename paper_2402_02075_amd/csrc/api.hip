@@ -474,53 +474,107 @@ cgks_status cgks_vcycle(cgks_ctx *c, double *W, double *G, double *alpha, int32_
     double r0 = 0.0, best = 0.0;
     int best_at = 0;
     bool mixed = c->prm.precision == 1;
-    if (tol_drop <= 0.0 && !mixed && max_cycles > 0 && max_cycles <= (1 << 22)) {
-        // No tolerance to test and no precision switch to decide: every cycle runs, so the cycles
-        // are queued back to back, each writing its norm into a device history that is read once
-        // (no host round trip and no copy per cycle).  Results are those of the checked loop
-        // below: a zero residual stops it early, and the cycles queued after it change nothing.
-        c->hist_dev.ensure((size_t)max_cycles);
-        for (int32_t k = 0; k < max_cycles; ++k) {
-            vcycle_once(c, W, G, alpha, false, false, c->hist_dev.p + k);
-            CGKS_HIP(hipGetLastError());
-        }
-        const std::vector<double> h = c->hist_dev.download((size_t)max_cycles, c->stream);
-        check_bad(c);
-        for (int32_t k = 0; k < max_cycles; ++k) {
-            const double r = h[k];
-            if (!std::isfinite(r)) throw Error{CGKS_E_NONFINITE, "non-finite residual in cycle " + std::to_string(k)};
-            if (hist) hist[k] = r;
-            if (n_done) *n_done = k + 1;
-            if (k == 0) {
-                r0 = r;
-                if (r == 0.0) return CGKS_OK;
-            }
-            if (r / r0 <= tol_drop) return CGKS_OK;
-        }
-        c->err = "residual drop not reached in max_cycles";
-        return CGKS_E_NOCONV;
-    }
-    for (int32_t k = 0; k < max_cycles; ++k) {
-        vcycle_once(c, W, G, alpha, mixed, mixed, c->scal.p);
-        CGKS_HIP(hipGetLastError());
-        CGKS_HIP(hipMemcpyAsync(c->pinned, c->scal.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        CGKS_HIP(hipMemcpyAsync(c->pinned_i, c->bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-        CGKS_HIP(hipStreamSynchronize(c->stream));
-        const double r = c->pinned[0];
-        if (*c->pinned_i != INT32_MAX) check_bad(c);
+    const int64_t N = c->N;
+    // The loop's decisions after each cycle: record the norm, then stop (converged), switch the
+    // mixed cycle to FP64, or go on.  Returns 1 to stop, 2 for a precision switch, 0 otherwise.
+    auto decide = [&](int32_t k, double r) -> int {
         if (!std::isfinite(r)) throw Error{CGKS_E_NONFINITE, "non-finite residual in cycle " + std::to_string(k)};
         if (hist) hist[k] = r;
         if (n_done) *n_done = k + 1;
         if (k == 0) {
             r0 = r;
             best = r;
-            if (r == 0.0) return CGKS_OK;
+            if (r == 0.0) return 1;
         }
         if (r < best) best = r, best_at = k;
         const double drop = r / r0;
-        if (drop <= tol_drop) return CGKS_OK;
-        if (mixed && (drop <= c->prm.mixed_switch || k - best_at >= 20)) mixed = false;
+        if (drop <= tol_drop) return 1;
+        if (mixed && (drop <= c->prm.mixed_switch || k - best_at >= 20)) return 2;
+        return 0;
+    };
+    // Cycles run in batches queued without a host wait, each cycle writing its norm into a
+    // device history read once per batch.  The state at the start of a batch is kept; when the
+    // history shows that the loop stops or switches precision before the batch's last cycle, the
+    // state is restored and the batch re-run up to that cycle, and a non-physical state found at
+    // the end of a batch is located by re-running the batch one cycle at a time.  The kernels are
+    // deterministic, so results are those of a loop that reads every norm.  Without a tolerance
+    // in FP64 one batch holds every cycle.
+    const int32_t B = (tol_drop <= 0.0 && !mixed) ? std::min<int32_t>(max_cycles, 1 << 22) : 16;
+    if (max_cycles > 0) c->hist_dev.ensure((size_t)B);
+    auto save = [&](bool back) {
+        const size_t n5 = 5 * N * sizeof(double), n15 = 15 * N * sizeof(double), n1 = N * sizeof(double);
+        if (!back) {
+            c->snapW.ensure(5 * N);
+            c->snapG.ensure(15 * N);
+            c->snapA.ensure(N);
+        }
+        CGKS_HIP(hipMemcpyAsync(back ? W : c->snapW.p, back ? c->snapW.p : W, n5, hipMemcpyDeviceToDevice, c->stream));
+        CGKS_HIP(hipMemcpyAsync(back ? G : c->snapG.p, back ? c->snapG.p : G, n15, hipMemcpyDeviceToDevice, c->stream));
+        CGKS_HIP(hipMemcpyAsync(back ? alpha : c->snapA.p, back ? c->snapA.p : alpha, n1, hipMemcpyDeviceToDevice,
+                                c->stream));
+    };
+    int32_t k = 0;
+    while (k < max_cycles) {
+        const int32_t nb = std::min(B, max_cycles - k);
+        const bool keep = nb > 1;
+        if (keep) save(false);
+        const bool mb = mixed;
+        for (int32_t j = 0; j < nb; ++j) {
+            vcycle_once(c, W, G, alpha, mb, mb, c->hist_dev.p + j);
+            CGKS_HIP(hipGetLastError());
+        }
+        CGKS_HIP(hipMemcpyAsync(c->pinned_i, c->bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        const std::vector<double> h = c->hist_dev.download((size_t)nb, c->stream);
+        if (*c->pinned_i != INT32_MAX) {
+            if (!keep) check_bad(c);
+            // re-run the batch from its start as the checked loop: a check after every cycle
+            save(true);
+            const int32_t clear = INT32_MAX;
+            CGKS_HIP(hipMemcpyAsync(c->bad.p, &clear, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+            for (int32_t j = 0; j < nb; ++j) {
+                vcycle_once(c, W, G, alpha, mixed, mixed, c->hist_dev.p + j);
+                CGKS_HIP(hipGetLastError());
+                check_bad(c);
+                CGKS_HIP(hipMemcpyAsync(c->pinned, c->hist_dev.p + j, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+                CGKS_HIP(hipStreamSynchronize(c->stream));
+                const int what = decide(k + j, c->pinned[0]);
+                if (what == 1) return CGKS_OK;
+                if (what == 2) mixed = false;
+            }
+            k += nb;
+            continue;
+        }
+        int32_t stop = -1, what = 0;
+        for (int32_t j = 0; j < nb && stop < 0; ++j) {
+            const double r = h[j];
+            if (!std::isfinite(r) && j + 1 < nb) {
+                // the state the checked loop would leave: after cycle k + j
+                save(true);
+                for (int32_t q = 0; q <= j; ++q) vcycle_once(c, W, G, alpha, mb, mb, c->hist_dev.p + q);
+                CGKS_HIP(hipStreamSynchronize(c->stream));
+            }
+            what = decide(k + j, r);
+            if (what) stop = j;
+        }
+        if (stop < 0) {
+            k += nb;
+            continue;
+        }
+        if (stop + 1 < nb) {
+            save(true);
+            for (int32_t q = 0; q <= stop; ++q) {
+                vcycle_once(c, W, G, alpha, mb, mb, c->hist_dev.p + q);
+                CGKS_HIP(hipGetLastError());
+            }
+        }
+        if (what == 1) {
+            CGKS_HIP(hipStreamSynchronize(c->stream));
+            return CGKS_OK;
+        }
+        mixed = false;
+        k += stop + 1;
     }
+    CGKS_HIP(hipStreamSynchronize(c->stream));
     c->err = "residual drop not reached in max_cycles";
     return CGKS_E_NOCONV;
     API_END(c)

@@ -180,7 +180,8 @@ struct cgks_ctx {
     cgks::AdjTape *adj = nullptr;
     // host pinned scalar for per-cycle reads
     double *pinned = nullptr;
-    cgks::DBuf<double> hist_dev;  // per-cycle residual norms of a V-cycle run without a tolerance
+    cgks::DBuf<double> hist_dev;                // per-cycle residual norms of a batch of V-cycles
+    cgks::DBuf<double> snapW, snapG, snapA;     // state at the start of the batch
     int32_t *pinned_i = nullptr;
 
     ~cgks_ctx();

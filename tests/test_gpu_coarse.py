@@ -180,6 +180,35 @@ def test_vcycle_queued_equals_checked(oracle, torch, hier):
     np.testing.assert_allclose(out[0.0][0], ohist, rtol=1e-10)
 
 
+def test_vcycle_stop_inside_a_batch(torch, hier):
+    """A tolerance reached in the middle of a batch of queued cycles: the call must stop after
+    exactly that cycle, with the state of a run of that many cycles."""
+    m, M, S, H, sizes = hier
+    x = mg.cell_node_mean(m)
+    W = mg.random_smooth_state(x, seed=22, amp=0.05)
+    G = np.zeros((15, m.n_cells))
+    al = np.ones(m.n_cells)
+
+    def run(n, tol):
+        Wd, Gd, ad = to_dev(torch, W), to_dev(torch, G), to_dev(torch, al)
+        hist, conv = S.vcycle(Wd, Gd, ad, n, tol)
+        return hist, conv, Wd.cpu().numpy(), Gd.cpu().numpy(), ad.cpu().numpy()
+
+    full = run(40, 0.0)[0]
+    drop = full / full[0]
+    tol = drop[21]
+    k_stop = int(np.nonzero(drop <= tol)[0][0])
+    say(f"[gpu] stop inside a batch at cycle {k_stop}")
+    assert k_stop > 0 and k_stop % 16 != 15  # not the last cycle of a batch of 16
+    hist, conv, Ws, Gs, As = run(40, tol)
+    assert conv and len(hist) == k_stop + 1
+    np.testing.assert_array_equal(hist, full[:k_stop + 1])
+    _, _, Wr, Gr, Ar = run(k_stop + 1, 0.0)
+    np.testing.assert_array_equal(Ws, Wr)
+    np.testing.assert_array_equal(Gs, Gr)
+    np.testing.assert_array_equal(As, Ar)
+
+
 def test_vcycle_converges_faster_than_explicit(cg, torch, hier):
     m, M, S, H, sizes = hier
     W, G = mg.uniform_state(m.n_cells)

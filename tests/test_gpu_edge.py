@@ -97,6 +97,14 @@ def test_nonphysical_state_is_reported_then_cleared(cg, torch):
     R = S.residual(to_dev(torch, W), to_dev(torch, G))[0]
     S.check()
     assert np.isfinite(R.cpu().numpy()).all()
+    # inside a batch of queued V-cycles the state is reported as well, and the flag cleared
+    S.agglomerate()
+    al = np.ones(m.n_cells)
+    with pytest.raises(cg.CgksError) as e:
+        S.vcycle(to_dev(torch, Wbad), to_dev(torch, G), to_dev(torch, al), 10, 1e-10)
+    assert e.value.code == cg.E_PHYS
+    hist, _ = S.vcycle(to_dev(torch, W), to_dev(torch, G), to_dev(torch, al), 3, 0.0)
+    assert len(hist) == 3 and np.isfinite(hist).all()
 
 
 def test_ragged_group_tail_matches_oracle(oracle, cg, torch):
