@@ -560,6 +560,14 @@ void build_hierarchy(cgks_ctx *c)
         L->pb.upload(allB, st);
         L->S.upload(allS, st);
         {
+            std::vector<double> as(4 * mall + 4);
+            for (int64_t j = 0; j < mall; ++j) {
+                for (int d = 0; d < 3; ++d) as[4 * j + d] = allAv[3 * j + d];
+                as[4 * j + 3] = allS[j];
+            }
+            L->AS.upload(as, st);
+        }
+        {
             DBuf<double> tmp;
             tmp.upload(allAv, st);
             L->A.alloc(3 * mall + 3);
@@ -622,7 +630,7 @@ template <class T> struct CoarseArgs {
     const int32_t *pa, *pb, *bown, *btag;
     const double *A, *bA;
     const BcTable *bc;
-    T *fflux;  // [5][m + nb], S n . F
+    T *fflux;  // [m + nb][5] (face-major: one face's five values together), S n . F
 };
 
 // S n . F of coarse face j (pairs j < m, then boundary faces) at the state W, or at W + D when D
@@ -684,7 +692,7 @@ template <class T> __global__ __launch_bounds__(256) void k_kfvs_face(CoarseArgs
     T ff[5];
     kfvs_face_flux(A, j, D, ff);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) A.fflux[q * tot + j] = ff[q];
+    for (int q = 0; q < 5; ++q) A.fflux[5 * j + q] = ff[q];
 }
 
 // Row kernels of a coarse level's first sweep and of its restriction input: the face-flux
@@ -696,7 +704,7 @@ template <class T> __global__ __launch_bounds__(256) void k_kfvs_face(CoarseArgs
 template <class T, bool FIRST>
 __global__ __launch_bounds__(256) void k_kfvs_rows(CoarseArgs<T> A, const T *__restrict__ ff,
                                                    const int32_t *__restrict__ ptr, const int32_t *__restrict__ item,
-                                                   const double *__restrict__ Ssum, const double *__restrict__ V,
+                                                   const double *__restrict__ AS, const double *__restrict__ V,
                                                    double cfl, double mu, int viscous, const T *__restrict__ Rs,
                                                    const T *__restrict__ D, T *__restrict__ F, T *__restrict__ Dout,
                                                    T *__restrict__ Wout, T *__restrict__ Rout)
@@ -704,7 +712,7 @@ __global__ __launch_bounds__(256) void k_kfvs_rows(CoarseArgs<T> A, const T *__r
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = t / RG;
     const int g = (int)(t % RG);
-    const int64_t n = A.n, tot = A.m + A.nb;
+    const int64_t n = A.n;
     if (i >= n) return;  // whole row groups leave together
     double u = 0, v = 0, w = 0, cs = 0, rho = 1, Vi = 0;
     if (FIRST) {
@@ -725,20 +733,20 @@ __global__ __launch_bounds__(256) void k_kfvs_rows(CoarseArgs<T> A, const T *__r
             const int j = it >> 1;
             const T s = (it & 1) ? T(1) : T(-1);
 #pragma unroll
-            for (int q = 0; q < 5; ++q) r[q] += s * ff[q * tot + j];
+            for (int q = 0; q < 5; ++q) r[q] += s * ff[5 * j + q];
         } else {
             const int64_t j = A.m + (-it - 1);
 #pragma unroll
-            for (int q = 0; q < 5; ++q) r[q] -= ff[q * tot + j];
+            for (int q = 0; q < 5; ++q) r[q] -= ff[5 * j + q];
         }
         if (FIRST) {
             double ax, ay, az, sa;
             if (it >= 0) {
                 const int j = it >> 1;
-                ax = A.A[j];
-                ay = A.A[A.m + j];
-                az = A.A[2 * A.m + j];
-                sa = Ssum[j];
+                ax = AS[4 * j];
+                ay = AS[4 * j + 1];
+                az = AS[4 * j + 2];
+                sa = AS[4 * j + 3];
             } else {
                 const int q = -it - 1;
                 ax = A.bA[q];
@@ -774,7 +782,7 @@ __global__ __launch_bounds__(256) void k_kfvs_rows(CoarseArgs<T> A, const T *__r
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_kfvs_gather(int64_t n, int64_t tot, int64_t m, const int32_t *__restrict__ ptr,
+__global__ __launch_bounds__(256) void k_kfvs_gather(int64_t n, int64_t m, const int32_t *__restrict__ ptr,
                                                      const int32_t *__restrict__ item, const T *__restrict__ ff,
                                                      const T *__restrict__ add, T *__restrict__ R)
 {
@@ -789,11 +797,11 @@ __global__ __launch_bounds__(256) void k_kfvs_gather(int64_t n, int64_t tot, int
             const int j = it >> 1;
             const T s = (it & 1) ? T(1) : T(-1);
 #pragma unroll
-            for (int q = 0; q < 5; ++q) r[q] += s * ff[q * tot + j];
+            for (int q = 0; q < 5; ++q) r[q] += s * ff[5 * j + q];
         } else {
             const int64_t j = m + (-it - 1);
 #pragma unroll
-            for (int q = 0; q < 5; ++q) r[q] -= ff[q * tot + j];
+            for (int q = 0; q < 5; ++q) r[q] -= ff[5 * j + q];
         }
     }
 #pragma unroll
@@ -966,7 +974,7 @@ template <class T> static void kfvs_impl(cgks_ctx *c, int level, const T *W, T *
     A.fflux = ff;
     const int64_t tot = L->m + L->nb;
     hipLaunchKernelGGL((k_kfvs_face<T>), G1(tot), dim3(256), 0, c->stream, A, (const T *)nullptr);
-    hipLaunchKernelGGL((k_kfvs_gather<T>), GR(L->n), dim3(256), 0, c->stream, L->n, tot, L->m, L->cf_ptr.p,
+    hipLaunchKernelGGL((k_kfvs_gather<T>), GR(L->n), dim3(256), 0, c->stream, L->n, L->m, L->cf_ptr.p,
                        L->cf_item.p, ff, add, R);
 }
 
@@ -1354,7 +1362,7 @@ template <class T> static void fas_level(cgks_ctx *c, int l, int pre_done)
         const CoarseArgs<T> ca = coarse_args<T>(c, l, b.W0, b.ff);
         hipLaunchKernelGGL((k_kfvs_face<T>), G1(L->m + L->nb), dim3(256), 0, st, ca, (const T *)b.D);
         hipLaunchKernelGGL((k_kfvs_rows<T, false>), GR(L->n), dim3(256), 0, st, ca, (const T *)b.ff, L->cf_ptr.p,
-                           L->cf_item.p, L->S.p, L->V.p, 0.0, 0.0, 0, (const T *)nullptr, (const T *)b.D, b.F,
+                           L->cf_item.p, L->AS.p, L->V.p, 0.0, 0.0, 0, (const T *)nullptr, (const T *)b.D, b.F,
                            (T *)nullptr, b.W, b.R);
         hipLaunchKernelGGL((k_restrict<T, T>), GR(C->n), dim3(256), 0, st, C->n, C->nfine, C->c2f_ptr.p, C->c2f_idx.p,
                            L->V.p, C->V.p, b.W, b.R, cb.W0, cb.Rs);
@@ -1382,7 +1390,7 @@ template <class T> static void coarse_visit(cgks_ctx *c, int l)
         const CoarseArgs<T> ca = coarse_args<T>(c, l, b.W0, b.ff);
         hipLaunchKernelGGL((k_kfvs_face<T>), G1(L->m + L->nb), dim3(256), 0, st, ca, (const T *)nullptr);
         hipLaunchKernelGGL((k_kfvs_rows<T, true>), GR(n), dim3(256), 0, st, ca, (const T *)b.ff, L->cf_ptr.p,
-                           L->cf_item.p, L->S.p, L->V.p, c->prm.cfl, c->prm.mu, c->prm.viscous, (const T *)b.Rs,
+                           L->cf_item.p, L->AS.p, L->V.p, c->prm.cfl, c->prm.mu, c->prm.viscous, (const T *)b.Rs,
                            (const T *)nullptr, b.F, b.D, (T *)nullptr, (T *)nullptr);
     } else {
         kfvs_impl<T>(c, l, b.W0, b.R, b.ff);

@@ -80,6 +80,7 @@ struct Level {
     DBuf<int32_t> pa, pb;            // [m] coarse interior pairs
     DBuf<double> S;                  // [m] summed fine areas
     DBuf<double> A;                  // [3][m] summed area vectors (SoA)
+    DBuf<double> AS;                 // [m][4] area vector and summed area, interleaved (row kernels)
     DBuf<int32_t> bown, btag;        // [nb] coarse owner, tag of the fine boundary faces
     DBuf<double> bA;                 // [3][nb]
     DBuf<int32_t> cf_ptr, cf_item;   // CSR cell -> (pair j: 2j + side) / (boundary k: -(k+1))
