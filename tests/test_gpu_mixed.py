@@ -110,3 +110,36 @@ def test_mixed_vcycle_reaches_fp64_fixed_point(torch, ad):
     d = np.abs(out[1][0] - out[0][0]).max(axis=1) / np.abs(out[0][0]).max(axis=1)
     say("    mixed vs FP64 converged state, max rel difference per component: " + " ".join(f"{x:.2e}" for x in d))
     assert d.max() < 1e-9
+
+
+def test_mixed_switch_inside_a_batch(torch, ad):
+    """The switch from the FP32 to the FP64 flux decided at a cycle inside a batch of queued
+    cycles: the run must equal one that stops the mixed cycle after that cycle and continues in
+    FP64 (same states bit for bit, same norms)."""
+    m = mg.bump_channel(24, 8, 4, n_prism=0, n_pyr=0)
+    W0, G0 = mg.uniform_state(m.n_cells)
+    al0 = np.ones(m.n_cells)
+
+    def dev():
+        return (torch.from_numpy(W0.copy()).cuda(), torch.from_numpy(G0.copy()).cuda(),
+                torch.from_numpy(al0.copy()).cuda())
+
+    n = 40
+    S = ad.channel_solver(m, 0.5, precision=1, mixed_switch=0.0)
+    h, _ = S.vcycle(*dev(), n, 1e-300)
+    drop = h / h[0]
+    x = drop[9]
+    s = int(np.nonzero(drop <= x)[0][0])
+    say(f"[gpu] mixed switch inside a batch at cycle {s}")
+    assert 0 < s < 15
+    SA = ad.channel_solver(m, 0.5, precision=1, mixed_switch=x)
+    WA, GA, aA = dev()
+    hA, _ = SA.vcycle(WA, GA, aA, n, 1e-300)
+    SB = ad.channel_solver(m, 0.5, precision=1, mixed_switch=0.0)
+    WB, GB, aB = dev()
+    hB1, _ = SB.vcycle(WB, GB, aB, s + 1, 1e-300)
+    SB.set_params(precision=0)
+    hB2, _ = SB.vcycle(WB, GB, aB, n - s - 1, 1e-300)
+    np.testing.assert_array_equal(hA, np.concatenate([hB1, hB2]))
+    for a, b in ((WA, WB), (GA, GB), (aA, aB)):
+        np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
