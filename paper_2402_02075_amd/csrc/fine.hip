@@ -5,8 +5,10 @@
 // (Eq. 2nd-flux), Sec. 2.4 (Eq. gauss-formula), Sec. 3 (HWENO, compression
 // factor, WENO weights), Sec. 4.2 (Eq. smo), local time stepping (Secs. 1, 4.3).
 //
-// Data layout (HBM): every per-cell and per-face array is structure-of-arrays,
-// component-major, so consecutive lanes touch consecutive addresses.  Faces are
+// Data layout (HBM): per-cell states and geometry are structure-of-arrays,
+// component-major, so consecutive lanes touch consecutive addresses; the
+// polynomial coefficients are cell-major (50 per cell, read by the Gauss-point
+// lanes) and the face records face-major (read by both cells' gathers).  Faces are
 // ordered by (left cell, right cell), cells keep the caller's order, and each
 // cell gathers its faces through a CSR list in a fixed order: sums are
 // deterministic without atomics.
@@ -463,7 +465,7 @@ template <class T, int MODE, bool VAL, int FOLD = 0> __global__ __launch_bounds_
 }
 
 // The inviscid residual-only flux held to 256 registers for two waves per SIMD (160 B of spills
-// per lane; 3 % faster than one wave per SIMD in FP64).
+// per lane; 4 % faster than one wave per SIMD in FP64).
 template <class T> __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_face_res2(FaceArgs A)
 {
     face_kernel<T, MODE_RESONLY, false, 1>(A);

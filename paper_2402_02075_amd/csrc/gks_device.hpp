@@ -10,7 +10,10 @@
 // Moments are tabulated per side as one-dimensional recursions and combined by
 // compile-time-indexed helpers, so every table entry stays in registers.
 // Micro-slopes use the closed-form inverse of the 5x5 moment matrix, derived in
-// peculiar velocity c = u - U where the matrix is nearly diagonal.
+// peculiar velocity c = u - U where the matrix is nearly diagonal.  Full-space
+// moments that equal Euler fluxes or their Jacobians applied to a vector are
+// formed in that closed form, and in the steady modes the time coefficients are
+// applied while the moments accumulate.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
