@@ -250,6 +250,46 @@ template <class T> CGKS_HD void euler_divergence(const EulerLin<T> &e, const T g
     for (int j = 0; j < 3; ++j) euler_jvp_acc(e, j, g[j], r);
 }
 
+// The interface Maxwellian's second-order transport term sum_j rho <u u_j psi psi^T> a_j, by the
+// same argument: it is sum_j dQ_j/dW dW_j with Q_j(W) = rho <u u_j psi> (x = u the normal),
+//   Q_j = (rho U_x U_j + p d_xj,  rho U_x U_j U_i + p (U_x d_ij + U_j d_xi + U_i d_xj),
+//          rho U_x U_j (|U|^2 + (K + 7) th) / 2 + p d_xj (|U|^2 + (K + 5) th) / 2),  th = p / rho,
+// the Maxwellian's third and fourth velocity moments.  Formed in closed form, this leaves the
+// interface Maxwellian without slopes, tables or moment matrices.
+template <class T>
+CGKS_HD void second_transport(const EulerLin<T> &e, const Side<T> &s, T K, const T g[3][5], T out[5])
+{
+    const T *U = e.U;
+    const T th = s.p * s.ir;
+    const T A = T(2) * e.q2h + (K + T(7)) * th;   // |U|^2 + (K + 7) th
+    const T Bc = T(2) * e.q2h + (K + T(5)) * th;  // |U|^2 + (K + 5) th
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[c] = T(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const T *d = g[j];
+        T rdu[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) rdu[i] = d[1 + i] - U[i] * d[0];  // rho dU_i
+        const T dp = e.gm1 * (d[4] - (U[0] * d[1] + U[1] * d[2] + U[2] * d[3]) + e.q2h * d[0]);
+        const T udu = U[0] * rdu[0] + U[1] * rdu[1] + U[2] * rdu[2];  // rho U.dU
+        const T dth = dp - th * d[0];                                  // rho d(th)
+        const T dmu = d[1] * U[j] + U[0] * rdu[j];                     // d(rho U_x U_j)
+        out[0] += dmu + (j == 0 ? dp : T(0));
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            T v = d[1] * U[j] * U[i] + U[0] * (rdu[j] * U[i] + U[j] * rdu[i]);
+            if (i == j) v += dp * U[0] + th * rdu[0];
+            if (i == 0) v += dp * U[j] + th * rdu[j];
+            if (j == 0) v += dp * U[i] + th * rdu[i];
+            out[1 + i] += v;
+        }
+        T v4 = T(0.5) * dmu * A + U[0] * U[j] * (udu + T(0.5) * (K + T(7)) * dth);
+        if (j == 0) v4 += T(0.5) * dp * Bc + th * (udu + T(0.5) * (K + T(5)) * dth);
+        out[4] += v4;
+    }
+}
+
 // Space slopes a_j from local-frame gradients g[j][c].
 template <class T> CGKS_HD void space_slopes(const Side<T> &s, const SlopeK<T> &k, const T g[3][5], T a[3][5])
 {
@@ -277,13 +317,13 @@ CGKS_HD void slopes(const Side<T> &s, T K, T iK3, const T g[3][5], T a[3][5], T 
     slope_solve(s, k, b, A);
 }
 
-// Interface Maxwellian (local frame): space slopes a_j, rho tr = sum_j A_j dW_j (= -rho <A psi>),
-// its Euler flux F_x(W) = rho <u psi> and A_x (rho tr) = -rho <u psi psi^T> A.
+// Interface Maxwellian (local frame), all in closed form: rho tr = sum_j A_j dW_j (= -rho <A psi>),
+// its Euler flux F_x(W) = rho <u psi>, A_x (rho tr) = -rho <u psi psi^T> A, and
+// sum_j rho <u u_j psi psi^T> a_j.
 template <class T>
-CGKS_HD void center_terms(const Side<T> &s, const T W[5], T K, T iK3, const T g[3][5], T a[3][5], T rtr[5],
-                          T fx[5], T jt[5])
+CGKS_HD void center_terms(const Side<T> &s, const T W[5], T K, T iK3, const T g[3][5], T rtr[5], T fx[5], T jt[5],
+                          T q2[5])
 {
-    space_slopes(s, slope_k(s, K, iK3), g, a);
     const EulerLin<T> e = euler_lin(s, K, iK3);
     euler_divergence(e, g, rtr);
     fx[0] = W[1];
@@ -294,6 +334,7 @@ CGKS_HD void center_terms(const Side<T> &s, const T W[5], T K, T iK3, const T g[
 #pragma unroll
     for (int c = 0; c < 5; ++c) jt[c] = T(0);
     euler_jvp_acc(e, 0, rtr, jt);
+    second_transport(e, s, K, g, q2);
 }
 
 struct GksCfg {
@@ -368,31 +409,17 @@ CGKS_HD bool gks_moments(const T wl[5], const T gl[3][5], const T wr[5], const T
     const Side<T> sc = side_of(Wc, gam);
     if (!(sc.rho > T(0) && sc.lam > T(0))) return false;
     {
-        T a[3][5];
-        {
-            T rtr[5], fx[5], jt[5];
-            center_terms(sc, Wc, K, iK3, dWc, a, rtr, fx, jt);
+        T rtr[5], fx[5], jt[5], q2[5];
+        center_terms(sc, Wc, K, iK3, dWc, rtr, fx, jt, q2);
 #pragma unroll
-            for (int c = 0; c < 5; ++c) {
-                o.Vc[0][c] = Wc[c];
-                o.Vc[1][c] = rtr[c];   // rho_c <(a_c.u) psi>
-                o.Vc[2][c] = -rtr[c];  // compatibility: <A_c psi> = -<(a_c.u) psi>
-                o.Mc[0][c] = fx[c];    // rho_c <u psi>
-                o.Mc[2][c] = -jt[c];   // rho_c <u A_c psi>
-                o.Mc[1][c] = T(0);
-            }
+        for (int c = 0; c < 5; ++c) {
+            o.Vc[0][c] = Wc[c];
+            o.Vc[1][c] = rtr[c];   // rho_c <(a_c.u) psi>
+            o.Vc[2][c] = -rtr[c];  // compatibility: <A_c psi> = -<(a_c.u) psi>
+            o.Mc[0][c] = fx[c];    // rho_c <u psi>
+            o.Mc[1][c] = q2[c];    // rho_c <u (a_c.u) psi>
+            o.Mc[2][c] = -jt[c];   // rho_c <u A_c psi>
         }
-        const T rho = sc.rho;
-        Tab<T> t;
-        tab_vw(t, sc, K);
-        tab_u_full(t, sc);
-        T m[15];
-        mmat<2, 0, 0>(t, m);
-        msym_acc(m, a[0], rho, o.Mc[1]);
-        mmat<1, 1, 0>(t, m);
-        msym_acc(m, a[1], rho, o.Mc[1]);
-        mmat<1, 0, 1>(t, m);
-        msym_acc(m, a[2], rho, o.Mc[1]);
     }
     o.Uc[0] = sc.U;
     o.Uc[1] = sc.V;
@@ -585,11 +612,12 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
     }
     const Side<T> sc = side_of(Wc, gam);
     if (!(sc.rho > T(0) && sc.lam > T(0))) return false;
-    T a[3][5];
     T Q[5];  // viscous: time-integrated conserved variables for the Prandtl correction
     {
-        T rtr[5], fx[5], jt[5];
-        center_terms(sc, Wc, K, iK3, dWc, a, rtr, fx, jt);
+        // interface Maxwellian in closed form (see center_terms), each term entering as formed
+        const EulerLin<T> e = euler_lin(sc, K, iK3);
+        T rtr[5];
+        euler_divergence(e, dWc, rtr);
         // rho_c <psi {1, a_c.u, A_c}> = {W_c, rho tr, -rho tr}
         if (VISC) {
 #pragma unroll
@@ -604,22 +632,19 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
 #pragma unroll
             for (int c = 0; c < 5; ++c) Wt[c] += cw.c1 * Wc[c] + (cw.c2 - cw.c3) * rtr[c];
         }
-        // rho_c <u psi {1, A_c}> = {F_x(W_c), -A_x rho tr}
+        // rho_c <u psi {1, a_c.u, A_c}> = {F_x(W_c), sum_j dQ_j dW_j, -A_x rho tr}
+        F[0] += cf.c1 * Wc[1];
+        F[1] += cf.c1 * (Wc[1] * sc.U + sc.p);
+        F[2] += cf.c1 * (Wc[1] * sc.V);
+        F[3] += cf.c1 * (Wc[1] * sc.W);
+        F[4] += cf.c1 * (e.Ep * sc.U);
+        T t5[5] = {T(0), T(0), T(0), T(0), T(0)};
+        euler_jvp_acc(e, 0, rtr, t5);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) F[c] += cf.c1 * fx[c] - cf.c3 * jt[c];
-    }
-    {
-        const T rho = sc.rho;
-        Tab<T> t;
-        tab_vw(t, sc, K);
-        tab_u_full(t, sc);
-        T m[15];
-        mmat<2, 0, 0>(t, m);
-        msym_acc(m, a[0], cf.c2 * rho, F);
-        mmat<1, 1, 0>(t, m);
-        msym_acc(m, a[1], cf.c2 * rho, F);
-        mmat<1, 0, 1>(t, m);
-        msym_acc(m, a[2], cf.c2 * rho, F);
+        for (int c = 0; c < 5; ++c) F[c] -= cf.c3 * t5[c];
+        second_transport(e, sc, K, dWc, t5);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) F[c] += cf.c2 * t5[c];
     }
     if (VISC && cfg.prandtl != 1.0) {
         const T Uc[3] = {sc.U, sc.V, sc.W};
