@@ -464,6 +464,13 @@ template <class T, int MODE, bool VAL, int FOLD = 0> __global__ __launch_bounds_
     face_kernel<T, MODE, VAL, FOLD>(A);
 }
 
+// The inviscid residual-only flux held to 256 registers for two waves per SIMD (its natural
+// allocation is a little above 256; the few spills cost less than the second wave gains).
+template <class T> __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_face_res2(FaceArgs A)
+{
+    face_kernel<T, MODE_RESONLY, false, 1>(A);
+}
+
 // ---------------------------------------------------------------- gathers
 struct GatherArgs {
     int64_t N, F;
@@ -812,7 +819,7 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
             else hipLaunchKernelGGL((k_face<double, MODE_RES, true, 2>), grid, blk, 0, c->stream, A);
             break;
         case MODE_RESONLY:
-            if (inv) hipLaunchKernelGGL((k_face<double, MODE_RESONLY, false, 1>), grid, blk, 0, c->stream, A);
+            if (inv) hipLaunchKernelGGL((k_face_res2<double>), grid, blk, 0, c->stream, A);
             else hipLaunchKernelGGL((k_face<double, MODE_RESONLY, false, 2>), grid, blk, 0, c->stream, A);
             break;
         case MODE_S1: hipLaunchKernelGGL((k_face<double, MODE_S1, true>), grid, blk, 0, c->stream, A); break;

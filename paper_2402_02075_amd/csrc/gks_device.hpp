@@ -583,8 +583,34 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
         T m[15];
         mmat<0, 0, 0>(t, m);  // <psi psi>_half
         if (!VISC) mcol0_acc(m, rho, Wc);
+        msym_acc(m, a[0], rho, dWc[0]);
+        // tangential transport <v psi psi^T>_half a_1 + <w psi psi^T>_half a_2: the half space
+        // restricts u only, so the v and w integrals are Gaussian with means V, W and variance
+        // th = p/rho, and <v f> = V <f> + th <df/dv> (Stein's identity) reduces each term to the
+        // <psi psi^T>_half products and columns already at hand
+        T tv[5];
+        if (VISC || VAL) {
+            T y1[5] = {T(0), T(0), T(0), T(0), T(0)}, y2[5] = {T(0), T(0), T(0), T(0), T(0)};
+            msym_acc(m, a[1], T(1), y1);
+            msym_acc(m, a[2], T(1), y2);
+            const T th = s.h;
+            const T c0[5] = {m[0], m[1], m[2], m[3], m[4]};     // <psi>
+            const T c2[5] = {m[2], m[6], m[9], m[10], m[11]};   // <v psi>
+            const T c3[5] = {m[3], m[7], m[10], m[12], m[13]};  // <w psi>
 #pragma unroll
-        for (int j = 0; j < 3; ++j) msym_acc(m, a[j], rho, dWc[j]);
+            for (int c = 0; c < 5; ++c) {
+                dWc[1][c] += rho * y1[c];
+                dWc[2][c] += rho * y2[c];
+                tv[c] = s.V * y1[c] + s.W * y2[c] +
+                        th * ((a[1][2] + a[2][3]) * c0[c] + a[1][4] * c2[c] + a[2][4] * c3[c]);
+            }
+            tv[2] += th * y1[0];
+            tv[3] += th * y2[0];
+            tv[4] += th * (y1[2] + y2[3]);
+        } else {
+            msym_acc(m, a[1], rho, dWc[1]);
+            msym_acc(m, a[2], rho, dWc[2]);
+        }
         if (VISC) {
             msym_acc(m, A, rho, Vk[2]);
         } else if (VAL) {
@@ -598,17 +624,32 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
             const T sv = VISC ? rho : -cw.k1 * rho;
             T *dst = VISC ? Vk[1] : Wt;
             msym_acc(m, a[0], sv, dst);
-            mmat<0, 1, 0>(t, m);
-            msym_acc(m, a[1], sv, dst);
-            mmat<0, 0, 1>(t, m);
-            msym_acc(m, a[2], sv, dst);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) dst[c] += sv * tv[c];
+        }
+        {
+            // <u v psi psi^T>_half a_1 + <u w psi psi^T>_half a_2 by the same identity, from the
+            // <u psi psi^T>_half products and columns
+            T y1[5] = {T(0), T(0), T(0), T(0), T(0)}, y2[5] = {T(0), T(0), T(0), T(0), T(0)};
+            msym_acc(m, a[1], T(1), y1);
+            msym_acc(m, a[2], T(1), y2);
+            const T th = s.h, sk = -cf.k1 * rho;
+            const T c0[5] = {m[0], m[1], m[2], m[3], m[4]};     // <u psi>
+            const T c2[5] = {m[2], m[6], m[9], m[10], m[11]};   // <u v psi>
+            const T c3[5] = {m[3], m[7], m[10], m[12], m[13]};  // <u w psi>
+            T tu[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+                tu[c] = s.V * y1[c] + s.W * y2[c] +
+                        th * ((a[1][2] + a[2][3]) * c0[c] + a[1][4] * c2[c] + a[2][4] * c3[c]);
+            tu[2] += th * y1[0];
+            tu[3] += th * y2[0];
+            tu[4] += th * (y1[2] + y2[3]);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) F[c] += sk * tu[c];
         }
         mmat<2, 0, 0>(t, m);
         msym_acc(m, a[0], -cf.k1 * rho, F);
-        mmat<1, 1, 0>(t, m);
-        msym_acc(m, a[1], -cf.k1 * rho, F);
-        mmat<1, 0, 1>(t, m);
-        msym_acc(m, a[2], -cf.k1 * rho, F);
     }
     const Side<T> sc = side_of(Wc, gam);
     if (!(sc.rho > T(0) && sc.lam > T(0))) return false;
