@@ -513,6 +513,30 @@ template <class T> CGKS_HD void value_at(const GksMoments<T> &m, T t, T tau, T t
     combine(c, m.Vc, m.Vk, Wt);
 }
 
+// Tangential transport over a half space in u: with m = <h(u) psi psi^T>_half for a weight h(u),
+// out = <h v psi psi^T>_half a1 + <h w psi psi^T>_half a2.  The half space restricts u only, so
+// the v and w integrals are Gaussian with means V, W and variance th = p/rho, and Stein's
+// identity <v f> = V <f> + th <df/dv> (dpsi/dv = e_v + v e_E) reduces both terms to the products
+// y1 = m a1, y2 = m a2 (returned) and the columns <h psi>, <h v psi>, <h w psi> of m.
+template <class T>
+CGKS_HD void tangential_transport(const T m[15], const T a1[5], const T a2[5], T V, T W, T th, T y1[5], T y2[5],
+                                  T out[5])
+{
+#pragma unroll
+    for (int c = 0; c < 5; ++c) y1[c] = y2[c] = T(0);
+    msym_acc(m, a1, T(1), y1);
+    msym_acc(m, a2, T(1), y2);
+    const T c0[5] = {m[0], m[1], m[2], m[3], m[4]};     // <h psi>
+    const T c2[5] = {m[2], m[6], m[9], m[10], m[11]};   // <h v psi>
+    const T c3[5] = {m[3], m[7], m[10], m[12], m[13]};  // <h w psi>
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+        out[c] = V * y1[c] + W * y2[c] + th * ((a1[2] + a2[3]) * c0[c] + a1[4] * c2[c] + a2[4] * c3[c]);
+    out[2] += th * y1[0];
+    out[3] += th * y2[0];
+    out[4] += th * (y1[2] + y2[3]);
+}
+
 // Flux over [0, dt] and interface value at dt of one Gauss point with the time coefficients
 // applied while the moments accumulate: the same sums as gks_moments + flux_integrated + value_at
 // without keeping the twelve moment vectors for a final combination.
@@ -584,29 +608,15 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
         mmat<0, 0, 0>(t, m);  // <psi psi>_half
         if (!VISC) mcol0_acc(m, rho, Wc);
         msym_acc(m, a[0], rho, dWc[0]);
-        // tangential transport <v psi psi^T>_half a_1 + <w psi psi^T>_half a_2: the half space
-        // restricts u only, so the v and w integrals are Gaussian with means V, W and variance
-        // th = p/rho, and <v f> = V <f> + th <df/dv> (Stein's identity) reduces each term to the
-        // <psi psi^T>_half products and columns already at hand
-        T tv[5];
+        T tv[5];  // <v psi psi^T>_half a_1 + <w psi psi^T>_half a_2
         if (VISC || VAL) {
-            T y1[5] = {T(0), T(0), T(0), T(0), T(0)}, y2[5] = {T(0), T(0), T(0), T(0), T(0)};
-            msym_acc(m, a[1], T(1), y1);
-            msym_acc(m, a[2], T(1), y2);
-            const T th = s.h;
-            const T c0[5] = {m[0], m[1], m[2], m[3], m[4]};     // <psi>
-            const T c2[5] = {m[2], m[6], m[9], m[10], m[11]};   // <v psi>
-            const T c3[5] = {m[3], m[7], m[10], m[12], m[13]};  // <w psi>
+            T y1[5], y2[5];
+            tangential_transport(m, a[1], a[2], s.V, s.W, s.h, y1, y2, tv);
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 dWc[1][c] += rho * y1[c];
                 dWc[2][c] += rho * y2[c];
-                tv[c] = s.V * y1[c] + s.W * y2[c] +
-                        th * ((a[1][2] + a[2][3]) * c0[c] + a[1][4] * c2[c] + a[2][4] * c3[c]);
             }
-            tv[2] += th * y1[0];
-            tv[3] += th * y2[0];
-            tv[4] += th * (y1[2] + y2[3]);
         } else {
             msym_acc(m, a[1], rho, dWc[1]);
             msym_acc(m, a[2], rho, dWc[2]);
@@ -628,23 +638,10 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
             for (int c = 0; c < 5; ++c) dst[c] += sv * tv[c];
         }
         {
-            // <u v psi psi^T>_half a_1 + <u w psi psi^T>_half a_2 by the same identity, from the
-            // <u psi psi^T>_half products and columns
-            T y1[5] = {T(0), T(0), T(0), T(0), T(0)}, y2[5] = {T(0), T(0), T(0), T(0), T(0)};
-            msym_acc(m, a[1], T(1), y1);
-            msym_acc(m, a[2], T(1), y2);
-            const T th = s.h, sk = -cf.k1 * rho;
-            const T c0[5] = {m[0], m[1], m[2], m[3], m[4]};     // <u psi>
-            const T c2[5] = {m[2], m[6], m[9], m[10], m[11]};   // <u v psi>
-            const T c3[5] = {m[3], m[7], m[10], m[12], m[13]};  // <u w psi>
-            T tu[5];
-#pragma unroll
-            for (int c = 0; c < 5; ++c)
-                tu[c] = s.V * y1[c] + s.W * y2[c] +
-                        th * ((a[1][2] + a[2][3]) * c0[c] + a[1][4] * c2[c] + a[2][4] * c3[c]);
-            tu[2] += th * y1[0];
-            tu[3] += th * y2[0];
-            tu[4] += th * (y1[2] + y2[3]);
+            // <u v psi psi^T>_half a_1 + <u w psi psi^T>_half a_2
+            T y1[5], y2[5], tu[5];
+            tangential_transport(m, a[1], a[2], s.V, s.W, s.h, y1, y2, tu);
+            const T sk = -cf.k1 * rho;
 #pragma unroll
             for (int c = 0; c < 5; ++c) F[c] += sk * tu[c];
         }
