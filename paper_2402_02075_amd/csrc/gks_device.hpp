@@ -537,6 +537,22 @@ CGKS_HD void tangential_transport(const T m[15], const T a1[5], const T a2[5], T
     out[4] += th * (y1[2] + y2[3]);
 }
 
+// Normal transport over a half space in u: <u^2 psi psi^T>_half a from mu = <u psi psi^T>_half,
+// y0 = <psi psi^T>_half a and yu = mu a.  Integrating by parts in u, (u - U) g = -th dg/du, so
+// <u f>_half = U <f>_half + th <df/du>_half plus a boundary term th f(0) g(0) that vanishes here
+// because f = u psi (psi.a) has the factor u; with dpsi/du = e_u + u e_E that leaves y0, yu and
+// the columns <u psi>, <u^2 psi> of mu.
+template <class T>
+CGKS_HD void normal_transport(const T mu[15], const T y0[5], const T yu[5], const T a[5], T U, T th, T out[5])
+{
+    const T c0[5] = {mu[0], mu[1], mu[2], mu[3], mu[4]};  // <u psi>
+    const T c1[5] = {mu[1], mu[5], mu[6], mu[7], mu[8]};  // <u^2 psi>
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[c] = U * yu[c] + th * (y0[c] + a[1] * c0[c] + a[4] * c1[c]);
+    out[1] += th * yu[0];
+    out[4] += th * yu[1];
+}
+
 // Flux over [0, dt] and interface value at dt of one Gauss point with the time coefficients
 // applied while the moments accumulate: the same sums as gks_moments + flux_integrated + value_at
 // without keeping the twelve moment vectors for a final combination.
@@ -607,7 +623,16 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
         T m[15];
         mmat<0, 0, 0>(t, m);  // <psi psi>_half
         if (!VISC) mcol0_acc(m, rho, Wc);
-        msym_acc(m, a[0], rho, dWc[0]);
+        // value modes keep <psi psi^T>_half a_0 for the normal transport below; the residual-only
+        // mode forms that term from <u^2 psi psi^T>_half instead (fewer live registers)
+        T y0[5] = {T(0), T(0), T(0), T(0), T(0)};
+        if (VISC || VAL) {
+            msym_acc(m, a[0], T(1), y0);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) dWc[0][c] += rho * y0[c];
+        } else {
+            msym_acc(m, a[0], rho, dWc[0]);
+        }
         T tv[5];  // <v psi psi^T>_half a_1 + <w psi psi^T>_half a_2
         if (VISC || VAL) {
             T y1[5], y2[5];
@@ -630,12 +655,13 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
         mmat<1, 0, 0>(t, m);  // <u psi psi>_half
         mcol0_acc(m, cf.e * rho, F);
         msym_acc(m, A, -cf.k2 * rho, F);
+        T yu[5] = {T(0), T(0), T(0), T(0), T(0)};  // <u psi psi^T>_half a_0
         if (VISC || VAL) {
+            msym_acc(m, a[0], T(1), yu);
             const T sv = VISC ? rho : -cw.k1 * rho;
             T *dst = VISC ? Vk[1] : Wt;
-            msym_acc(m, a[0], sv, dst);
 #pragma unroll
-            for (int c = 0; c < 5; ++c) dst[c] += sv * tv[c];
+            for (int c = 0; c < 5; ++c) dst[c] += sv * (yu[c] + tv[c]);
         }
         {
             // <u v psi psi^T>_half a_1 + <u w psi psi^T>_half a_2
@@ -645,8 +671,17 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
 #pragma unroll
             for (int c = 0; c < 5; ++c) F[c] += sk * tu[c];
         }
-        mmat<2, 0, 0>(t, m);
-        msym_acc(m, a[0], -cf.k1 * rho, F);
+        if (VISC || VAL) {
+            // <u^2 psi psi^T>_half a_0
+            T tn[5];
+            normal_transport(m, y0, yu, a[0], s.U, s.h, tn);
+            const T sk = -cf.k1 * rho;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) F[c] += sk * tn[c];
+        } else {
+            mmat<2, 0, 0>(t, m);
+            msym_acc(m, a[0], -cf.k1 * rho, F);
+        }
     }
     const Side<T> sc = side_of(Wc, gam);
     if (!(sc.rho > T(0) && sc.lam > T(0))) return false;
