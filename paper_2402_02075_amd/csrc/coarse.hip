@@ -725,6 +725,20 @@ __global__ __launch_bounds__(256) void k_kfvs_rows(CoarseArgs<T> A, const T *__r
         cs = sqrt(A.gam * p * ir);
         Vi = V[i];
     }
+    // the row's own inputs of the epilogue, requested before the face loop so that their latency
+    // overlaps it (lane 0 of the row uses them)
+    T pre[10];
+    if (g == 0) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            if (FIRST) {
+                pre[q] = Rs[q * n + i];
+            } else {
+                pre[q] = A.W[q * n + i] + D[q * n + i];
+                pre[5 + q] = F[q * n + i];
+            }
+        }
+    }
     T r[5] = {T(0), T(0), T(0), T(0), T(0)};
     double sum = 0.0;
     for (int k = ptr[i] + g; k < ptr[i + 1]; k += RG) {
@@ -768,15 +782,14 @@ __global__ __launch_bounds__(256) void k_kfvs_rows(CoarseArgs<T> A, const T *__r
         const T h = dti / T(Vi);
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            const T rs = Rs[q * n + i];
-            F[q * n + i] = rs - r[q];
-            Dout[q * n + i] = h * rs;
+            F[q * n + i] = pre[q] - r[q];
+            Dout[q * n + i] = h * pre[q];
         }
     } else {
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            Wout[q * n + i] = A.W[q * n + i] + D[q * n + i];
-            Rout[q * n + i] = r[q] + F[q * n + i];
+            Wout[q * n + i] = pre[q];
+            Rout[q * n + i] = r[q] + pre[5 + q];
         }
     }
 }
@@ -889,6 +902,7 @@ __global__ __launch_bounds__(256) void k_restrict(int64_t nc, int64_t nf, const 
     const int64_t k = t / RG;
     const int g = (int)(t % RG);
     if (k >= nc) return;  // whole row groups leave together
+    const double vk = (g == 0 && Wc) ? Vc[k] : 1.0;  // requested ahead of the member loop
     double w[5] = {0, 0, 0, 0, 0}, r[5] = {0, 0, 0, 0, 0};
     for (int q = ptr[k] + g; q < ptr[k + 1]; q += RG) {
         const int i = idx[q];
@@ -907,7 +921,7 @@ __global__ __launch_bounds__(256) void k_restrict(int64_t nc, int64_t nf, const 
     if (g == 0)
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            if (Wc) Wc[c * nc + k] = Tc(w[c] / Vc[k]);
+            if (Wc) Wc[c * nc + k] = Tc(w[c] / vk);
             if (Rc) Rc[c * nc + k] = Tc(r[c]);
         }
 }
