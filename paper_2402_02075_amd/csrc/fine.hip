@@ -506,6 +506,14 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A, double *__restrict
     const int64_t N = A.N;
     double r2 = 0.0;
     if (i < N) {  // whole cell groups take the same branch
+        // the cell's own inputs, requested before the face loop so that their latency overlaps it
+        const double vi = A.vol[i];
+        double dti = 0.0, w0[5] = {0, 0, 0, 0, 0};
+        if (FE && g == 0) {
+            dti = dt[i];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) w0[q] = W[q * N + i];
+        }
         double r[5] = {0, 0, 0, 0, 0};
         double gs[15];
 #pragma unroll
@@ -531,7 +539,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A, double *__restrict
             for (int q = 0; q < 15; ++q) gs[q] = cell_sum(gs[q]);
             al = cell_prod(al);
         }
-        const double iv = 1.0 / A.vol[i];
+        const double iv = 1.0 / vi;
         if (g == 0) {
 #pragma unroll
             for (int q = 0; q < 5; ++q) R[q * N + i] = r[q];
@@ -541,9 +549,9 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A, double *__restrict
                 an[i] = al;
             }
             if (FE) {
-                const double h = dt[i] * iv;
+                const double h = dti * iv;
 #pragma unroll
-                for (int q = 0; q < 5; ++q) W[q * N + i] += h * r[q];
+                for (int q = 0; q < 5; ++q) W[q * N + i] = w0[q] + h * r[q];
             }
             const double rr = r[0] * iv;
             r2 = rr * rr;
