@@ -803,6 +803,10 @@ __global__ __launch_bounds__(256) void k_kfvs_gather(int64_t n, int64_t m, const
     const int64_t i = t / RG;
     const int g = (int)(t % RG);
     if (i >= n) return;  // whole row groups leave together
+    T ad[5];  // requested before the face loop so its latency overlaps it
+    if (g == 0 && add)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) ad[q] = add[q * n + i];
     T r[5] = {T(0), T(0), T(0), T(0), T(0)};
     for (int k = ptr[i] + g; k < ptr[i + 1]; k += RG) {
         const int it = item[k];
@@ -821,7 +825,7 @@ __global__ __launch_bounds__(256) void k_kfvs_gather(int64_t n, int64_t m, const
     for (int q = 0; q < 5; ++q) r[q] = row_sum(r[q]);
     if (g == 0)
 #pragma unroll
-        for (int q = 0; q < 5; ++q) R[q * n + i] = add ? r[q] + add[q * n + i] : r[q];
+        for (int q = 0; q < 5; ++q) R[q * n + i] = add ? r[q] + ad[q] : r[q];
 }
 
 // local time step on a coarse level
@@ -1117,6 +1121,16 @@ template <class T> __global__ __launch_bounds__(256) void k_imp_diag(ImpArgs<T> 
     T Ui[5];
     load5(a.W, n, i, Ui);
     const double Vi = a.V[i];
+    // the row's own epilogue inputs, requested before the face loop so their latency overlaps it
+    T dti = T(1), rh[5], d0[5];
+    if (g == 0) {
+        dti = a.dt[i];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            rh[q] = a.rhs[q * n + i];
+            d0[q] = a.acc ? a.dout[q * n + i] : T(0);
+        }
+    }
     T sum = T(0);
     for (int k = a.ptr[i] + g; k < a.ptr[i + 1]; k += RG) {
         const int it = a.item[k];
@@ -1153,12 +1167,12 @@ template <class T> __global__ __launch_bounds__(256) void k_imp_diag(ImpArgs<T> 
     }
     sum = row_sum(sum);
     if (g == 0) {
-        const T d = T(Vi) / a.dt[i] + sum;
+        const T d = T(Vi) / dti + sum;
         a.dg[i] = d;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            const T v = a.rhs[q * n + i] / d;
-            a.dout[q * n + i] = a.acc ? a.dout[q * n + i] + v : v;
+            const T v = rh[q] / d;
+            a.dout[q * n + i] = a.acc ? d0[q] + v : v;
         }
     }
 }
@@ -1171,6 +1185,16 @@ template <class T> __global__ __launch_bounds__(256) void k_imp_sweep(ImpArgs<T>
     const int g = (int)(t % RG);
     if (i >= a.n) return;  // whole row groups leave together
     const int64_t n = a.n;
+    // the row's own epilogue inputs, requested before the face loop so their latency overlaps it
+    T dgi = T(1), rh[5], d0[5];
+    if (g == 0) {
+        dgi = a.dg[i];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            rh[q] = a.rhs[q * n + i];
+            d0[q] = a.acc ? a.dout[q * n + i] : T(0);
+        }
+    }
     T r[5] = {T(0), T(0), T(0), T(0), T(0)};
     for (int k = a.ptr[i] + g; k < a.ptr[i + 1]; k += RG) {
         const int it = a.item[k];
@@ -1199,11 +1223,10 @@ template <class T> __global__ __launch_bounds__(256) void k_imp_sweep(ImpArgs<T>
 #pragma unroll
     for (int q = 0; q < 5; ++q) r[q] = row_sum(r[q]);
     if (g == 0) {
-        const T d = a.dg[i];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            const T v = (a.rhs[q * n + i] - r[q]) / d;
-            a.dout[q * n + i] = a.acc ? a.dout[q * n + i] + v : v;
+            const T v = (rh[q] - r[q]) / dgi;
+            a.dout[q * n + i] = a.acc ? d0[q] + v : v;
         }
     }
 }
