@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 # Algorithmic operations per face Gauss point of the fine flux kernel (inviscid steady mode, FP64),
 # counted by instantiating the kernel's per-point source with a counting scalar
 # (paper_2402_02075_amd/csrc/flopcount.hip; quadrilateral faces, face sum included).
-FLOPS_PER_GP = 3905.75
+FLOPS_PER_GP = 3775.75
 FP64_PEAK_TFLOPS = 78.6       # MI355X dense FP64 vector
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the same face kernel on this workload, from two rocprofv3 counter passes

@@ -537,6 +537,27 @@ CGKS_HD void tangential_transport(const T m[15], const T a1[5], const T a2[5], T
     out[4] += th * (y1[2] + y2[3]);
 }
 
+// The parts of tangential_transport that are not m (V a1 + W a2): th ((a1_v + a2_w) <h psi> +
+// a1_E <h v psi> + a2_E <h w psi>) and the e_v, e_w, e_E terms from rows 0, 2 and 3 of m times
+// a1, a2.  A caller that folds m (V a1 + W a2) into another product with m adds these.
+template <class T>
+CGKS_HD void tangential_rest(const T m[15], const T a1[5], const T a2[5], T th, T s, T out[5])
+{
+    const T r10 = m[0] * a1[0] + m[1] * a1[1] + m[2] * a1[2] + m[3] * a1[3] + m[4] * a1[4];     // (m a1)_0
+    const T r12 = m[2] * a1[0] + m[6] * a1[1] + m[9] * a1[2] + m[10] * a1[3] + m[11] * a1[4];   // (m a1)_v
+    const T r20 = m[0] * a2[0] + m[1] * a2[1] + m[2] * a2[2] + m[3] * a2[3] + m[4] * a2[4];     // (m a2)_0
+    const T r23 = m[3] * a2[0] + m[7] * a2[1] + m[10] * a2[2] + m[12] * a2[3] + m[13] * a2[4];  // (m a2)_w
+    const T c0[5] = {m[0], m[1], m[2], m[3], m[4]};
+    const T c2[5] = {m[2], m[6], m[9], m[10], m[11]};
+    const T c3[5] = {m[3], m[7], m[10], m[12], m[13]};
+    const T st = s * th;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[c] += st * ((a1[2] + a2[3]) * c0[c] + a1[4] * c2[c] + a2[4] * c3[c]);
+    out[2] += st * r10;
+    out[3] += st * r20;
+    out[4] += st * (r12 + r23);
+}
+
 // Normal transport over a half space in u: <u^2 psi psi^T>_half a from mu = <u psi psi^T>_half,
 // y0 = <psi psi^T>_half a and yu = mu a.  Integrating by parts in u, (u - U) g = -th dg/du, so
 // <u f>_half = U <f>_half + th <df/du>_half plus a boundary term th f(0) g(0) that vanishes here
@@ -654,7 +675,16 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
         }
         mmat<1, 0, 0>(t, m);  // <u psi psi>_half
         mcol0_acc(m, cf.e * rho, F);
-        msym_acc(m, A, -cf.k2 * rho, F);
+        const T sk = -cf.k1 * rho;
+        {
+            // F += <u psi psi^T>_half (-k2 rho A - k1 rho (V a_1 + W a_2)) in one product, then the
+            // rest of the tangential transport <u v psi psi^T>_half a_1 + <u w psi psi^T>_half a_2
+            T b[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) b[c] = -cf.k2 * rho * A[c] + sk * (s.V * a[1][c] + s.W * a[2][c]);
+            msym_acc(m, b, T(1), F);
+            tangential_rest(m, a[1], a[2], s.h, sk, F);
+        }
         T yu[5] = {T(0), T(0), T(0), T(0), T(0)};  // <u psi psi^T>_half a_0
         if (VISC || VAL) {
             msym_acc(m, a[0], T(1), yu);
@@ -663,19 +693,10 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
 #pragma unroll
             for (int c = 0; c < 5; ++c) dst[c] += sv * (yu[c] + tv[c]);
         }
-        {
-            // <u v psi psi^T>_half a_1 + <u w psi psi^T>_half a_2
-            T y1[5], y2[5], tu[5];
-            tangential_transport(m, a[1], a[2], s.V, s.W, s.h, y1, y2, tu);
-            const T sk = -cf.k1 * rho;
-#pragma unroll
-            for (int c = 0; c < 5; ++c) F[c] += sk * tu[c];
-        }
         if (VISC || VAL) {
             // <u^2 psi psi^T>_half a_0
             T tn[5];
             normal_transport(m, y0, yu, a[0], s.U, s.h, tn);
-            const T sk = -cf.k1 * rho;
 #pragma unroll
             for (int c = 0; c < 5; ++c) F[c] += sk * tn[c];
         } else {
