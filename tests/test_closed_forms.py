@@ -31,7 +31,7 @@ static double rel(const double *a, const double *b) {
 int main() {
     std::mt19937_64 rng(3);
     std::uniform_real_distribution<double> U(-1, 1);
-    double e_tr = 0, e_fx = 0, e_jt = 0, e_q2 = 0, e_tan = 0, e_tanu = 0, e_nor = 0;
+    double e_tr = 0, e_fx = 0, e_jt = 0, e_q2 = 0, e_tan = 0, e_tanu = 0, e_nor = 0, e_rest = 0;
     for (int it = 0; it < 2000; ++it) {
         const double gam = it % 2 ? 1.4 : 5.0 / 3.0, K = (5 - 3 * gam) / (gam - 1), iK3 = 1 / (K + 3);
         double w[5];
@@ -80,6 +80,12 @@ int main() {
             e_tan = fmax(e_tan, rel(out, ref));
             tangential_transport(mu, a[1], a[2], s.V, s.W, s.h, y1, y2, out);
             e_tanu = fmax(e_tanu, rel(out, refu));
+            // the same through one product with mu plus the remaining row terms
+            double bb[5], comb[5] = {0, 0, 0, 0, 0};
+            for (int c = 0; c < 5; ++c) bb[c] = s.V * a[1][c] + s.W * a[2][c];
+            msym_acc(mu, bb, 1.0, comb);
+            tangential_rest(mu, a[1], a[2], s.h, 1.0, comb);
+            e_rest = fmax(e_rest, rel(comb, refu));
             double y0[5] = {0, 0, 0, 0, 0}, yu[5] = {0, 0, 0, 0, 0};
             msym_acc(m0, a[0], 1.0, y0);
             msym_acc(mu, a[0], 1.0, yu);
@@ -87,7 +93,7 @@ int main() {
             e_nor = fmax(e_nor, rel(out, refn));
         }
     }
-    printf("%.3e %.3e %.3e %.3e %.3e %.3e %.3e\n", e_tr, e_fx, e_jt, e_q2, e_tan, e_tanu, e_nor);
+    printf("%.3e %.3e %.3e %.3e %.3e %.3e %.3e %.3e\n", e_tr, e_fx, e_jt, e_q2, e_tan, e_tanu, e_nor, e_rest);
     return 0;
 }
 """
@@ -106,11 +112,11 @@ def errors(tmp_path_factory):
     assert r.returncode == 0, r.stderr[-2000:]
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     names = ["transport", "euler_flux", "time_slope_moment", "second_transport", "tangential", "tangential_u",
-             "normal_u2"]
+             "normal_u2", "tangential_merged"]
     return dict(zip(names, map(float, out)))
 
 
 @pytest.mark.parametrize("name", ["transport", "euler_flux", "time_slope_moment", "second_transport", "tangential",
-                                  "tangential_u", "normal_u2"])
+                                  "tangential_u", "normal_u2", "tangential_merged"])
 def test_closed_form_matches_moment_matrices(errors, name):
     assert errors[name] < 1e-12, errors
