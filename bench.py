@@ -413,8 +413,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true", help="run a plain 1 GiB copy first (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
-                                   "not an implemented path", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this solver runs on one GPU; sharding the mesh over several GPUs is "
+                                   "not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     from paper_2402_02075_amd import cgks as cg
