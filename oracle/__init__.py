@@ -61,6 +61,8 @@ def lib():
         L.om_reconstruct_all.argtypes = [P, P, P, P, P, P]
         L.om_gks_point_flat.argtypes = [P, P, P, P, D, P, P]
         L.om_kfvs_point.argtypes = [P, P, D, P]
+        L.om_cf_point.restype = D
+        L.om_cf_point.argtypes = [P, P, D]
         L.om_slopes_flat.argtypes = [D, P, D, D, P, P, P]
         L.om_monomial_moment.restype = D
         L.om_monomial_moment.argtypes = [P, D, D, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
@@ -220,6 +222,11 @@ def kfvs_point(Wl, Wr, gamma=1.4):
     F = np.zeros(5)
     lib().om_kfvs_point(_p(_f64(Wl)), _p(_f64(Wr)), float(gamma), _p(F))
     return F
+
+
+def cf_point(Wl, Wr, gamma=1.4):
+    """Compression factor of one Gauss point from the two states in the face frame (normal = x)."""
+    return lib().om_cf_point(_p(_f64(Wl)), _p(_f64(Wr)), float(gamma))
 
 
 def slopes(rho, U, lam, K, dW):

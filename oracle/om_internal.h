@@ -84,6 +84,8 @@ void om_rotate_state(const double *W, const double *n, const double *t1, const d
 void om_rotate_back(const double *Wl, const double *n, const double *t1, const double *t2, double *W);
 void om_rotate_grad(const double *G, const double *n, const double *t1, const double *t2, double *Gl);
 
+double om_cf_point(const double *wl, const double *wr, double gamma);
+
 /* bc.c */
 void om_bc_ghost_state(const om_bc *bc, const double *n, const double *Wi, double gamma, double *Wg);
 void om_bc_ghost_grad(const om_bc *bc, const double *n, const double *Gi, double *Gg);

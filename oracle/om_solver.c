@@ -62,6 +62,27 @@ int om_local_dt(const om_mesh *m, const om_params *p, const double *W, double *d
     return bad < 0 ? 0 : -1;
 }
 
+/* Gradient compression factor of one Gauss point (Sec. 3.3) from the two reconstructed states in
+ * the face frame (first momentum component along the normal): 1/(1 + A^2) with A the pressure
+ * jump relative to each side's pressure plus the squared jumps of the normal and tangential Mach
+ * numbers (tangential speed over sound speed). */
+double om_cf_point(const double *wl, const double *wr, double gamma)
+{
+    double pr[2], man[2], mat[2];
+    const double *S2[2] = {wl, wr};
+    for (int s = 0; s < 2; ++s) {
+        const double *ws = S2[s];
+        double u = ws[1] / ws[0], v = ws[2] / ws[0], ww = ws[3] / ws[0];
+        pr[s] = (gamma - 1.0) * (ws[4] - 0.5 * ws[0] * (u * u + v * v + ww * ww));
+        double cs = sqrt(gamma * pr[s] / ws[0]);
+        man[s] = u / cs;
+        mat[s] = sqrt(v * v + ww * ww) / cs;
+    }
+    double dp = fabs(pr[0] - pr[1]);
+    double A = dp / pr[0] + dp / pr[1] + (man[0] - man[1]) * (man[0] - man[1]) + (mat[0] - mat[1]) * (mat[0] - mat[1]);
+    return 1.0 / (1.0 + A * A);
+}
+
 typedef struct {
     double F[5];      /* sum_k w_k S F_avg (along n, L -> R) */
     double Fh[5];     /* sum_k w_k S F_int(dt/2) */
@@ -117,22 +138,7 @@ static int face_eval(const om_mesh *m, const om_params *p, const double *coef, i
                 o->Wc[3 * q + d] += w * Wcc[q] * n[d];
             }
         }
-        if (r >= 0) {
-            /* gradient compression factor from the two Gauss-point states */
-            double pr[2], man[2], mat[2];
-            const double *S2[2] = {wl, wr};
-            for (int s = 0; s < 2; ++s) {
-                const double *ws = S2[s];
-                double u = ws[1] / ws[0], v = ws[2] / ws[0], ww = ws[3] / ws[0];
-                pr[s] = (p->gamma - 1.0) * (ws[4] - 0.5 * ws[0] * (u * u + v * v + ww * ww));
-                double cs = sqrt(p->gamma * pr[s] / ws[0]);
-                man[s] = u / cs;
-                mat[s] = sqrt(v * v + ww * ww) / cs;
-            }
-            double dp = fabs(pr[0] - pr[1]);
-            double A = dp / pr[0] + dp / pr[1] + (man[0] - man[1]) * (man[0] - man[1]) + (mat[0] - mat[1]) * (mat[0] - mat[1]);
-            o->alpha *= 1.0 / (1.0 + A * A);
-        }
+        if (r >= 0) o->alpha *= om_cf_point(wl, wr, p->gamma);
     }
     return 0;
 }
