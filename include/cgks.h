@@ -16,7 +16,8 @@
  *    ROCm), used stream-ordered on the stream given to cgks_set_stream (the
  *    null stream by default).  The library never frees caller memory.
  *    "host" pointers are read or written before the call returns.
- *  - Cell fields are FP64, component-major, in the caller's cell order:
+ *  - Cell fields are FP64, component-major, in the caller's cell order (or in the library's
+ *    internal order with params.cell_order = 2, see cgks_cell_order):
  *      W[c*N + i]        c = rho, rho u, rho v, rho w, rho E      (5 x N)
  *      G[(3c+d)*N + i]   cell average of dW_c/dx_d, d = x, y, z    (15 x N)
  *      alpha[i]          gradient compression factor               (N)
@@ -79,6 +80,16 @@ typedef struct {
     double cfl_implicit;     /* CFL number of the implicit coarse smoother's local step (0.25) */
     int32_t cycle_gamma;     /* visits of each coarser level per visit of its parent, each continuing
                                 with the same forcing: 1 V-cycle (default), 2 W-cycle (1..3) */
+    int32_t cell_order;      /* internal order of the cells, fixed by cgks_set_mesh:
+                                0  the caller's order;
+                                1  (default) a locality order (by element type, then along the
+                                   Hilbert curve through the cell centroids; faces sorted by their
+                                   cells in that order); every cell array at
+                                   this ABI stays in the caller's order and is gathered / scattered
+                                   at the call (one extra pass over the array);
+                                2  the same locality order, and cell arrays at this ABI are exchanged
+                                   in it (no gather or scatter; cgks_cell_order gives the order).
+                                Switching between 0 and 1/2 needs a new cgks_set_mesh. */
 } cgks_params;
 
 /* Fill *p with the defaults above. */
@@ -110,6 +121,15 @@ cgks_status cgks_set_stream(cgks_ctx *ctx, void *hip_stream);
 cgks_status cgks_set_mesh(cgks_ctx *ctx, int64_t n_nodes, const double *xyz, int64_t n_cells, const uint8_t *ctype,
                           const int64_t *cnode_ptr, const int64_t *cnode, int64_t n_bfaces, const int64_t *bnode_ptr,
                           const int64_t *bnode, const int32_t *btag, const int64_t *node_canon);
+
+/*
+ * Internal cell order (the data layout in HBM): perm[i] (host out, int32[N]) is the caller's id of
+ * the i-th cell as the library stores it.  The identity with params.cell_order = 0.  With
+ * cell_order = 2 every cell array at this ABI is indexed in this order.  The agglomeration
+ * (cgks_agglomerate) always hashes and orders by the caller's ids (paper Sec. 4.1), so the
+ * hierarchy does not depend on the internal order.  CGKS_E_STATE without a mesh.
+ */
+cgks_status cgks_cell_order(const cgks_ctx *ctx, int32_t *perm);
 
 /* Boundary condition of a tag (1..63).  prim = far-field rho, u, v, w, p (host, used by CGKS_BC_FARFIELD). */
 cgks_status cgks_set_bc(cgks_ctx *ctx, int32_t tag, int32_t kind, const double *prim);

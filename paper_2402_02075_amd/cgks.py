@@ -23,7 +23,7 @@ EXPORTS = ["cgks_default_params", "cgks_create", "cgks_destroy", "cgks_last_erro
            "cgks_reconstruct", "cgks_residual", "cgks_step", "cgks_check", "cgks_residual_norm",
            "cgks_agglomerate_graph", "cgks_agglomerate", "cgks_level_map", "cgks_kfvs_residual", "cgks_restrict",
            "cgks_prolong", "cgks_vcycle", "cgks_timing", "cgks_wall_force", "cgks_linearize", "cgks_vjp_residual",
-           "cgks_vjp_wall_force", "cgks_vjp_kfvs", "cgks_adjoint_solve", "cgks_coarse_implicit"]
+           "cgks_vjp_wall_force", "cgks_vjp_kfvs", "cgks_adjoint_solve", "cgks_coarse_implicit", "cgks_cell_order"]
 
 
 class Params(C.Structure):
@@ -33,7 +33,7 @@ class Params(C.Structure):
                 ("passes", C.c_int32), ("precision", C.c_int32), ("nu_pre", C.c_int32 * 8),
                 ("nu_post", C.c_int32 * 8), ("mixed_switch", C.c_double), ("seed", C.c_uint64),
                 ("coarse_smoother", C.c_int32), ("relax_sweeps", C.c_int32), ("cfl_implicit", C.c_double),
-                ("cycle_gamma", C.c_int32)]
+                ("cycle_gamma", C.c_int32), ("cell_order", C.c_int32)]
 
 
 class CgksError(RuntimeError):
@@ -65,7 +65,7 @@ def lib():
             "cgks_wall_force": [P, P, P, P, I32, P], "cgks_linearize": [P, P, P, P],
             "cgks_vjp_residual": [P, P, P, P, P, P, P], "cgks_vjp_wall_force": [P, I32, P, P, P, P],
             "cgks_vjp_kfvs": [P, I32, P, P, P], "cgks_adjoint_solve": [P, I32, P, I32, D, P, P, P, P, P, P, P, P],
-            "cgks_coarse_implicit": [P, I32, P, P, P],
+            "cgks_coarse_implicit": [P, I32, P, P, P], "cgks_cell_order": [P, P],
         }
         for name, args in sig.items():
             if not hasattr(L, name):
@@ -161,6 +161,12 @@ class Solver:
         self._check(lib().cgks_set_mesh(self.h, m.n_nodes, p[0], m.n_cells, p[1], p[2], p[3], m.n_bfaces, p[4], p[5],
                                         p[6], p[7]))
         self.info()
+
+    def cell_order(self):
+        """perm[i] = caller id of the i-th cell in the library's internal (locality) order."""
+        perm = np.zeros(self.n_cells, np.int32)
+        self._check(lib().cgks_cell_order(self.h, perm.ctypes.data_as(C.c_void_p)))
+        return perm
 
     def set_bc(self, tag, kind, prim=None):
         pr = None if prim is None else _np(prim, np.float64)

@@ -839,7 +839,7 @@ void adj_linearize(cgks_ctx *c, const double *W, const double *G, const double *
     if (hb != INT32_MAX) {
         const int32_t big = INT32_MAX;
         CGKS_HIP(hipMemcpy(c->bad.p, &big, sizeof(int32_t), hipMemcpyHostToDevice));
-        throw Error{CGKS_E_PHYS, "non-physical Gauss-point state while linearising, cell " + std::to_string(hb)};
+        throw Error{CGKS_E_PHYS, "non-physical Gauss-point state while linearising, cell " + std::to_string(c->caller_cell(hb))};
     }
     T.ready = true;
 }

@@ -23,6 +23,7 @@
 // The skewness predicate uses +, -, * only in a fixed association order with
 // contraction off, so it takes bit-identical decisions on identical inputs.
 #include <hipcub/hipcub.hpp>
+#include <parallel/algorithm>
 
 #include "common.hpp"
 #include "gks_device.hpp"
@@ -385,30 +386,6 @@ void agglomerate_graph(cgks_ctx *c, int64_t n, const double *V, const double *P,
 }
 
 // ---------------------------------------------------------------- hierarchy
-__global__ void k_first_moment(int64_t N, const double *__restrict__ vol, const double *__restrict__ cen,
-                               double *__restrict__ P)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) P[3 * i + d] = vol[i] * cen[d * N + i];
-}
-
-__global__ void k_gather_pairs(int64_t m, const int32_t *__restrict__ fidx, int64_t F, const double *__restrict__ farea,
-                               const double *__restrict__ fmom, const double *__restrict__ favec, double *__restrict__ S,
-                               double *__restrict__ M, double *__restrict__ A)
-{
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
-    const int f = fidx[j];
-    S[j] = farea[f];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        M[3 * j + d] = fmom[d * F + f];
-        A[3 * j + d] = favec[d * F + f];
-    }
-}
-
 __global__ void k_interleaved_to_soa(int64_t m, const double *__restrict__ in, double *__restrict__ out)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -470,12 +447,21 @@ void build_hierarchy(cgks_ctx *c)
     const int levels = c->prm.levels;
     if (levels <= 1) return;
     const int64_t N = c->N, F = c->F, Fi = c->Fi;
-    // fine graph: interior, non-periodic faces as pairs (L < R, sorted); periodic faces kept aside
+    // Fine graph in the caller's cell ids (Sec. 4.1: the hash of Eq. (hash value) and the order of
+    // Algorithm 1 act on the input numbering): interior, non-periodic faces as pairs a < b of caller
+    // ids, sorted lexicographically, area vectors oriented a -> b; volumes and first moments indexed
+    // by caller id.  Periodic faces are kept aside (never merged).
     std::vector<int32_t> hfl = c->fl.download(F, st), hfr = c->fr.download(F, st), htag = c->ftag.download(F, st);
     std::vector<double> hsh = c->fshift.download(3 * F, st), hav = c->favec.download(3 * F, st),
-                        har = c->farea.download(F, st);
-    std::vector<int32_t> ga, gb, gidx, pera, perb;
+                        har = c->farea.download(F, st), hfm = c->fmom.download(3 * F, st);
+    std::vector<int32_t> pera, perb;
     std::vector<double> perA, perS;
+    struct GPair {
+        int32_t a, b, f;
+        bool flip;
+    };
+    std::vector<GPair> gp;
+    gp.reserve(Fi);
     for (int64_t f = 0; f < Fi; ++f) {
         const bool per = hsh[f] != 0.0 || hsh[F + f] != 0.0 || hsh[2 * F + f] != 0.0;
         if (per) {
@@ -485,11 +471,27 @@ void build_hierarchy(cgks_ctx *c)
             perS.push_back(har[f]);
             continue;
         }
-        if (!ga.empty() && ga.back() == hfl[f] && gb.back() == hfr[f])
+        const int32_t a = (int32_t)c->caller_cell(hfl[f]), b = (int32_t)c->caller_cell(hfr[f]);
+        gp.push_back({std::min(a, b), std::max(a, b), (int32_t)f, a > b});
+    }
+    if (c->permuted)
+        __gnu_parallel::sort(gp.begin(), gp.end(),
+                             [](const GPair &x, const GPair &y) { return x.a != y.a ? x.a < y.a : x.b < y.b; });
+    const int64_t m0 = (int64_t)gp.size();
+    std::vector<int32_t> ga(m0), gb(m0);
+    std::vector<double> gS(m0 + 1), gM(3 * m0 + 3), gA(3 * m0 + 3);
+    for (int64_t j = 0; j < m0; ++j) {
+        if (j > 0 && gp[j].a == gp[j - 1].a && gp[j].b == gp[j - 1].b)
             throw Error{CGKS_E_MESH, "two faces between the same pair of cells are not supported by agglomeration"};
-        ga.push_back(hfl[f]);
-        gb.push_back(hfr[f]);
-        gidx.push_back((int32_t)f);
+        ga[j] = gp[j].a;
+        gb[j] = gp[j].b;
+        const int32_t f = gp[j].f;
+        const double sg = gp[j].flip ? -1.0 : 1.0;
+        gS[j] = har[f];
+        for (int d = 0; d < 3; ++d) {
+            gM[3 * j + d] = hfm[d * F + f];
+            gA[3 * j + d] = sg * hav[d * F + f];
+        }
     }
     std::vector<int32_t> bown, btag;
     std::vector<double> bA;
@@ -499,21 +501,25 @@ void build_hierarchy(cgks_ctx *c)
     }
     const int64_t nbf = F - Fi;
     // device graph of the current finest level
-    int64_t n = N, m = (int64_t)ga.size();
+    int64_t n = N, m = m0;
     DBuf<double> V, P, S, M, A;
-    DBuf<int32_t> pa, pb, fidx;
-    V.alloc(n);
-    P.alloc(3 * n);
-    S.alloc(m + 1);
-    M.alloc(3 * m + 3);
-    A.alloc(3 * m + 3);
+    DBuf<int32_t> pa, pb;
+    {
+        std::vector<double> hv = c->vol.download(N, st), hc = c->cen.download(3 * N, st);
+        std::vector<double> gV(N), gP(3 * N);
+        for (int64_t i = 0; i < N; ++i) {
+            const int64_t o = c->caller_cell(i);
+            gV[o] = hv[i];
+            for (int d = 0; d < 3; ++d) gP[3 * o + d] = hv[i] * hc[d * N + i];
+        }
+        V.upload(gV, st);
+        P.upload(gP, st);
+    }
+    S.upload(gS, st);
+    M.upload(gM, st);
+    A.upload(gA, st);
     pa.upload(ga, st);
     pb.upload(gb, st);
-    fidx.upload(gidx, st);
-    CGKS_HIP(hipMemcpyAsync(V.p, c->vol.p, 8 * n, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_first_moment, G1(n), dim3(256), 0, st, n, c->vol.p, c->cen.p, P.p);
-    if (m) hipLaunchKernelGGL(k_gather_pairs, G1(m), dim3(256), 0, st, m, fidx.p, F, c->farea.p, c->fmom.p, c->favec.p,
-                              S.p, M.p, A.p);
     // fine boundary area vectors (SoA)
     std::vector<double> hbA(3 * nbf);
     for (int64_t k = 0; k < nbf; ++k)
@@ -541,6 +547,13 @@ void build_hierarchy(cgks_ctx *c)
                           nullptr, pac.p, pbc.p, Sc.p, Mc.p, Ac.p);
         L->n = nc;
         std::vector<int32_t> hf2c = L->f2c.download(n, st);
+        if (l == 1 && c->permuted) {
+            // level 1 is kept indexed by internal fine cells: f2c_internal[i] = f2c_caller[perm[i]]
+            std::vector<int32_t> fi(n);
+            for (int64_t i = 0; i < n; ++i) fi[i] = hf2c[c->caller_cell(i)];
+            hf2c.swap(fi);
+            L->f2c.upload(hf2c, st);
+        }
         // periodic pairs carried to the coarse level
         std::vector<int32_t> hpa = pac.download(mc, st), hpb = pbc.download(mc, st);
         std::vector<double> hS = Sc.download(mc, st), hA = Ac.download(3 * mc, st);

@@ -140,7 +140,20 @@ struct cgks_ctx {
     uint64_t tags_used = 0;  // bit t: the mesh has boundary faces with tag t
     uint64_t tags_set = 0;   // bit t: a boundary condition was given for tag t
 
-    // fine geometry (internal order = caller order for cells)
+    // Internal cell order: cells are stored in a locality order (params.cell_order >= 1), the
+    // caller's order otherwise.  perm[i] = caller id of internal cell i (identity when not
+    // permuted); cell arrays crossing the ABI are gathered from / scattered to caller order unless
+    // params.cell_order == 2 (arrays exchanged in the internal order).
+    bool permuted = false;
+    std::vector<int32_t> perm_h;
+    cgks::DBuf<int32_t> perm;
+    cgks::DBuf<double> io[8];  // staging buffers of the ABI gathers and scatters
+    int64_t caller_cell(int64_t i) const
+    {
+        return permuted && i >= 0 && i < (int64_t)perm_h.size() ? perm_h[i] : i;
+    }
+
+    // fine geometry (internal cell order)
     cgks::DBuf<double> vol, cen, mom2;  // [N], [3][N], [6][N]
     cgks::DBuf<int32_t> fl, fr, ftag;   // [F]
     cgks::DBuf<int32_t> fngp;           // [F] 3 or 4

@@ -3,12 +3,15 @@
 // The per-point physics in gks_device.hpp is host-and-device; here it is
 // instantiated on the host with a scalar that counts every add, multiply,
 // divide and transcendental call, following the exact sequence the face kernel
-// executes in its inviscid steady mode (FP64): polynomial evaluation on both
-// sides, rotation to the face frame, moments and micro-slopes of the three
-// Maxwellians with the time coefficients of the flux and of the interface value
-// applied as they accumulate, compression factor, rotation back and the weighted
-// contribution.  A fused multiply-add counts as
-// two operations, matching the convention of the FP64 peak.
+// executes in its steady mode with the gradient update (FP64): polynomial
+// evaluation on both sides, rotation to the face frame, moments and micro-slopes
+// of the three Maxwellians with the time coefficients of the flux and of the
+// interface value applied as they accumulate, compression factor, rotation back
+// and the weighted contribution.  Argument 1: Gauss points of the face (3 or 4);
+// argument 2: "inviscid" (default) or "viscous" (Navier-Stokes path: a first
+// pass for the interface state, tau = mu/p_c, and the Prandtl-number correction
+// of the heat flux).  A fused multiply-add counts as two operations, matching
+// the convention of the FP64 peak.
 #include <cstdio>
 #include <cstring>
 
@@ -51,6 +54,7 @@ using namespace cgks;
 int main(int argc, char **argv)
 {
     const int ngp = argc > 1 ? atoi(argv[1]) : 4;  // Gauss points of the face (3 or 4) for the face-sum share
+    const bool visc = argc > 2 && std::strcmp(argv[2], "viscous") == 0;
     // a smooth, non-degenerate state on both sides
     Cnt coefL[50], coefR[50];
     for (int c = 0; c < 5; ++c)
@@ -63,7 +67,7 @@ int main(int argc, char **argv)
     Cnt n[3] = {1.0, 0.0, 0.0};
     Cnt wS = 0.01, dtf = 0.002;
     const double gam = 1.4;
-    GksCfg cfg{gam, (5.0 - 3.0 * gam) / (gam - 1.0), 0.0, 1.0, 0.01, 1.0, 0};
+    GksCfg cfg{gam, (5.0 - 3.0 * gam) / (gam - 1.0), visc ? 2e-3 : 0.0, visc ? 0.72 : 1.0, 0.01, 1.0, visc ? 1 : 0};
     g = Tally();
     // polynomial evaluation, both sides
     Cnt WL[5], GL[15], WR[5], GR[15];
@@ -80,9 +84,10 @@ int main(int argc, char **argv)
     to_local(WL, GL, n, t1, t2, wl, gl);
     to_local(WR, GR, n, t1, t2, wr, gr);
     const Tally t_rot = g;
-    // the inviscid steady path of the kernel: moments with the time coefficients folded in
+    // the steady path of the kernel: moments with the time coefficients folded in
     Cnt Fl[5], Fg[5], Wt[5], pl, pr;
-    gks_flux_folded<Cnt, true, false>(wl, gl, wr, gr, Cnt(gam), Cnt(cfg.K), dtf, cfg, Fl, Wt, pl, pr);
+    if (visc) gks_flux_folded<Cnt, true, true>(wl, gl, wr, gr, Cnt(gam), Cnt(cfg.K), dtf, cfg, Fl, Wt, pl, pr);
+    else gks_flux_folded<Cnt, true, false>(wl, gl, wr, gr, Cnt(gam), Cnt(cfg.K), dtf, cfg, Fl, Wt, pl, pr);
     const Tally t_mom = g;
     to_global(Fl, n, t1, t2, Fg);
     const Cnt s = wS / dtf;

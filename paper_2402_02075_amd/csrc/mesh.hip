@@ -449,11 +449,12 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
     for (int64_t i = 0; i < N; ++i) {
         const int t = ctype[i];
         if ((t != 4 && t != 5 && t != 6 && t != 8) || cptr[i + 1] - cptr[i] != t)
-            throw Error{CGKS_E_MESH, "cell " + std::to_string(i) + ": unsupported type or node count"};
+            throw Error{CGKS_E_MESH, "cell " + std::to_string(c->caller_cell(i)) + ": unsupported type or node count"};
         const int *hm = hex_of(t);
         for (int a = 0; a < 8; ++a) {
             const int64_t nd = cnode[cptr[i] + hm[a]];
-            if (nd < 0 || nd >= n_nodes) throw Error{CGKS_E_MESH, "cell " + std::to_string(i) + ": node out of range"};
+            if (nd < 0 || nd >= n_nodes)
+                throw Error{CGKS_E_MESH, "cell " + std::to_string(c->caller_cell(i)) + ": node out of range"};
             hexn[a * N + i] = (int32_t)nd;
         }
         nside += faces_of(t);
@@ -506,7 +507,7 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
         } else if (cnt == 2 && sides[i].cell >= 0 && sides[i + 1].cell < 0) {
             faces.push_back({sides[i].cell, -1, sides[i].aux, -1, sides[i + 1].aux});
         } else {
-            throw Error{CGKS_E_MESH, "non-conforming face at cell " + std::to_string(sides[i].cell) + " (" +
+            throw Error{CGKS_E_MESH, "non-conforming face at cell " + std::to_string(c->caller_cell(sides[i].cell)) + " (" +
                                          std::to_string(cnt) + " records)"};
         }
         i = j;
@@ -576,7 +577,7 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
     }
     for (int64_t i = 0; i < N; ++i)
         if (cfp[i + 1] - cfp[i] != faces_of(ctype[i]))
-            throw Error{CGKS_E_MESH, "cell " + std::to_string(i) + ": face count mismatch"};
+            throw Error{CGKS_E_MESH, "cell " + std::to_string(c->caller_cell(i)) + ": face count mismatch"};
     // interior neighbour counts and operator offsets
     std::vector<uint8_t> nint(N, 0);
     for (int64_t f = 0; f < Fi; ++f) {
@@ -683,11 +684,12 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
     int32_t hb = 0;
     CGKS_HIP(hipMemcpyAsync(&hb, c->bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     CGKS_HIP(hipStreamSynchronize(s));
-    if (hb != INT32_MAX) throw Error{CGKS_E_MESH, "singular reconstruction stencil at cell " + std::to_string(hb)};
+    if (hb != INT32_MAX)
+        throw Error{CGKS_E_MESH, "singular reconstruction stencil at cell " + std::to_string(c->caller_cell(hb))};
     // negative volumes are a mesh error
     std::vector<double> hv = c->vol.download(N, s);
     for (int64_t i = 0; i < N; ++i)
-        if (!(hv[i] > 0)) throw Error{CGKS_E_MESH, "cell " + std::to_string(i) + ": non-positive volume"};
+        if (!(hv[i] > 0)) throw Error{CGKS_E_MESH, "cell " + std::to_string(c->caller_cell(i)) + ": non-positive volume"};
     // work buffers
     c->coef.alloc(50 * N);
     c->dtc.alloc(N);

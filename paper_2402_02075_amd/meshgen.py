@@ -645,3 +645,129 @@ def cell_node_mean(m: Mesh) -> np.ndarray:
     s = np.zeros((m.n_cells, 3))
     np.add.at(s, idx, m.xyz[m.cnode])
     return s / cnt[:, None]
+
+
+# ---------------------------------------------------------------- cell averages of analytic fields
+_COLLAPSE = {4: [0, 1, 2, 2, 3, 3, 3, 3], 5: [0, 1, 2, 3, 4, 4, 4, 4], 6: [0, 1, 2, 2, 3, 4, 5, 5],
+             8: [0, 1, 2, 3, 4, 5, 6, 7]}
+
+
+def cell_quadrature(m: Mesh, q: int = 6):
+    """Quadrature points and weights of every cell: each element is mapped as a (collapsed)
+    trilinear hexahedron from the reference cube and integrated with q^3 Gauss points.
+    Returns (x (N, q^3, 3), w (N, q^3)); sum_k w[i, k] = |Omega_i| up to the rule's error."""
+    g, gw = np.polynomial.legendre.leggauss(q)
+    g = 0.5 * (g + 1.0)
+    gw = 0.5 * gw
+    r, s, t = np.meshgrid(g, g, g, indexing="ij")
+    r, s, t = r.ravel(), s.ravel(), t.ravel()
+    wref = np.einsum("i,j,k->ijk", gw, gw, gw).ravel()
+    # trilinear shape functions (hex node order 0..3 bottom, 4..7 top) and their derivatives
+    sh = np.stack([(1 - r) * (1 - s) * (1 - t), r * (1 - s) * (1 - t), r * s * (1 - t), (1 - r) * s * (1 - t),
+                   (1 - r) * (1 - s) * t, r * (1 - s) * t, r * s * t, (1 - r) * s * t], 1)
+    dr = np.stack([-(1 - s) * (1 - t), (1 - s) * (1 - t), s * (1 - t), -s * (1 - t),
+                   -(1 - s) * t, (1 - s) * t, s * t, -s * t], 1)
+    ds = np.stack([-(1 - r) * (1 - t), -r * (1 - t), r * (1 - t), (1 - r) * (1 - t),
+                   -(1 - r) * t, -r * t, r * t, (1 - r) * t], 1)
+    dt = np.stack([-(1 - r) * (1 - s), -r * (1 - s), -r * s, -(1 - r) * s,
+                   (1 - r) * (1 - s), r * (1 - s), r * s, (1 - r) * s], 1)
+    N = m.n_cells
+    nq = r.shape[0]
+    X = np.empty((N, nq, 3))
+    Wt = np.empty((N, nq))
+    for ct, col in _COLLAPSE.items():
+        sel = np.nonzero(m.ctype == ct)[0]
+        if sel.size == 0:
+            continue
+        nodes = m.cnode[m.cnode_ptr[sel][:, None] + np.array(col)[None, :]]
+        P = m.xyz[nodes]                                   # (n, 8, 3)
+        X[sel] = np.einsum("qa,nad->nqd", sh, P)
+        J = np.stack([np.einsum("qa,nad->nqd", dr, P), np.einsum("qa,nad->nqd", ds, P),
+                      np.einsum("qa,nad->nqd", dt, P)], -1)  # (n, q, 3, 3)
+        Wt[sel] = np.abs(np.linalg.det(J)) * wref[None, :]
+    return X, Wt
+
+
+def density_wave_cell_averages(m: Mesh, T: float = 0.0, u=(0.5, 0.3, 0.2), p=1.0, gamma=1.4, amp=0.2, q=6):
+    """Cell averages and averaged gradients of the density wave rho = 1 + amp sin2pi(x - u_x T)
+    sin2pi(y - u_y T) sin2pi(z - u_z T), velocity u, pressure p, on any mesh (quadrature of
+    `cell_quadrature`).  Returns (W (5, N), G (15, N)) as `density_wave_averages`."""
+    X, Wt = cell_quadrature(m, q)
+    vol = Wt.sum(1)
+    tp = 2.0 * np.pi
+    sx, sy, sz = (np.sin(tp * (X[..., d] - u[d] * T)) for d in range(3))
+    cx, cy, cz = (tp * np.cos(tp * (X[..., d] - u[d] * T)) for d in range(3))
+    avg = lambda f: (f * Wt).sum(1) / vol
+    rho = 1.0 + amp * avg(sx * sy * sz)
+    grad = amp * np.stack([avg(cx * sy * sz), avg(sx * cy * sz), avg(sx * sy * cz)])
+    N = m.n_cells
+    W = np.empty((5, N))
+    G = np.empty((15, N))
+    W[0] = rho
+    for d in range(3):
+        W[1 + d] = rho * u[d]
+    q2 = 0.5 * (u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+    W[4] = p / (gamma - 1.0) + q2 * rho
+    for d in range(3):
+        G[d] = grad[d]
+        for c in range(3):
+            G[3 * (1 + c) + d] = u[c] * grad[d]
+        G[12 + d] = q2 * grad[d]
+    return W, G
+
+
+# ---------------------------------------------------------------- sub-meshes (bounded samples)
+_FACES = {4: [(0, 1, 3), (1, 2, 3), (2, 0, 3), (0, 2, 1)],
+          5: [(0, 3, 2, 1), (0, 1, 4), (1, 2, 4), (2, 3, 4), (3, 0, 4)],
+          6: [(0, 2, 1), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (2, 0, 3, 5)],
+          8: [(0, 3, 2, 1), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7)]}
+
+
+def submesh(m: Mesh, cells, cut_tag: int = TAG_FARFIELD) -> Mesh:
+    """The mesh made of the listed cells (no periodic images): faces shared with a cell left out
+    become boundary faces with `cut_tag`; boundary faces of the kept cells keep their tags."""
+    assert m.node_canon is None
+    cells = np.unique(np.asarray(cells, np.int64))
+    bset = {}
+    for b in range(m.btag.shape[0]):
+        nodes = m.bnode[m.bnode_ptr[b]:m.bnode_ptr[b + 1]]
+        bset[tuple(sorted(nodes.tolist()))] = int(m.btag[b])
+    count, first = {}, {}
+    for c in cells:
+        nodes = m.cnode[m.cnode_ptr[c]:m.cnode_ptr[c + 1]]
+        for loc in _FACES[int(m.ctype[c])]:
+            f = tuple(int(nodes[k]) for k in loc)
+            key = tuple(sorted(f))
+            count[key] = count.get(key, 0) + 1
+            first.setdefault(key, f)
+    bfaces = []
+    for key, k in count.items():
+        if k == 1:
+            bfaces.append((first[key], bset.get(key, cut_tag)))
+    used = np.unique(np.concatenate([m.cnode[m.cnode_ptr[c]:m.cnode_ptr[c + 1]] for c in cells]))
+    new_id = -np.ones(m.n_nodes, np.int64)
+    new_id[used] = np.arange(used.shape[0])
+    ctype = m.ctype[cells].astype(np.uint8)
+    sizes = ctype.astype(np.int64)
+    ptr = np.zeros(cells.shape[0] + 1, np.int64)
+    ptr[1:] = np.cumsum(sizes)
+    cnode = np.concatenate([new_id[m.cnode[m.cnode_ptr[c]:m.cnode_ptr[c + 1]]] for c in cells])
+    bsz = np.array([len(f) for f, _ in bfaces], np.int64)
+    bptr = np.zeros(len(bfaces) + 1, np.int64)
+    bptr[1:] = np.cumsum(bsz)
+    bnode = new_id[np.array([n for f, _ in bfaces for n in f], np.int64)]
+    btag = np.array([t for _, t in bfaces], np.int32)
+    return Mesh(m.xyz[used].copy(), ctype, ptr, cnode, bptr, bnode, btag, None, name=f"{m.name}_sub{cells.shape[0]}",
+                info=dict(m.info, parent_cells=int(m.n_cells)))
+
+
+def permute_cells(m: Mesh, seed: int = 1) -> Mesh:
+    """The same mesh with its cells listed in a seeded random order (nodes and boundary faces
+    unchanged); `info["order"][k]` is the original id of the k-th cell."""
+    order = np.argsort(uniform01(seed, m.n_cells, stream=7), kind="stable")
+    sizes = (m.cnode_ptr[1:] - m.cnode_ptr[:-1])[order]
+    ptr = np.zeros(m.n_cells + 1, np.int64)
+    ptr[1:] = np.cumsum(sizes)
+    cnode = np.concatenate([m.cnode[m.cnode_ptr[c]:m.cnode_ptr[c + 1]] for c in order])
+    return Mesh(m.xyz, m.ctype[order].copy(), ptr, cnode, m.bnode_ptr, m.bnode, m.btag, m.node_canon,
+                name=f"{m.name}_shuffled{seed}", info=dict(m.info, order=order))

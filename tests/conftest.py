@@ -13,6 +13,16 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
 
 
+def pytest_collection_modifyitems(config, items):
+    # runs of many V-cycles on the CPU oracle take minutes: opt-in with CGKS_SLOW=1
+    if os.environ.get("CGKS_SLOW") == "1":
+        return
+    skip = pytest.mark.skip(reason="slow oracle run: set CGKS_SLOW=1")
+    for it in items:
+        if "slow" in it.keywords:
+            it.add_marker(skip)
+
+
 @pytest.fixture(scope="session")
 def oracle():
     import oracle as om
