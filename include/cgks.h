@@ -187,6 +187,22 @@ cgks_status cgks_step(cgks_ctx *ctx, double *W, double *G, double *alpha, double
 cgks_status cgks_check(cgks_ctx *ctx);
 
 /*
+ * cgks_residual without any device allocation, for callers that cannot allocate (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc).  Same arguments, outputs and
+ * kernels as cgks_residual; its work memory (local steps, polynomial coefficients, boundary ghost
+ * states, face records, and with params.cell_order = 1 the reordered inputs and outputs) comes from
+ * one fixed device array of 32 Mi doubles (256 MiB) per GPU, kept until the process ends, instead
+ * of the context's buffers.  It needs N + 50 N + 5 Fb + 21 F doubles (5 F without G_new), plus
+ * 42 N with cell_order 1, each rounded up to 32; a mesh that needs more returns CGKS_E_ARG before
+ * any work (about 230k mixed cells with cell_order 1, 330k with 0 or 2).  Nothing in the array
+ * needs clearing: every call writes all it reads.  All calls on one GPU share the array, from every
+ * context: calls that overlap on one GPU (other streams, other host threads) race and must be
+ * ordered by the caller.  The context's device must be the current device (CGKS_E_DEVICE).
+ */
+cgks_status cgks_residual_noalloc(cgks_ctx *ctx, const double *W, const double *G, const double *alpha, double *R,
+                                  double *G_new, double *alpha_new);
+
+/*
  * Force of the gas on the boundary faces carrying `tag` (the integrated surface force behind the
  * drag coefficients of paper Sec. 5): F[d] = sum over those faces of S_p sum_k w_k F_mom,d(x_pk),
  * the momentum part of the same time-averaged face flux as cgks_residual, normal pointing out of

@@ -23,7 +23,8 @@ EXPORTS = ["cgks_default_params", "cgks_create", "cgks_destroy", "cgks_last_erro
            "cgks_reconstruct", "cgks_residual", "cgks_step", "cgks_check", "cgks_residual_norm",
            "cgks_agglomerate_graph", "cgks_agglomerate", "cgks_level_map", "cgks_kfvs_residual", "cgks_restrict",
            "cgks_prolong", "cgks_vcycle", "cgks_timing", "cgks_wall_force", "cgks_linearize", "cgks_vjp_residual",
-           "cgks_vjp_wall_force", "cgks_vjp_kfvs", "cgks_adjoint_solve", "cgks_coarse_implicit", "cgks_cell_order"]
+           "cgks_vjp_wall_force", "cgks_vjp_kfvs", "cgks_adjoint_solve", "cgks_coarse_implicit", "cgks_cell_order",
+           "cgks_residual_noalloc"]
 
 
 class Params(C.Structure):
@@ -66,6 +67,7 @@ def lib():
             "cgks_vjp_residual": [P, P, P, P, P, P, P], "cgks_vjp_wall_force": [P, I32, P, P, P, P],
             "cgks_vjp_kfvs": [P, I32, P, P, P], "cgks_adjoint_solve": [P, I32, P, I32, D, P, P, P, P, P, P, P, P],
             "cgks_coarse_implicit": [P, I32, P, P, P], "cgks_cell_order": [P, P],
+            "cgks_residual_noalloc": [P, P, P, P, P, P, P],
         }
         for name, args in sig.items():
             if not hasattr(L, name):
@@ -207,6 +209,14 @@ class Solver:
         Gn = self.empty(15, N) if grad else None
         an = self.empty(N) if grad else None
         self._check(lib().cgks_residual(self.h, _ptr(W), _ptr(G), _ptr(alpha), _ptr(R), _ptr(Gn), _ptr(an)))
+        return R, Gn, an
+
+    def residual_noalloc(self, W, G, alpha=None, R=None, Gn=None, an=None):
+        """cgks_residual with the library's fixed work array (no device allocation in the library);
+        the outputs are the caller's tensors when given."""
+        N = self.n_cells
+        R = self.empty(5, N) if R is None else R
+        self._check(lib().cgks_residual_noalloc(self.h, _ptr(W), _ptr(G), _ptr(alpha), _ptr(R), _ptr(Gn), _ptr(an)))
         return R, Gn, an
 
     def step(self, W, G, alpha, dt_global=-1.0, resnorm=None):

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <parallel/algorithm>
 
 #include "common.hpp"
@@ -217,6 +218,31 @@ static std::vector<int32_t> locality_order(int64_t N, int64_t n_nodes, const dou
     return perm;
 }
 
+// ---------------------------------------------------------------- work memory without allocation
+// cgks_residual_noalloc takes its work memory (local steps, polynomial coefficients, boundary
+// ghost states, face records and, with cell_order 1, the reordered inputs and outputs) from this
+// file-scope device array instead of the context's buffers or hipMalloc.  Every GPU the library
+// runs on holds its own copy until the process ends.  Host code never passes the array's name to
+// a kernel: its device address is looked up once per device with hipGetSymbolAddress and kept.
+static constexpr size_t SCRATCH_DOUBLES = size_t(32) << 20;  // 32 Mi doubles = 256 MiB
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[256];
+
+static double *scratch_on_device(int device)
+{
+    if (device < 0 || device >= 256) throw Error{CGKS_E_DEVICE, "device ordinal out of range"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            throw Error{CGKS_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+        g_scratch_ptr[device] = static_cast<double *>(ptr);
+    }
+    return g_scratch_ptr[device];
+}
+
 static cgks_status vcycle_impl(cgks_ctx *c, double *W, double *G, double *alpha, int32_t max_cycles,
                                double tol_drop, double *hist, int32_t *n_done)
 {
@@ -380,6 +406,7 @@ cgks_status cgks_create(const cgks_params *p, cgks_ctx **out)
         hipDeviceProp_t prop;
         CGKS_HIP(hipGetDeviceProperties(&prop, c->device));
         c->gpu_cus = prop.multiProcessorCount;
+        c->scratch = scratch_on_device(c->device);
         CGKS_HIP(hipHostMalloc((void **)&c->pinned, 64 * sizeof(double), hipHostMallocDefault));
         CGKS_HIP(hipHostMalloc((void **)&c->pinned_i, 16 * sizeof(int32_t), hipHostMallocDefault));
         for (int t = 0; t < 64; ++t) {
@@ -562,6 +589,62 @@ cgks_status cgks_residual(cgks_ctx *c, const double *W, const double *G, const d
     cells_out(c, R, 5, 3);
     cells_out(c, G_new, 15, 4);
     cells_out(c, alpha_new, 1, 5);
+    CGKS_HIP(hipGetLastError());
+    API_END(c)
+}
+
+cgks_status cgks_residual_noalloc(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *R,
+                                  double *G_new, double *alpha_new)
+{
+    API_BEGIN(c)
+    need_bc(c);
+    if (!W || !G || !R || (G_new == nullptr) != (alpha_new == nullptr))
+        throw Error{CGKS_E_ARG, "W, G, R required; G_new and alpha_new both or neither"};
+    const int mode = G_new ? MODE_RES : MODE_RESONLY;
+    const bool moved = io_moved(c);
+    const int64_t N = c->N, F = c->F, Fb = c->F - c->Fi;
+    // carve the work array: every piece 256-byte aligned
+    auto up = [](int64_t n) { return (n + 31) / 32 * 32; };
+    const int64_t n_dt = up(N), n_coef = up(50 * N), n_bgq = up(5 * (Fb > 0 ? Fb : 1)),
+                  n_rec = up((mode == MODE_RES ? 21 : 5) * F), n_io = moved ? up(21 * N) : 0;
+    const int64_t need = n_dt + n_coef + n_bgq + n_rec + 2 * n_io;
+    if (need > (int64_t)SCRATCH_DOUBLES)
+        throw Error{CGKS_E_ARG, "mesh too large for cgks_residual_noalloc: it needs " + std::to_string(need) +
+                                    " doubles of work memory, the fixed array holds " +
+                                    std::to_string(SCRATCH_DOUBLES)};
+    if (c->device_now() != c->device) throw Error{CGKS_E_DEVICE, "the context's device is not the current device"};
+    double *p = c->scratch;
+    double *dtc = p, *coef = p + n_dt, *bgq = coef + n_coef, *rec = bgq + n_bgq, *in = rec + n_rec, *out = in + n_io;
+    const double *w = W, *g = G, *a = alpha;
+    double *r = R, *gn = G_new, *an = alpha_new;
+    if (moved) {
+        // reordered inputs and outputs: W, G, alpha and R, G_new, alpha_new (5 + 15 + 1 components)
+        auto gather = [&](const double *src, double *dst, int nc) {
+            hipLaunchKernelGGL(k_cells_in, dim3(blocks_for(N, 256), nc), dim3(256), 0, c->stream, N, c->perm.p, src,
+                               dst);
+        };
+        gather(W, in, 5);
+        gather(G, in + 5 * N, 15);
+        w = in;
+        g = in + 5 * N;
+        if (alpha) {
+            gather(alpha, in + 20 * N, 1);
+            a = in + 20 * N;
+        }
+        r = out;
+        gn = G_new ? out + 5 * N : nullptr;
+        an = alpha_new ? out + 20 * N : nullptr;
+    }
+    launch_local_dt_recon(c, w, g, a, dtc, coef, bgq);
+    launch_face(c, mode, coef, dtc, -1.0, c->prm.precision == 1, rec);
+    launch_gather_res(c, r, gn, an, mode, rec);
+    if (moved) {
+        cells_scatter(c, (const double *)out, R, 5);
+        if (G_new) {
+            cells_scatter(c, (const double *)(out + 5 * N), G_new, 15);
+            cells_scatter(c, (const double *)(out + 20 * N), alpha_new, 1);
+        }
+    }
     CGKS_HIP(hipGetLastError());
     API_END(c)
 }

@@ -197,6 +197,13 @@ struct cgks_ctx {
     cgks::DBuf<double> hist_dev;                // per-cycle residual norms of a batch of V-cycles
     cgks::DBuf<double> snapW, snapG, snapA;     // state at the start of the batch
     int32_t *pinned_i = nullptr;
+    // device address of the no-allocation entry point's work array on this context's device
+    double *scratch = nullptr;
+    int device_now() const
+    {
+        int d = -1;
+        return hipGetDevice(&d) == hipSuccess ? d : -1;
+    }
 
     ~cgks_ctx();
 };
@@ -210,14 +217,17 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_cells
 void launch_local_dt(cgks_ctx *c, const double *W, double *dt);
 // cell-major: coef[50 i + 10 c + k], else coef[(10 c + k) N + i]; ghosts_ready: the boundary
 // ghost states at W are already in bgq
+// bgq: where the boundary ghost states go (nullptr: the context's buffer)
 void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef,
-                  bool cell_major = true, bool ghosts_ready = false);
+                  bool cell_major = true, bool ghosts_ready = false, double *bgq = nullptr);
 // launch_local_dt + launch_recon (cell-major) with the ghost states formed in the local-step launch
 void launch_local_dt_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *dt,
-                           double *coef);
+                           double *coef, double *bgq = nullptr);
 enum FaceMode { MODE_RES = 0, MODE_RESONLY = 1, MODE_S1 = 2, MODE_S2 = 3 };
-void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cell, double dt_global, bool fp32);
-void launch_gather_res(cgks_ctx *c, double *R, double *Gn, double *an, int mode);
+// out: face records (nullptr: the context's buffer; a launch with its own buffer is never timed)
+void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cell, double dt_global, bool fp32,
+                 double *out = nullptr);
+void launch_gather_res(cgks_ctx *c, double *R, double *Gn, double *an, int mode, const double *fout = nullptr);
 void launch_gather_fe(cgks_ctx *c, double *W, double *G, double *alpha, const double *dt, double *Rout, double *norm_part);
 void launch_gather_s2o4(cgks_ctx *c, int stage, double dt, double *W, double *G, double *alpha);
 void launch_norm(cgks_ctx *c, const double *R, const double *vol, int64_t n, double *out);

@@ -729,18 +729,20 @@ void launch_local_dt(cgks_ctx *c, const double *W, double *dt)
 }
 
 void launch_local_dt_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *dt,
-                           double *coef)
+                           double *coef, double *bgq)
 {
     const int64_t Fb = c->F - c->Fi;
+    if (!bgq) bgq = c->bgq.p;
     hipLaunchKernelGGL(k_local_dt_ghost, dim3(blocks_for(c->N + Fb, 256)), dim3(256), 0, c->stream, c->N, c->F, c->Fi,
                        c->prm.gamma, c->prm.cfl, c->prm.mu, c->prm.viscous, W, c->cf_ptr.p, c->cf_face.p, c->favec.p,
-                       c->farea.p, c->vol.p, dt, c->fl.p, c->ftag.p, c->bc.p, c->bgq.p);
-    launch_recon(c, W, G, alpha, coef, true, true);
+                       c->farea.p, c->vol.p, dt, c->fl.p, c->ftag.p, c->bc.p, bgq);
+    launch_recon(c, W, G, alpha, coef, true, true, bgq);
 }
 
 void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef, bool cell_major,
-                  bool ghosts_ready)
+                  bool ghosts_ready, double *bgq)
 {
+    if (!bgq) bgq = c->bgq.p;
     ReconArgs A{};
     A.N = c->N;
     A.F = c->F;
@@ -768,16 +770,17 @@ void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *a
     A.nface = c->nface.p;
     A.Fi = c->Fi;
     A.Fb = c->F - c->Fi;
-    A.bgq = c->bgq.p;
+    A.bgq = bgq;
     if (A.Fb > 0 && !ghosts_ready)
         hipLaunchKernelGGL(k_bnd_ghost, dim3(blocks_for(A.Fb, 256)), dim3(256), 0, c->stream, c->N, c->F, c->Fi, W,
-                           c->fl.p, c->ftag.p, c->favec.p, c->bc.p, c->prm.gamma, c->bgq.p);
+                           c->fl.p, c->ftag.p, c->favec.p, c->bc.p, c->prm.gamma, bgq);
     const dim3 grid(blocks_for(c->N, OP_GROUP)), blk(5 * OP_GROUP);
     if (cell_major) hipLaunchKernelGGL((k_recon<true>), grid, blk, 0, c->stream, A);
     else hipLaunchKernelGGL((k_recon<false>), grid, blk, 0, c->stream, A);
 }
 
-void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cell, double dt_global, bool fp32)
+void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cell, double dt_global, bool fp32,
+                 double *out)
 {
     FaceArgs A;
     A.N = c->N;
@@ -790,11 +793,11 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
     A.lgeo = c->lgeo.p;
     A.NL = c->NL;
     A.bc = c->bc.p;
-    A.out = c->fout.p;
+    A.out = out ? out : c->fout.p;
     A.bad = c->bad.p;
     const dim3 grid(blocks_for(c->NL, 256)), blk(256);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool timed = c->timing && mode == MODE_RES;
+    const bool timed = c->timing && mode == MODE_RES && !out;
     if (timed) {
         while (c->ev_pool.size() < c->ev_used + 2) {
             hipEvent_t e;
@@ -837,14 +840,14 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
     if (timed) CGKS_HIP(hipEventRecord(e1, c->stream));
 }
 
-static GatherArgs gargs(cgks_ctx *c)
+static GatherArgs gargs(cgks_ctx *c, const double *fout = nullptr)
 {
     GatherArgs g;
     g.N = c->N;
     g.F = c->F;
     g.cf_ptr = c->cf_ptr.p;
     g.cf_face = c->cf_face.p;
-    g.fout = c->fout.p;
+    g.fout = fout ? fout : c->fout.p;
     g.vol = c->vol.p;
     return g;
 }
@@ -852,14 +855,15 @@ static GatherArgs gargs(cgks_ctx *c)
 int norm_blocks(int64_t n) { return blocks_for(n, 256); }
 int gather_blocks(int64_t n) { return blocks_for(CG * n, 256); }
 
-void launch_gather_res(cgks_ctx *c, double *R, double *Gn, double *an, int mode)
+void launch_gather_res(cgks_ctx *c, double *R, double *Gn, double *an, int mode, const double *fout)
 {
     const dim3 grid(blocks_for(CG * c->N, 256)), blk(256);
     if (mode == MODE_RES)
-        hipLaunchKernelGGL((k_gather<false, true>), grid, blk, 0, c->stream, gargs(c), R, Gn, an, nullptr, nullptr, nullptr);
+        hipLaunchKernelGGL((k_gather<false, true>), grid, blk, 0, c->stream, gargs(c, fout), R, Gn, an, nullptr, nullptr,
+                           nullptr);
     else
-        hipLaunchKernelGGL((k_gather<false, false>), grid, blk, 0, c->stream, gargs(c), R, nullptr, nullptr, nullptr,
-                           nullptr, nullptr);
+        hipLaunchKernelGGL((k_gather<false, false>), grid, blk, 0, c->stream, gargs(c, fout), R, nullptr, nullptr,
+                           nullptr, nullptr, nullptr);
 }
 
 void launch_gather_fe(cgks_ctx *c, double *W, double *G, double *alpha, const double *dt, double *Rout, double *part)

@@ -1,0 +1,81 @@
+"""The no-allocation residual entry point against cgks_residual (GPU).
+
+cgks_residual_noalloc runs the same kernels as cgks_residual with its work memory in the
+library's fixed device array instead of the context's buffers: its outputs must be bit-identical,
+on two calls in a row where the second has a smaller mesh (the array keeps the first call's
+contents), in both cell-order modes at the ABI and with and without the gradient update; a mesh
+whose work memory exceeds the array is rejected before any work.
+"""
+import numpy as np
+import pytest
+
+from paper_2402_02075_amd import meshgen as mg
+
+from gpu_common import channel_bcs, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def cg(torch):
+    from paper_2402_02075_amd import cgks
+    return cgks
+
+
+def _case(cg, torch, m, order, seed):
+    S = cg.Solver(cell_order=order)
+    S.set_mesh(m)
+    channel_bcs(S.set_bc, cg.BC_FARFIELD, cg.BC_SLIP)
+    x = mg.cell_node_mean(m)
+    W = mg.random_smooth_state(x, seed=seed, amp=0.06)
+    rng = np.random.default_rng(seed)
+    G = rng.normal(size=(15, m.n_cells)) * 0.1
+    al = rng.uniform(0.7, 1.0, size=m.n_cells)
+    return S, to_dev(torch, W), to_dev(torch, G), to_dev(torch, al)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_noalloc_residual_equals_residual(cg, torch, order):
+    big = mg.bump_channel(20, 10, 6, n_prism=2, n_pyr=3, jitter=0.05, seed=2, amp=0.05)
+    small = mg.bump_channel(12, 4, 2, n_prism=1, n_pyr=1, jitter=0.05, seed=3, amp=0.05)
+    for m, seed in ((big, 1), (small, 2)):
+        say(f"[gpu] no-allocation residual, cell_order {order}, {m.n_cells} cells")
+        S, W, G, al = _case(cg, torch, m, order, seed)
+        N = m.n_cells
+        R, Gn, an = S.residual(W, G, al)
+        R2, Gn2, an2 = S.residual_noalloc(W, G, al, Gn=S.empty(15, N), an=S.empty(N))
+        S.check()
+        torch.cuda.synchronize()
+        assert torch.equal(R, R2) and torch.equal(Gn, Gn2) and torch.equal(an, an2)
+        Ro, _, _ = S.residual(W, G, al, grad=False)
+        Ro2, _, _ = S.residual_noalloc(W, G, al)
+        torch.cuda.synchronize()
+        assert torch.equal(Ro, Ro2)
+        S.close()
+
+
+def test_noalloc_rejects_a_mesh_beyond_the_array(cg, torch):
+    m = mg.sphere_shell(level=4, n_layers=32, n_prism=12)
+    say(f"[gpu] no-allocation residual on {m.n_cells} cells: must be rejected")
+    S = cg.Solver(viscous=1, mu=2e-3, prandtl=0.72)
+    S.set_mesh(m)
+    S.set_bc(mg.TAG_SPHERE, cg.BC_NOSLIP_ADIABATIC)
+    S.set_bc(mg.TAG_FARFIELD, cg.BC_FARFIELD, np.array([1.0, 0.2, 0.0, 0.0, 1.0 / 1.4]))
+    W0, G0 = mg.uniform_state(m.n_cells, vel=(0.2, 0.0, 0.0))
+    W, G = to_dev(torch, W0), to_dev(torch, G0)
+    R = S.empty(5, m.n_cells)
+    R.fill_(7.0)
+    with pytest.raises(cg.CgksError) as e:
+        S.residual_noalloc(W, G, None, R=R)
+    assert e.value.code == cg.E_ARG and "too large" in str(e.value)
+    torch.cuda.synchronize()
+    assert bool((R == 7.0).all())   # nothing written
+    S.close()
