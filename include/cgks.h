@@ -251,6 +251,19 @@ cgks_status cgks_vjp_wall_force(cgks_ctx *ctx, int32_t tag, const double *e, dou
 cgks_status cgks_vjp_kfvs(cgks_ctx *ctx, int32_t level, const double *Wc, const double *barRc, double *barWc);
 
 /*
+ * Parameter directions for the gradients of cgks_adjoint_solve (the inflow Mach number and a shape
+ * parameter of the spec adjoint workload, or any other scalar parameters).  Parameter k
+ * moves, per unit, the far-field primitives (rho, u, v, w, p) of boundary tag t by
+ * dprim[(k * 64 + t) * 5 + q] (host, nullable = no change) and node j of the mesh (caller's node
+ * numbering) by dxyz[k * 3 n_nodes + 3 j + d] (host, nullable = no node moves); n_params <= 8.
+ * step: the parameter step h of the differences of the explicit dependence (see
+ * cgks_adjoint_solve; 1e-6 suits parameters of order one: the operator has kinks (|p_l - p_r| of
+ * the collision time, min of the smoothness indicators) that a larger step may straddle).  Copied; cleared by cgks_set_mesh.  CGKS_E_STATE without a mesh.
+ */
+cgks_status cgks_set_param_directions(cgks_ctx *ctx, int32_t n_params, const double *dprim, const double *dxyz,
+                                      double step);
+
+/*
  * Adjoint fixed point of the V-cycle (cgks_vcycle, FP64, one pre-sweep per level,
  * no post-sweeps) at the linearised state, which must be converged:
  *   lam = (dPhi/dU)^T lam + dJ/dU,  J = e . F_wall(tag),  U = (W, G, alpha),
@@ -258,12 +271,17 @@ cgks_status cgks_vjp_kfvs(cgks_ctx *ctx, int32_t level, const double *Wc, const 
  * (each nullable): lamW[5N], lamG[15N], lamA[N]; and the cotangents cR[5N], cG[15N],
  * cA[N] on the fine operator's outputs (R, G_new, alpha_new) with which a parameter
  * p enters: dJ/dp = dJ/dp|_U + cR . dR/dp + cG . dG_new/dp + cA . dalpha_new/dp.
+ * dJ_dparams (host, nullable, one per direction of cgks_set_param_directions) receives that
+ * gradient for every parameter: the library rebuilds the geometry, reconstruction operators and
+ * boundary states at p = +-h, +-2h (same cells and faces), evaluates J and E at the fixed state,
+ * and forms dJ/dp|_U and c . dE/dp|_U by the fourth-order central difference
+ * (8 (f(h) - f(-h)) - (f(2h) - f(-2h))) / 12h (truncation O(h^4), rounding O(eps/h)).
  * hist (host, nullable, max_iter doubles) receives the relative change per iteration;
  * n_done (host) the iterations run.  Synchronises once per iteration.
  */
 cgks_status cgks_adjoint_solve(cgks_ctx *ctx, int32_t tag, const double *e, int32_t max_iter, double tol,
                                double *lamW, double *lamG, double *lamA, double *cR, double *cG, double *cA,
-                               double *hist, int32_t *n_done);
+                               double *hist, int32_t *n_done, double *dJ_dparams);
 
 /* RMS of R_rho/|Omega| (device R in, device scalar out). */
 cgks_status cgks_residual_norm(cgks_ctx *ctx, const double *R, double *out);

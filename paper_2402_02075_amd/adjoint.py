@@ -4,16 +4,12 @@
   alpha_new) as a ``torch.autograd.Function``; forward is ``cgks_residual``,
   backward linearises at the forward state and applies ``cgks_vjp_residual``.
 * ``gradients``: sensitivities of the wall force with respect to the inflow
-  Mach number and the bump amplitude at a converged state, from the adjoint
-  fixed point (``cgks_adjoint_solve``) plus the explicit dependence of the
-  operator and of the objective on the parameter at the fixed state.
-
-The explicit parameter partials are central differences of the operator and of
-the objective evaluated at the *fixed* converged state (one residual evaluation
-per side); the state sensitivity, which carries the converged solution's
-response, comes entirely from the adjoint.  The bump parameter displaces the
-mesh by linear blending in y: y' = y_0 + A exp(-25 (x - 1.5)^2) (1 - y_0) with
-y_0 the unbumped node height, so meshes at A +- h share their topology.
+  Mach number and the bump amplitude at a converged state, from the library's
+  adjoint solve (``cgks_adjoint_solve`` with the parameter directions of
+  ``cgks_set_param_directions``); this module only describes the two
+  parameters: the far-field velocity of the inlet and outlet tags (Mach), and
+  the node displacement of the bump blending y' = y_0 + A exp(-25 (x - 1.5)^2)
+  (1 - y_0), y_0 the unbumped node height.
 """
 from __future__ import annotations
 
@@ -56,27 +52,6 @@ def residual(solver, W, G, alpha):
     return ResidualFunction.apply(W, G, alpha, solver)
 
 
-def _operator(S, W, G, al):
-    R, Gn, an = S.residual(W, G, al, grad=True)
-    return R, Gn, an
-
-
-def _dot(cots, outs):
-    return float(sum((c * o).sum() for c, o in zip(cots, outs)))
-
-
-def explicit_partials(S_plus, S_minus, W, G, al, cots, tag, e, h):
-    """Central differences at the fixed state of J and of cots . E with respect to one parameter."""
-    torch = _torch()
-    Jp = float(torch.dot(S_plus.wall_force(W, G, al, tag), torch.tensor(e, dtype=torch.float64, device=W.device)))
-    Jm = float(torch.dot(S_minus.wall_force(W, G, al, tag), torch.tensor(e, dtype=torch.float64, device=W.device)))
-    Ep = _operator(S_plus, W, G, al)
-    Em = _operator(S_minus, W, G, al)
-    dJ = (Jp - Jm) / (2 * h)
-    dE = (_dot(cots, Ep) - _dot(cots, Em)) / (2 * h)
-    return dJ, dE
-
-
 def channel_solver(m, mach, gamma=1.4, agglomerate=True, **par):
     """Library solver on a bump-channel mesh with far field of Mach `mach` and slip walls."""
     S = cg.Solver(**par)
@@ -92,32 +67,37 @@ def channel_solver(m, mach, gamma=1.4, agglomerate=True, **par):
     return S
 
 
-def gradients(mesh_fn, amp, mach, W, G, al, tag=mg.TAG_WALL_BOTTOM, e=(1.0, 0.0, 0.0), h=1e-5, max_iter=40000,
-              tol=1e-11, **par):
-    """dJ/dMach and dJ/dA at the converged state (W, G, al) of mesh_fn(amp) at `mach`.
+def bump_direction(mesh_fn, amp, delta=0.01):
+    """Node displacement per unit bump amplitude: the generator places every node affinely in the
+    amplitude (grid nodes by the blending y' = y0 + A b(x) (1 - y0), pyramid centres as means of
+    blended corners), so the difference of its meshes at amp +- delta is exact up to rounding."""
+    return (mesh_fn(amp + delta).xyz - mesh_fn(amp - delta).xyz) / (2.0 * delta)
 
-    mesh_fn(a) builds the mesh at bump amplitude a (same topology for every a).
-    Returns a dict with the two gradients, the adjoint iteration count and history.
-    """
-    S = channel_solver(mesh_fn(amp), mach, **par)
+
+def mach_direction(gamma=1.4):
+    """Far-field primitive change per unit Mach number (rho = 1 and p = 1/gamma fixed, so the sound
+    speed is 1 and u = Mach) on the inlet and outlet tags."""
+    d = np.zeros((64, 5))
+    for tag in (mg.TAG_INLET, mg.TAG_OUTLET):
+        d[tag, 1] = 1.0
+    return d
+
+
+def gradients(S, mesh_fn, amp, mach, W, G, al, tag=mg.TAG_WALL_BOTTOM, e=(1.0, 0.0, 0.0), max_iter=40000,
+              tol=1e-11, step=1e-6):
+    """dJ/dMach and dJ/dA at the converged state (W, G, al) of the bump channel mesh_fn(amp)
+    at `mach`, from the library's adjoint solve with two parameter directions: the far-field
+    velocity of the inlet and outlet tags, and the bump blending of the mesh nodes.
+    Returns a dict with the two gradients, the adjoint iteration count and history."""
+    dprim = np.stack([mach_direction(), np.zeros((64, 5))])
+    d = bump_direction(mesh_fn, amp)
+    dxyz = np.stack([np.zeros_like(d), d])
+    S.set_param_directions(dprim, dxyz, step)
     S.linearize(W, G, al)
     adj = S.adjoint_solve(tag, e, max_iter=max_iter, tol=tol)
-    cots = (adj["cR"], adj["cG"], adj["cA"])
-    out = {"adjoint_iterations": adj["iterations"], "adjoint_final_change": float(adj["hist"][-1])}
-    # Mach: far-field state at M +- h on unagglomerated solvers (the coarse levels do not enter)
-    Sp = channel_solver(mesh_fn(amp), mach + h, agglomerate=False, **par)
-    Sm = channel_solver(mesh_fn(amp), mach - h, agglomerate=False, **par)
-    dJ, dE = explicit_partials(Sp, Sm, W, G, al, cots, tag, e, h)
-    out["dJ_dMach"] = dJ + dE
-    out["dJ_dMach_explicit"] = dJ
-    # bump amplitude: meshes at A +- h
-    Sp = channel_solver(mesh_fn(amp + h), mach, agglomerate=False, **par)
-    Sm = channel_solver(mesh_fn(amp - h), mach, agglomerate=False, **par)
-    dJ, dE = explicit_partials(Sp, Sm, W, G, al, cots, tag, e, h)
-    out["dJ_dA"] = dJ + dE
-    out["dJ_dA_explicit"] = dJ
-    out["hist"] = adj["hist"]
-    return out
+    return {"dJ_dMach": float(adj["dJ_dparams"][0]), "dJ_dA": float(adj["dJ_dparams"][1]),
+            "adjoint_iterations": adj["iterations"], "adjoint_final_change": float(adj["hist"][-1]),
+            "hist": adj["hist"]}
 
 
 def converge(S, m, W=None, G=None, al=None, cycles=40000, tol=1e-13):

@@ -24,7 +24,7 @@ EXPORTS = ["cgks_default_params", "cgks_create", "cgks_destroy", "cgks_last_erro
            "cgks_agglomerate_graph", "cgks_agglomerate", "cgks_level_map", "cgks_kfvs_residual", "cgks_restrict",
            "cgks_prolong", "cgks_vcycle", "cgks_timing", "cgks_wall_force", "cgks_linearize", "cgks_vjp_residual",
            "cgks_vjp_wall_force", "cgks_vjp_kfvs", "cgks_adjoint_solve", "cgks_coarse_implicit", "cgks_cell_order",
-           "cgks_residual_noalloc"]
+           "cgks_residual_noalloc", "cgks_set_param_directions"]
 
 
 class Params(C.Structure):
@@ -65,7 +65,8 @@ def lib():
             "cgks_vcycle": [P, P, P, P, I32, D, P, P], "cgks_timing": [P, I32, P, P],
             "cgks_wall_force": [P, P, P, P, I32, P], "cgks_linearize": [P, P, P, P],
             "cgks_vjp_residual": [P, P, P, P, P, P, P], "cgks_vjp_wall_force": [P, I32, P, P, P, P],
-            "cgks_vjp_kfvs": [P, I32, P, P, P], "cgks_adjoint_solve": [P, I32, P, I32, D, P, P, P, P, P, P, P, P],
+            "cgks_vjp_kfvs": [P, I32, P, P, P], "cgks_adjoint_solve": [P, I32, P, I32, D, P, P, P, P, P, P, P, P, P],
+            "cgks_set_param_directions": [P, I32, P, P, D],
             "cgks_coarse_implicit": [P, I32, P, P, P], "cgks_cell_order": [P, P],
             "cgks_residual_noalloc": [P, P, P, P, P, P, P],
         }
@@ -156,6 +157,7 @@ class Solver:
 
     # ---------------------------------------------------------------- mesh
     def set_mesh(self, m):
+        self._n_params = 0
         keep = [_np(m.xyz, np.float64), _np(m.ctype, np.uint8), _np(m.cnode_ptr, np.int64), _np(m.cnode, np.int64),
                 _np(m.bnode_ptr, np.int64), _np(m.bnode, np.int64), _np(m.btag, np.int32),
                 None if m.node_canon is None else _np(m.node_canon, np.int64)]
@@ -262,22 +264,43 @@ class Solver:
         self._check(lib().cgks_vjp_kfvs(self.h, C.c_int32(int(level)), _ptr(Wc), _ptr(barRc), _ptr(out)))
         return out
 
+    def set_param_directions(self, dprim=None, dxyz=None, step=1e-6):
+        """Parameter directions of the adjoint gradients: dprim (n, 64, 5) far-field primitive
+        derivatives per tag, dxyz (n, n_nodes, 3) node displacements per unit parameter."""
+        n = None
+        for a in (dprim, dxyz):
+            if a is not None:
+                n = a.shape[0] if n is None else n
+                if a.shape[0] != n:
+                    raise ValueError("dprim and dxyz must describe the same number of parameters")
+        n = n or 0
+        dp = None if dprim is None else _np(dprim, np.float64).reshape(n, 64, 5)
+        dx = None if dxyz is None else _np(dxyz, np.float64).reshape(n, -1, 3)
+        self._n_params = n
+        self._check(lib().cgks_set_param_directions(self.h, C.c_int32(n),
+                                                    None if dp is None else dp.ctypes.data_as(C.c_void_p),
+                                                    None if dx is None else dx.ctypes.data_as(C.c_void_p),
+                                                    float(step)))
+
     def adjoint_solve(self, tag, e=(1.0, 0.0, 0.0), max_iter=20000, tol=1e-10):
         """Adjoint fixed point through the transposed V-cycle at the linearised (converged) state.
 
-        Returns dict with lamW, lamG, lamA, cR, cG, cA (device tensors), hist (numpy) and iterations."""
+        Returns dict with lamW, lamG, lamA, cR, cG, cA (device tensors), hist (numpy), iterations
+        and dJ_dparams (numpy, one per direction of set_param_directions)."""
         N = self.n_cells
         out = {k: self.empty(*s) for k, s in (("lamW", (5, N)), ("lamG", (15, N)), ("lamA", (N,)), ("cR", (5, N)),
                                                 ("cG", (15, N)), ("cA", (N,)))}
         hist = np.zeros(int(max_iter))
         nd = C.c_int32(0)
         ev = (C.c_double * 3)(*[float(x) for x in e])
+        dj = np.zeros(max(getattr(self, "_n_params", 0), 1))
         self._check(lib().cgks_adjoint_solve(self.h, C.c_int32(int(tag)), ev, C.c_int32(int(max_iter)), float(tol),
                                              _ptr(out["lamW"]), _ptr(out["lamG"]), _ptr(out["lamA"]), _ptr(out["cR"]),
                                              _ptr(out["cG"]), _ptr(out["cA"]), hist.ctypes.data_as(C.c_void_p),
-                                             C.byref(nd)))
+                                             C.byref(nd), dj.ctypes.data_as(C.c_void_p)))
         out["hist"] = hist[:nd.value]
         out["iterations"] = nd.value
+        out["dJ_dparams"] = dj[:getattr(self, "_n_params", 0)]
         return out
 
     # ---------------------------------------------------------------- multigrid

@@ -32,6 +32,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <memory>
+
 #include "common.hpp"
 #include "gks_device.hpp"
 #include "dual.hpp"
@@ -1034,6 +1036,102 @@ int adj_solve(cgks_ctx *c, int32_t tag, const double e[3], int max_iter, double 
     if (cA) CGKS_HIP(hipMemcpyAsync(cA, l1A, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     CGKS_HIP(hipStreamSynchronize(st));
     return it;
+}
+
+// ---------------------------------------------------------------- parameter sensitivities
+// sum over blocks of a . b, one partial per block (fixed grid: the sum is deterministic)
+__global__ __launch_bounds__(256) void k_dot_part(int64_t n, const double *a, const double *b, double *part)
+{
+    __shared__ double sh[256];
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v += a[i] * b[i];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Explicit dependence on the parameters at the fixed (linearised) state.  A parameter p_k moves the
+// far-field states of the boundary tags and the mesh nodes along the directions given to
+// cgks_set_param_directions; J = e . F_wall(tag) and E = (R, G_new, alpha_new) change with it at
+// fixed (W, G, alpha) through the ghost states, the geometry, the reconstruction operators and the
+// local steps.  Both are evaluated on a context rebuilt at p_k = +-h, +-2h (same cells, same
+// internal order) and differentiated by the fourth-order central difference
+// f' = (8 (f(h) - f(-h)) - (f(2h) - f(-2h))) / (12 h); with the adjoint's cotangents c on E,
+// dJ/dp_k = dJ/dp_k|_U + c . dE/dp_k|_U.
+void adj_param_derivatives(cgks_ctx *c, int32_t tag, const double e[3], double *out)
+{
+    AdjTape &T = tape(c);
+    hipStream_t st = c->stream;
+    const int64_t N = c->N;
+    const auto &H = c->hmesh;
+    const double *cRp = T.cR.p, *cGp = T.lam1.p + 5 * N, *cAp = T.lam1.p + 20 * N;
+    const int nbk = 256;
+    DBuf<double> part, R, Gn, an, Fw;
+    part.alloc(3 * nbk);
+    R.alloc(5 * N);
+    Gn.alloc(15 * N);
+    an.alloc(N);
+    Fw.alloc(3);
+    std::vector<double> hp(3 * nbk);
+    const double h = c->param_step;
+    const double steps[4] = {-2.0 * h, -h, h, 2.0 * h};
+    for (int k = 0; k < c->n_params; ++k) {
+        double fE[4], fJ[4];
+        for (int q = 0; q < 4; ++q) {
+            const double sk = steps[q];
+            std::unique_ptr<cgks_ctx> X(new cgks_ctx());
+            X->prm = c->prm;
+            X->prm.cell_order = 0;
+            X->stream = st;
+            X->device = c->device;
+            X->gpu_cus = c->gpu_cus;
+            X->bc_host = c->bc_host;
+            X->tags_set = c->tags_set;
+            for (int t = 0; t < 64; ++t)
+                for (int v = 0; v < 5; ++v) X->bc_host.prim[t][v] += sk * c->pdir_prim[((size_t)k * 64 + t) * 5 + v];
+            X->bc.alloc(1);
+            CGKS_HIP(hipMemcpyAsync(X->bc.p, &X->bc_host, sizeof(BcTable), hipMemcpyHostToDevice, st));
+            std::vector<double> xyz = H.xyz;
+            if (!c->pdir_xyz.empty()) {
+                const double *d = c->pdir_xyz.data() + (size_t)k * 3 * H.n_nodes;
+                for (size_t j = 0; j < xyz.size(); ++j) xyz[j] += sk * d[j];
+            }
+            mesh_build(X.get(), H.n_nodes, xyz.data(), N, H.ct.data(), H.cp.data(), H.cn.data(), H.n_bf,
+                       H.bp.empty() ? nullptr : H.bp.data(), H.bn.empty() ? nullptr : H.bn.data(),
+                       H.bt.empty() ? nullptr : H.bt.data(), H.canon.empty() ? nullptr : H.canon.data());
+            if (X->F != c->F) throw Error{CGKS_E_MESH, "a parameter step changed the mesh topology"};
+            launch_local_dt_recon(X.get(), T.W.p, T.G.p, T.al.p, X->dtc.p, X->coef.p);
+            launch_face(X.get(), MODE_RES, X->coef.p, X->dtc.p, -1.0, false);
+            launch_gather_res(X.get(), R.p, Gn.p, an.p, MODE_RES);
+            launch_face(X.get(), MODE_RESONLY, X->coef.p, X->dtc.p, -1.0, false);
+            launch_wall_force(X.get(), tag, Fw.p);
+            hipLaunchKernelGGL(k_dot_part, dim3(nbk), dim3(256), 0, st, 5 * N, cRp, R.p, part.p);
+            hipLaunchKernelGGL(k_dot_part, dim3(nbk), dim3(256), 0, st, 15 * N, cGp, Gn.p, part.p + nbk);
+            hipLaunchKernelGGL(k_dot_part, dim3(nbk), dim3(256), 0, st, N, cAp, an.p, part.p + 2 * nbk);
+            CGKS_HIP(hipGetLastError());
+            double hF[3];
+            CGKS_HIP(hipMemcpyAsync(hp.data(), part.p, sizeof(double) * 3 * nbk, hipMemcpyDeviceToHost, st));
+            CGKS_HIP(hipMemcpyAsync(hF, Fw.p, sizeof(hF), hipMemcpyDeviceToHost, st));
+            CGKS_HIP(hipStreamSynchronize(st));
+            int32_t hb = 0;
+            CGKS_HIP(hipMemcpy(&hb, X->bad.p, sizeof(int32_t), hipMemcpyDeviceToHost));
+            if (hb != INT32_MAX)
+                throw Error{CGKS_E_PHYS, "non-physical Gauss-point state at a parameter step, cell " +
+                                             std::to_string(c->caller_cell(hb))};
+            double acc = 0.0;
+            for (int b = 0; b < 3 * nbk; ++b) acc += hp[b];
+            fE[q] = acc;
+            fJ[q] = e[0] * hF[0] + e[1] * hF[1] + e[2] * hF[2];
+        }
+        const double dE = (8.0 * (fE[2] - fE[1]) - (fE[3] - fE[0])) / (12.0 * h);
+        const double dJ = (8.0 * (fJ[2] - fJ[1]) - (fJ[3] - fJ[0])) / (12.0 * h);
+        out[k] = dJ + dE;
+    }
 }
 
 }  // namespace cgks

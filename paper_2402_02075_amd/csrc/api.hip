@@ -491,6 +491,30 @@ cgks_status cgks_set_mesh(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64
     }
     c->perm.upload(c->permuted ? c->perm_h : std::vector<int32_t>(), c->stream);
     CGKS_HIP(hipStreamSynchronize(c->stream));
+    // host copy of the mesh in the internal order (parameter sensitivities rebuild its geometry)
+    {
+        auto &H = c->hmesh;
+        H.n_nodes = n_nodes;
+        H.n_bf = n_bfaces;
+        H.xyz.assign(xyz, xyz + 3 * n_nodes);
+        H.ct.resize(n_cells);
+        H.cp.assign(n_cells + 1, 0);
+        H.cn.resize(cnode_ptr[n_cells]);
+        for (int64_t i = 0; i < n_cells; ++i) {
+            const int64_t o = c->caller_cell(i);
+            H.ct[i] = ctype[o];
+            H.cp[i + 1] = H.cp[i] + (cnode_ptr[o + 1] - cnode_ptr[o]);
+            std::copy(cnode + cnode_ptr[o], cnode + cnode_ptr[o + 1], H.cn.begin() + H.cp[i]);
+        }
+        H.bp.assign(bnode_ptr ? bnode_ptr : nullptr, bnode_ptr ? bnode_ptr + n_bfaces + 1 : nullptr);
+        H.bn.assign(bnode, bnode ? bnode + (n_bfaces ? bnode_ptr[n_bfaces] : 0) : nullptr);
+        H.bt.assign(btag, btag ? btag + n_bfaces : nullptr);
+        if (node_canon) H.canon.assign(node_canon, node_canon + n_nodes);
+        else H.canon.clear();
+    }
+    c->n_params = 0;
+    c->pdir_prim.clear();
+    c->pdir_xyz.clear();
     API_END(c)
 }
 
@@ -712,9 +736,25 @@ cgks_status cgks_vjp_kfvs(cgks_ctx *c, int32_t level, const double *Wc, const do
     API_END(c)
 }
 
+cgks_status cgks_set_param_directions(cgks_ctx *c, int32_t n_params, const double *dprim, const double *dxyz,
+                                      double step)
+{
+    API_BEGIN(c)
+    need_mesh(c);
+    if (n_params < 0 || n_params > 8) throw Error{CGKS_E_ARG, "n_params must be in 0..8"};
+    if (n_params > 0 && !(step > 0.0)) throw Error{CGKS_E_ARG, "step must be positive"};
+    c->n_params = n_params;
+    c->param_step = step;
+    c->pdir_prim.assign((size_t)n_params * 64 * 5, 0.0);
+    if (dprim) std::copy(dprim, dprim + (size_t)n_params * 64 * 5, c->pdir_prim.begin());
+    c->pdir_xyz.clear();
+    if (dxyz) c->pdir_xyz.assign(dxyz, dxyz + (size_t)n_params * 3 * c->hmesh.n_nodes);
+    API_END(c)
+}
+
 cgks_status cgks_adjoint_solve(cgks_ctx *c, int32_t tag, const double *e, int32_t max_iter, double tol,
                                double *lamW, double *lamG, double *lamA, double *cR, double *cG, double *cA,
-                               double *hist, int32_t *n_done)
+                               double *hist, int32_t *n_done, double *dJ_dparams)
 {
     API_BEGIN(c)
     need_bc(c);
@@ -729,6 +769,7 @@ cgks_status cgks_adjoint_solve(cgks_ctx *c, int32_t tag, const double *e, int32_
     cells_out(c, cR, 5, 3);
     cells_out(c, cG, 15, 4);
     cells_out(c, cA, 1, 5);
+    if (dJ_dparams && c->n_params > 0) adj_param_derivatives(c, tag, e, dJ_dparams);
     API_END(c)
 }
 

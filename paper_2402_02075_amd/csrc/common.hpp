@@ -153,6 +153,22 @@ struct cgks_ctx {
         return permuted && i >= 0 && i < (int64_t)perm_h.size() ? perm_h[i] : i;
     }
 
+    // Host copy of the mesh as built (cells in the internal order), kept for the parameter
+    // sensitivities of the adjoint, which rebuild the geometry at displaced nodes.
+    struct HostMesh {
+        int64_t n_nodes = 0, n_bf = 0;
+        std::vector<double> xyz;
+        std::vector<uint8_t> ct;
+        std::vector<int64_t> cp, cn, bp, bn, canon;
+        std::vector<int32_t> bt;
+    } hmesh;
+    // parameter directions of the adjoint (cgks_set_param_directions): per parameter the derivative
+    // of every tag's far-field primitives and of every node's coordinates
+    int32_t n_params = 0;
+    double param_step = 1e-6;
+    std::vector<double> pdir_prim;  // [n_params][64][5]
+    std::vector<double> pdir_xyz;   // [n_params][3 n_nodes]; empty when no parameter moves the nodes
+
     // fine geometry (internal cell order)
     cgks::DBuf<double> vol, cen, mom2;  // [N], [3][N], [6][N]
     cgks::DBuf<int32_t> fl, fr, ftag;   // [F]
@@ -266,6 +282,8 @@ void adj_vjp_wall(cgks_ctx *c, int32_t tag, const double e[3], double *oW, doubl
 void adj_vjp_kfvs(cgks_ctx *c, int level, const double *Wc, const double *bR, double *oW, bool accumulate);
 int adj_solve(cgks_ctx *c, int32_t tag, const double e[3], int max_iter, double tol, double *lamW, double *lamG,
               double *lamA, double *cR, double *cG, double *cA, double *hist);
+// after adj_solve: dJ/dp_k = dJ/dp_k|_U + c . dE/dp_k|_U for every parameter direction (host out[n_params])
+void adj_param_derivatives(cgks_ctx *c, int32_t tag, const double e[3], double *out);
 
 inline int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 

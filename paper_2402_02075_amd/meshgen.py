@@ -723,11 +723,32 @@ _FACES = {4: [(0, 1, 3), (1, 2, 3), (2, 0, 3), (0, 2, 1)],
           8: [(0, 3, 2, 1), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7)]}
 
 
-def submesh(m: Mesh, cells, cut_tag: int = TAG_FARFIELD) -> Mesh:
+def _cut_faces_per_cell(m: Mesh, cells, bkeys):
+    count = {}
+    keys = []
+    for c in cells:
+        nodes = m.cnode[m.cnode_ptr[c]:m.cnode_ptr[c + 1]]
+        ks = [tuple(sorted(int(nodes[k]) for k in loc)) for loc in _FACES[int(m.ctype[c])]]
+        keys.append(ks)
+        for key in ks:
+            count[key] = count.get(key, 0) + 1
+    return np.array([sum(1 for key in ks if count[key] == 1 and key not in bkeys) for ks in keys])
+
+
+def submesh(m: Mesh, cells, cut_tag: int = TAG_FARFIELD, max_cut: int | None = None) -> Mesh:
     """The mesh made of the listed cells (no periodic images): faces shared with a cell left out
-    become boundary faces with `cut_tag`; boundary faces of the kept cells keep their tags."""
+    become boundary faces with `cut_tag`; boundary faces of the kept cells keep their tags.  With
+    `max_cut`, cells with more cut faces than that are dropped repeatedly, so that every kept cell
+    keeps all but `max_cut` of its face neighbours (a full-rank reconstruction stencil)."""
     assert m.node_canon is None
     cells = np.unique(np.asarray(cells, np.int64))
+    if max_cut is not None:
+        bkeys = {tuple(sorted(m.bnode[m.bnode_ptr[b]:m.bnode_ptr[b + 1]].tolist())) for b in range(m.btag.shape[0])}
+        while True:
+            cut = _cut_faces_per_cell(m, cells, bkeys)
+            if not np.any(cut > max_cut):
+                break
+            cells = cells[cut <= max_cut]
     bset = {}
     for b in range(m.btag.shape[0]):
         nodes = m.bnode[m.bnode_ptr[b]:m.bnode_ptr[b + 1]]
