@@ -45,9 +45,10 @@ FACE_SUM_OPS = 21.0
 FP64_PEAK_TFLOPS = 78.6       # MI355X dense FP64 vector
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of that kernel on the headline workload, from two rocprofv3 --pmc passes
-# (FETCH_SIZE and WRITE_SIZE, scaled by the factors a 1 GiB copy and fill read in the same runs).
-# None whenever the kernel has changed since the counters were taken.
-FACE_HBM_BYTES_PER_LAUNCH = None
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a 1 GiB copy and fill read in the same runs;
+# profiles/counters_fine_kernels_sphere6M.md).  None whenever the kernel has changed since the
+# counters were taken.
+FACE_HBM_BYTES_PER_LAUNCH = 12.57e9
 
 
 def log(*a):
