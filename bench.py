@@ -450,6 +450,44 @@ def adjoint_check(torch, cg, mg):
     return out
 
 
+def long_run(torch, cg, mg, name, cycles, chunk=1000):
+    """FP64 then mixed V-cycles from the free stream on one sphere mesh, `cycles` each, with the drop,
+    minimum drop and drag every `chunk` cycles, then the mixed run's density-field and drag
+    differences from the FP64 run (a long convergence record, not part of the default run)."""
+    spec = {"sphere6M": (6, 33, 12), "sphere1p47M": (5, 32, 12)}[name]
+    m, S, sizes, setup = sphere_solver(cg, mg, *spec)
+    N = m.n_cells
+    out = {"long_run": name, "cells": N, "level_cells": [int(x) for x in sizes], "cycles": cycles}
+    ref = None
+    for prec, key in ((0, "fp64"), (1, "mixed")):
+        S.set_params(precision=prec)
+        W, G, al = free_stream(torch, mg, N, (0.2, 0.0, 0.0))
+        hs, cps, done = [], [], 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while done < cycles:
+            n = min(chunk, cycles - done)
+            h, _ = S.vcycle(W, G, al, n, 0.0)
+            hs.append(np.asarray(h))
+            done += n
+            hh = np.concatenate(hs)
+            cd = drag(S, mg, W, G, al)
+            cps.append({"cycles": done, "seconds": time.perf_counter() - t0, "drop": float(hh[-1] / hh[0]),
+                        "min_drop": float(hh.min() / hh[0]), "Cd": cd})
+            log(name, key, json.dumps(cps[-1]))
+        out[key] = cps
+        if ref is None:
+            ref = (W[0].clone(), cd)
+        else:
+            d = W[0] - ref[0]
+            out["mixed_vs_fp64"] = {"density_l2": float(torch.sqrt((d * d).mean())),
+                                    "density_max": float(d.abs().max()), "Cd_diff": cd - ref[1],
+                                    "Cd_rel": (cd - ref[1]) / ref[1]}
+        del W, G, al
+    S.close()
+    return out
+
+
 def copy_bandwidth(torch):
     """Achievable HBM bandwidth: a 4 GiB device-to-device copy (8 GiB moved), median of 5."""
     a = torch.empty(1 << 29, dtype=torch.float64, device="cuda")
@@ -488,6 +526,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient check and timings")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--headline-only", action="store_true", help="only the headline workload (profiling)")
+    ap.add_argument("--long-run", choices=("sphere6M", "sphere1p47M"),
+                    help="instead of the benchmark: FP64 and mixed V-cycles from the free stream on that sphere")
+    ap.add_argument("--cycles", type=int, default=8000, help="V-cycles per precision of --long-run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="a plain 1 GiB fill and copy first (known bytes for scaling the HBM counters)")
     args = ap.parse_args()
@@ -499,6 +540,9 @@ def main():
     from paper_2402_02075_amd import cgks as cg
     from paper_2402_02075_amd import meshgen as mg
     torch.cuda.set_device(0)
+    if args.long_run:
+        print(json.dumps(long_run(torch, cg, mg, args.long_run, args.cycles)))
+        return
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         a.fill_(1.0)

@@ -237,6 +237,18 @@ cgks_status cgks_vjp_residual(cgks_ctx *ctx, const double *barR, const double *b
                               double *barW, double *barG, double *barAlpha);
 
 /*
+ * Directional derivative of the fine operator: (dR, dG, dA) = dE/d(W, G, alpha) . (vW, vG, vA) at
+ * (W, G, alpha) (device; alpha and vA nullable = ones / zero; dG, dA nullable), by one pass of
+ * forward-mode dual numbers through the reconstruction (Sec. 3), the local steps, the Gauss-point
+ * BGK solution in its moment-matrix form (Eq. 2nd-flux, Sec. 2.4, Sec. 3.3) and the cell sums.
+ * It needs no cgks_linearize and shares no recorded Jacobian with the vector-Jacobian products,
+ * so <u, J v> against <J^T u, v> checks them.  Same one-sided conventions at kinks as the
+ * linearisation.  Allocates its work memory per call; synchronises.
+ */
+cgks_status cgks_jvp_residual(cgks_ctx *ctx, const double *W, const double *G, const double *alpha, const double *vW,
+                              const double *vG, const double *vA, double *dR, double *dG, double *dA);
+
+/*
  * Gradient of J = e . F_wall(tag) (cgks_wall_force) at the linearised state with
  * respect to (W, G, alpha): device barW[5N], barG[15N], barAlpha[N] (nullable); e host double[3].
  */
@@ -345,6 +357,18 @@ cgks_status cgks_prolong(cgks_ctx *ctx, int32_t level, const double *dWc, double
  */
 cgks_status cgks_vcycle(cgks_ctx *ctx, double *W, double *G, double *alpha, int32_t max_cycles, double tol_drop,
                         double *hist, int32_t *n_done);
+
+/*
+ * Host-pointer twins of cgks_residual and cgks_vcycle: the same arguments and results with every
+ * cell array in host memory (caller's cell order); the library copies them to and from device
+ * memory it allocates for the call and synchronises before returning.  cgks_vcycle_host writes the
+ * state back also when it returns CGKS_E_NOCONV, CGKS_E_PHYS or CGKS_E_NONFINITE (the state the
+ * device call leaves).
+ */
+cgks_status cgks_residual_host(cgks_ctx *ctx, const double *W, const double *G, const double *alpha, double *R,
+                               double *G_new, double *alpha_new);
+cgks_status cgks_vcycle_host(cgks_ctx *ctx, double *W, double *G, double *alpha, int32_t max_cycles, double tol_drop,
+                             double *hist, int32_t *n_done);
 
 /*
  * Kernel timing for profiling: with enable = 1 the library brackets every

@@ -24,7 +24,8 @@ EXPORTS = ["cgks_default_params", "cgks_create", "cgks_destroy", "cgks_last_erro
            "cgks_agglomerate_graph", "cgks_agglomerate", "cgks_level_map", "cgks_kfvs_residual", "cgks_restrict",
            "cgks_prolong", "cgks_vcycle", "cgks_timing", "cgks_wall_force", "cgks_linearize", "cgks_vjp_residual",
            "cgks_vjp_wall_force", "cgks_vjp_kfvs", "cgks_adjoint_solve", "cgks_coarse_implicit", "cgks_cell_order",
-           "cgks_residual_noalloc", "cgks_set_param_directions"]
+           "cgks_residual_noalloc", "cgks_set_param_directions", "cgks_jvp_residual",
+           "cgks_residual_host", "cgks_vcycle_host"]
 
 
 class Params(C.Structure):
@@ -66,7 +67,8 @@ def lib():
             "cgks_wall_force": [P, P, P, P, I32, P], "cgks_linearize": [P, P, P, P],
             "cgks_vjp_residual": [P, P, P, P, P, P, P], "cgks_vjp_wall_force": [P, I32, P, P, P, P],
             "cgks_vjp_kfvs": [P, I32, P, P, P], "cgks_adjoint_solve": [P, I32, P, I32, D, P, P, P, P, P, P, P, P, P],
-            "cgks_set_param_directions": [P, I32, P, P, D],
+            "cgks_set_param_directions": [P, I32, P, P, D], "cgks_jvp_residual": [P, P, P, P, P, P, P, P, P, P],
+            "cgks_residual_host": [P, P, P, P, P, P, P], "cgks_vcycle_host": [P, P, P, P, I32, D, P, P],
             "cgks_coarse_implicit": [P, I32, P, P, P], "cgks_cell_order": [P, P],
             "cgks_residual_noalloc": [P, P, P, P, P, P, P],
         }
@@ -221,6 +223,30 @@ class Solver:
         self._check(lib().cgks_residual_noalloc(self.h, _ptr(W), _ptr(G), _ptr(alpha), _ptr(R), _ptr(Gn), _ptr(an)))
         return R, Gn, an
 
+    def residual_host(self, W, G, alpha=None):
+        """cgks_residual on host (numpy) arrays in the caller's order -> numpy (R, G_new, alpha_new)."""
+        N = self.n_cells
+        W, G = _np(W, np.float64), _np(G, np.float64)
+        al = None if alpha is None else _np(alpha, np.float64)
+        R, Gn, an = np.zeros((5, N)), np.zeros((15, N)), np.zeros(N)
+        p = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+        self._check(lib().cgks_residual_host(self.h, p(W), p(G), p(al), p(R), p(Gn), p(an)))
+        return R, Gn, an
+
+    def vcycle_host(self, W, G, alpha, max_cycles, tol_drop=1e-10):
+        """cgks_vcycle on host (numpy, contiguous float64, updated in place) arrays."""
+        for a in (W, G, alpha):
+            if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous):
+                raise ValueError("vcycle_host needs contiguous float64 numpy arrays (updated in place)")
+        hist = np.zeros(max(max_cycles, 1))
+        done = C.c_int32(0)
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        code = lib().cgks_vcycle_host(self.h, p(W), p(G), p(alpha), int(max_cycles), float(tol_drop), p(hist),
+                                      C.byref(done))
+        if code not in (OK, E_NOCONV):
+            self._check(code)
+        return hist[:done.value], code == OK
+
     def step(self, W, G, alpha, dt_global=-1.0, resnorm=None):
         self._check(lib().cgks_step(self.h, _ptr(W), _ptr(G), _ptr(alpha), float(dt_global), _ptr(resnorm)))
 
@@ -250,6 +276,14 @@ class Solver:
         self._check(lib().cgks_vjp_residual(self.h, _ptr(barR), _ptr(barGnew), _ptr(barAnew), _ptr(bW), _ptr(bG),
                                             _ptr(bA)))
         return bW, bG, bA
+
+    def jvp_residual(self, W, G, alpha, vW, vG, vA=None):
+        """dE/dU . (vW, vG, vA) at (W, G, alpha) by forward-mode dual numbers -> (dR, dG, dA)."""
+        N = self.n_cells
+        dR, dG, dA = self.empty(5, N), self.empty(15, N), self.empty(N)
+        self._check(lib().cgks_jvp_residual(self.h, _ptr(W), _ptr(G), _ptr(alpha), _ptr(vW), _ptr(vG), _ptr(vA),
+                                            _ptr(dR), _ptr(dG), _ptr(dA)))
+        return dR, dG, dA
 
     def vjp_wall_force(self, tag, e=(1.0, 0.0, 0.0)):
         """Gradient of e . F_wall(tag) with respect to (W, G, alpha) at the linearised state."""

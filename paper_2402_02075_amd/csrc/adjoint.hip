@@ -1038,6 +1038,212 @@ int adj_solve(cgks_ctx *c, int32_t tag, const double e[3], int max_iter, double 
     return it;
 }
 
+// ---------------------------------------------------------------- forward-mode JVP
+// Directional derivative of the fine operator E(W, G, alpha) = (R, G_new, alpha_new) along
+// (vW, vG, vA), by one pass of dual numbers (one tangent) through the reconstruction, the local
+// steps, the Gauss-point physics (the moment-matrix form of the flux, as in the linearisation)
+// and the cell sums.  It uses no recorded Jacobian, so it checks the vector-Jacobian products
+// independently (their dot products must agree to rounding).
+using D1 = Dual<1>;
+
+template <int C> __device__ __forceinline__ void recon_jvp_comp(const ReconArgs &A, const double *vW, const double *vG,
+                                                               const double *vA, int64_t i, double *cv, double *ct)
+{
+    const int64_t N = A.N;
+    D1 x[6];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        x[c] = D1(A.W[c * N + i]);
+        x[c].d[0] = vW[c * N + i];
+    }
+    x[5] = D1(A.alpha ? A.alpha[i] : 1.0);
+    x[5].d[0] = (A.alpha && vA) ? vA[i] : 0.0;
+    D1 nbw[6], nbg[6][3];
+    for (int s = 0; s < 6; ++s) {
+        const int nbv = A.slot_nb[s * N + i];
+        const bool in = nbv >= 0;
+        nbw[s] = D1(in ? A.W[C * N + nbv] : 0.0);
+        nbw[s].d[0] = in ? vW[C * N + nbv] : 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            nbg[s][d] = D1(in ? A.G[(3 * C + d) * N + nbv] : 0.0);
+            nbg[s][d].d[0] = in ? vG[(3 * C + d) * N + nbv] : 0.0;
+        }
+    }
+    D1 r[10];
+    recon_generic<D1, C>(A, i, x, x[5], nbw, nbg, r);
+#pragma unroll
+    for (int o = 0; o < 10; ++o) {
+        cv[i * 50 + 10 * C + o] = r[o].v;
+        ct[i * 50 + 10 * C + o] = r[o].d[0];
+    }
+}
+
+__global__ __launch_bounds__(320) void k_recon_jvp(ReconArgs A, const double *vW, const double *vG, const double *vA,
+                                                   double *cv, double *ct)
+{
+    const int64_t i = (int64_t)blockIdx.x * OP_GROUP + (threadIdx.x & (OP_GROUP - 1));
+    if (i >= A.N) return;
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+    case 0: recon_jvp_comp<0>(A, vW, vG, vA, i, cv, ct); break;
+    case 1: recon_jvp_comp<1>(A, vW, vG, vA, i, cv, ct); break;
+    case 2: recon_jvp_comp<2>(A, vW, vG, vA, i, cv, ct); break;
+    case 3: recon_jvp_comp<3>(A, vW, vG, vA, i, cv, ct); break;
+    default: recon_jvp_comp<4>(A, vW, vG, vA, i, cv, ct); break;
+    }
+}
+
+__global__ void k_dt_jvp(int64_t N, int64_t F, double gam, double cfl, double mu, int viscous, const double *W,
+                         const double *vW, const int32_t *cf_ptr, const int32_t *cf_face, const double *favec,
+                         const double *farea, const double *vol, double *dtv, double *dtt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    D1 w[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        w[c] = D1(W[c * N + i]);
+        w[c].d[0] = vW[c * N + i];
+    }
+    const D1 dt = local_dt_t(i, F, gam, cfl, mu, viscous, w, cf_ptr, cf_face, favec, farea, vol[i]);
+    dtv[i] = dt.v;
+    dtt[i] = dt.d[0];
+}
+
+// one lane per Gauss-point slot: the 11 outputs and their tangents, [22][NS]
+__global__ __launch_bounds__(64) void k_face_jvp(GpArgs A, const double *ct, const double *dtt, double *sv)
+{
+    const int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = gp >> 2;
+    const int k = (int)(gp & 3);
+    if (f >= A.F || k >= A.fngp[f]) return;
+    const int64_t F = A.F, N = A.N, NS = A.NS;
+    const int L = A.fl[f], R = A.fr[f];
+    const double x[3] = {A.gpx[(3 * k) * F + f], A.gpx[(3 * k + 1) * F + f], A.gpx[(3 * k + 2) * F + f]};
+    const double n[3] = {A.gpn[(3 * k) * F + f], A.gpn[(3 * k + 1) * F + f], A.gpn[(3 * k + 2) * F + f]};
+    // the face step: the smaller of the two local steps (the left one on a tie)
+    const bool left = R < 0 || A.dt[L] <= A.dt[R];
+    D1 dtf(left ? A.dt[L] : A.dt[R]);
+    dtf.d[0] = left ? dtt[L] : dtt[R];
+    D1 WL[5], GL[15], WR[5], GR[15];
+    auto eval = [&](int cell, const double dx[3], D1 w[5], D1 g[15]) {
+        const D1 dxd[3] = {D1(dx[0]), D1(dx[1]), D1(dx[2])};
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            D1 r[10];
+#pragma unroll
+            for (int q = 0; q < 10; ++q) {
+                r[q] = D1(A.coef[cell * 50 + 10 * c + q]);
+                r[q].d[0] = ct[cell * 50 + 10 * c + q];
+            }
+            poly_eval(r, dxd, w[c], &g[3 * c]);
+        }
+    };
+    {
+        const double dx[3] = {x[0] - A.cen[L], x[1] - A.cen[N + L], x[2] - A.cen[2 * N + L]};
+        eval(L, dx, WL, GL);
+    }
+    if (R >= 0) {
+        const double dx[3] = {x[0] - A.fshift[f] - A.cen[R], x[1] - A.fshift[F + f] - A.cen[N + R],
+                              x[2] - A.fshift[2 * F + f] - A.cen[2 * N + R]};
+        eval(R, dx, WR, GR);
+    }
+    D1 out[GP_OUT];
+    const bool ok = gp_outputs(A, (int)f, R, n, WL, GL, WR, GR, dtf, out);
+    if (!ok) atomicMin(A.bad, L);
+#pragma unroll
+    for (int o = 0; o < GP_OUT; ++o) {
+        sv[(int64_t)o * NS + gp] = ok ? out[o].v : (o == 10 ? 1.0 : 0.0);
+        sv[(int64_t)(GP_OUT + o) * NS + gp] = ok ? out[o].d[0] : 0.0;
+    }
+}
+
+// per cell: R = -sum_faces s sum_k w_k S F, G_new = alpha_new S_gv / V with
+// S_gv = sum_faces s sum_k w_k S W(dt_f) n, alpha_new = product over interior-face points
+__global__ void k_gather_jvp(int64_t N, int64_t F, int64_t NS, const int32_t *cf_ptr, const int32_t *cf_face,
+                             const int32_t *fr, const int32_t *fngp, const double *gpw, const double *gpn,
+                             const double *vol, const double *sv, double *dR, double *dG, double *dA)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    D1 r[5], gs[15], al(1.0);
+    for (int k = cf_ptr[i]; k < cf_ptr[i + 1]; ++k) {
+        const int it = cf_face[k];
+        const int f = it >> 1;
+        const double s = (it & 1) ? -1.0 : 1.0;
+        for (int q = 0; q < fngp[f]; ++q) {
+            const int64_t gp = 4 * (int64_t)f + q;
+            const double wS = gpw[(int64_t)q * F + f];
+            D1 o[GP_OUT];
+#pragma unroll
+            for (int j = 0; j < GP_OUT; ++j) {
+                o[j] = D1(sv[(int64_t)j * NS + gp]);
+                o[j].d[0] = sv[(int64_t)(GP_OUT + j) * NS + gp];
+            }
+#pragma unroll
+            for (int c = 0; c < 5; ++c) r[c] = r[c] - (s * wS) * o[c];
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) gs[3 * c + d] = gs[3 * c + d] + (s * wS * gpn[(int64_t)(3 * q + d) * F + f]) * o[5 + c];
+            if (fr[f] >= 0) al = al * o[10];
+        }
+    }
+    const double iv = 1.0 / vol[i];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) dR[c * N + i] = r[c].d[0];
+#pragma unroll
+    for (int q = 0; q < 15; ++q) {
+        const D1 g = al * gs[q] * D1(iv);
+        if (dG) dG[q * N + i] = g.d[0];
+    }
+    if (dA) dA[i] = al.d[0];
+}
+
+void jvp_residual(cgks_ctx *c, const double *W, const double *G, const double *alpha, const double *vW,
+                  const double *vG, const double *vA, double *dR, double *dG, double *dA)
+{
+    hipStream_t st = c->stream;
+    const int64_t N = c->N, F = c->F, NS = 4 * F;
+    DBuf<double> cv, ct, dtv, dtt, sv, bg;
+    cv.alloc(50 * N);
+    ct.alloc(50 * N);
+    dtv.alloc(N);
+    dtt.alloc(N);
+    sv.alloc(2 * GP_OUT * NS);
+    ReconArgs RA = recon_args(c, W, G, alpha);
+    hipLaunchKernelGGL(k_recon_jvp, dim3(blocks_for(N, OP_GROUP)), dim3(5 * OP_GROUP), 0, st, RA, vW, vG, vA, cv.p,
+                       ct.p);
+    hipLaunchKernelGGL(k_dt_jvp, B1(N), dim3(256), 0, st, N, F, c->prm.gamma, c->prm.cfl, c->prm.mu, c->prm.viscous, W,
+                       vW, c->cf_ptr.p, c->cf_face.p, c->favec.p, c->farea.p, c->vol.p, dtv.p, dtt.p);
+    GpArgs A;
+    A.N = N;
+    A.F = F;
+    A.NS = NS;
+    A.cfg = cfg_of(c);
+    A.coef = cv.p;
+    A.dt = dtv.p;
+    A.cen = c->cen.p;
+    A.gpx = c->gpx.p;
+    A.gpw = c->gpw.p;
+    A.gpn = c->gpn.p;
+    A.fshift = c->fshift.p;
+    A.dtL = nullptr;
+    A.fl = c->fl.p;
+    A.fr = c->fr.p;
+    A.ftag = c->ftag.p;
+    A.fngp = c->fngp.p;
+    A.bc = c->bc.p;
+    A.Jf = nullptr;
+    A.agp = nullptr;
+    A.bad = c->bad.p;
+    hipLaunchKernelGGL(k_face_jvp, B1(NS, 64), dim3(64), 0, st, A, ct.p, dtt.p, sv.p);
+    hipLaunchKernelGGL(k_gather_jvp, B1(N), dim3(256), 0, st, N, F, NS, c->cf_ptr.p, c->cf_face.p, c->fr.p, c->fngp.p,
+                       c->gpw.p, c->gpn.p, c->vol.p, sv.p, dR, dG, dA);
+    CGKS_HIP(hipGetLastError());
+    CGKS_HIP(hipStreamSynchronize(st));
+}
+
 // ---------------------------------------------------------------- parameter sensitivities
 // sum over blocks of a . b, one partial per block (fixed grid: the sum is deterministic)
 __global__ __launch_bounds__(256) void k_dot_part(int64_t n, const double *a, const double *b, double *part)

@@ -711,6 +711,39 @@ cgks_status cgks_vjp_residual(cgks_ctx *c, const double *barR, const double *bar
     API_END(c)
 }
 
+cgks_status cgks_jvp_residual(cgks_ctx *c, const double *W, const double *G, const double *alpha, const double *vW,
+                              const double *vG, const double *vA, double *dR, double *dG, double *dA)
+{
+    API_BEGIN(c)
+    need_bc(c);
+    if (!W || !G || !vW || !vG || !dR) throw Error{CGKS_E_ARG, "W, G, vW, vG and dR required"};
+    const double *w = cells_in(c, W, 5, 0), *g = cells_in(c, G, 15, 1), *a = cells_in(c, alpha, 1, 2);
+    const double *tw = cells_in(c, vW, 5, 3), *tg = cells_in(c, vG, 15, 4), *ta = cells_in(c, vA, 1, 5);
+    DBuf<double> oR, oG, oA;
+    double *r = dR, *gn = dG, *an = dA;
+    if (io_moved(c)) {
+        oR.alloc(5 * c->N);
+        r = oR.p;
+        if (dG) {
+            oG.alloc(15 * c->N);
+            gn = oG.p;
+        }
+        if (dA) {
+            oA.alloc(c->N);
+            an = oA.p;
+        }
+    }
+    jvp_residual(c, w, g, a, tw, tg, ta, r, gn, an);
+    if (io_moved(c)) {
+        cells_scatter(c, (const double *)r, dR, 5);
+        if (dG) cells_scatter(c, (const double *)gn, dG, 15);
+        if (dA) cells_scatter(c, (const double *)an, dA, 1);
+        CGKS_HIP(hipStreamSynchronize(c->stream));
+    }
+    check_bad(c);
+    API_END(c)
+}
+
 cgks_status cgks_vjp_wall_force(cgks_ctx *c, int32_t tag, const double *e, double *barW, double *barG,
                                 double *barAlpha)
 {
@@ -943,6 +976,61 @@ cgks_status cgks_vcycle(cgks_ctx *c, double *W, double *G, double *alpha, int32_
     cells_out(c, G, 15, 1);
     cells_out(c, alpha, 1, 2);
     if (st != CGKS_OK) return st;
+    API_END(c)
+}
+
+// ---------------------------------------------------------------- host-pointer twins
+cgks_status cgks_residual_host(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *R,
+                               double *G_new, double *alpha_new)
+{
+    API_BEGIN(c)
+    need_bc(c);
+    if (!W || !G || !R || (G_new == nullptr) != (alpha_new == nullptr))
+        throw Error{CGKS_E_ARG, "W, G, R required; G_new and alpha_new both or neither"};
+    const int64_t N = c->N;
+    DBuf<double> w, g, a, r, gn, an;
+    w.upload(W, 5 * N, c->stream);
+    g.upload(G, 15 * N, c->stream);
+    if (alpha) a.upload(alpha, N, c->stream);
+    r.alloc(5 * N);
+    if (G_new) {
+        gn.alloc(15 * N);
+        an.alloc(N);
+    }
+    const cgks_status st = cgks_residual(c, w.p, g.p, alpha ? a.p : nullptr, r.p, gn.p, an.p);
+    if (st != CGKS_OK) return st;
+    CGKS_HIP(hipMemcpyAsync(R, r.p, 5 * N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (G_new) {
+        CGKS_HIP(hipMemcpyAsync(G_new, gn.p, 15 * N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        CGKS_HIP(hipMemcpyAsync(alpha_new, an.p, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    CGKS_HIP(hipStreamSynchronize(c->stream));
+    check_bad(c);
+    API_END(c)
+}
+
+cgks_status cgks_vcycle_host(cgks_ctx *c, double *W, double *G, double *alpha, int32_t max_cycles, double tol_drop,
+                             double *hist, int32_t *n_done)
+{
+    API_BEGIN(c)
+    need_bc(c);
+    if (!W || !G || !alpha || max_cycles < 0) throw Error{CGKS_E_ARG, "bad arguments"};
+    const int64_t N = c->N;
+    DBuf<double> w, g, a;
+    w.upload(W, 5 * N, c->stream);
+    g.upload(G, 15 * N, c->stream);
+    a.upload(alpha, N, c->stream);
+    const cgks_status st = cgks_vcycle(c, w.p, g.p, a.p, max_cycles, tol_drop, hist, n_done);
+    if (st != CGKS_OK && st != CGKS_E_NOCONV && st != CGKS_E_PHYS && st != CGKS_E_NONFINITE) return st;
+    const std::string msg = c->err;
+    CGKS_HIP(hipMemcpyAsync(W, w.p, 5 * N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CGKS_HIP(hipMemcpyAsync(G, g.p, 15 * N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CGKS_HIP(hipMemcpyAsync(alpha, a.p, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CGKS_HIP(hipStreamSynchronize(c->stream));
+    if (st != CGKS_OK) {
+        c->err = msg;
+        return st;
+    }
     API_END(c)
 }
 

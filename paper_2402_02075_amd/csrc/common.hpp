@@ -282,6 +282,9 @@ void adj_vjp_wall(cgks_ctx *c, int32_t tag, const double e[3], double *oW, doubl
 void adj_vjp_kfvs(cgks_ctx *c, int level, const double *Wc, const double *bR, double *oW, bool accumulate);
 int adj_solve(cgks_ctx *c, int32_t tag, const double e[3], int max_iter, double tol, double *lamW, double *lamG,
               double *lamA, double *cR, double *cG, double *cA, double *hist);
+// directional derivative of the fine operator by forward-mode dual numbers (no recorded Jacobian)
+void jvp_residual(cgks_ctx *c, const double *W, const double *G, const double *alpha, const double *vW,
+                  const double *vG, const double *vA, double *dR, double *dG, double *dA);
 // after adj_solve: dJ/dp_k = dJ/dp_k|_U + c . dE/dp_k|_U for every parameter direction (host out[n_params])
 void adj_param_derivatives(cgks_ctx *c, int32_t tag, const double e[3], double *out);
 

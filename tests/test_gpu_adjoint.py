@@ -3,12 +3,14 @@
 * VJP of the fine operator E = (R, G_new, alpha_new) against central differences of
   the library's own operator (dot-product test, Richardson-extrapolated) and
   against central differences of the CPU oracle's operator at the same seeded state.
+* VJP of the fine operator against a forward-mode dual-number JVP that uses no recorded
+  Jacobian (dot products equal to 1e-12).
 * VJP of the coarse KFVS operator and of the wall force, likewise.
 * torch.autograd path through ResidualFunction.
 * Gradients of the lower-wall x-force with respect to the inflow Mach number and
-  the bump amplitude from the adjoint fixed point, against central differences of
-  the converged objective, on a small hexahedral bump channel that converges to
-  the round-off floor.
+  the bump amplitude returned by the library's adjoint solve, against central
+  differences (step 1e-6) of the converged objective, on a small hexahedral bump
+  channel that converges to the round-off floor.
 Inputs come from the seeded generators; no expected value comes from the library.
 """
 import numpy as np
@@ -92,6 +94,34 @@ def test_vjp_residual_dot(torch, ad, name):
     rel = abs(lhs - rhs) / abs(rhs)
     say(f"    vjp {lhs:.12e} fd {rhs:.12e} rel {rel:.2e}")
     assert rel < 1e-6
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_vjp_against_dual_number_jvp(torch, ad, name):
+    """<u, J v> with J v from cgks_jvp_residual (one forward pass of dual numbers, no recorded
+    Jacobian) against <J^T u, v> from the linearisation's VJP, to 1e-12 of the summed magnitudes."""
+    m = MESHES[name]()
+    say(f"[gpu] vjp vs dual-number jvp {name} cells={m.n_cells}")
+    S = ad.channel_solver(m, 0.5, agglomerate=False)
+    W, G, al = _smooth(torch, m, seed=17)
+    N = m.n_cells
+    g = torch.Generator(device="cuda").manual_seed(9)
+    u = (_randn(torch, g, 5, N), _randn(torch, g, 15, N), _randn(torch, g, N))
+    v = (_randn(torch, g, 5, N) * W.abs().mean(1, keepdim=True), _randn(torch, g, 15, N) * 0.1,
+         _randn(torch, g, N) * 0.1)
+    dR, dG, dA = S.jvp_residual(W, G, al, *v)
+    S.linearize(W, G, al)
+    bW, bG, bA = S.vjp_residual(*u)
+    terms_l = [(u[0] * dR), (u[1] * dG), (u[2] * dA)]
+    terms_r = [(bW * v[0]), (bG * v[1]), (bA * v[2])]
+    lhs = float(sum(t.sum() for t in terms_l))
+    rhs = float(sum(t.sum() for t in terms_r))
+    scale = float(sum(t.abs().sum() for t in terms_l + terms_r))
+    say(f"    <u, Jv> {lhs:.15e} <J^T u, v> {rhs:.15e} diff/scale {abs(lhs - rhs) / scale:.2e}")
+    assert abs(lhs - rhs) <= 1e-12 * scale
+    # the JVP itself against central differences of the operator (its own sanity check)
+    fd = _richardson(lambda h: _ops_dot(S, W, G, al, u, v, h), H_FD)
+    assert abs(lhs - fd) <= 1e-6 * abs(fd)
 
 
 def test_vjp_residual_vs_oracle(torch, ad, oracle):

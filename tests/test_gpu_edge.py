@@ -131,3 +131,85 @@ def test_ragged_group_tail_matches_oracle(oracle, cg, torch):
     F = M.faces()
     assert_residual_close(R, oR, cell_surface(F, m.n_cells), flux_scale(W), what="R ragged")
     np.testing.assert_allclose(an, oan, rtol=1e-10, atol=1e-14)
+
+
+def test_host_twins_equal_device_calls(cg, torch):
+    """cgks_residual_host and cgks_vcycle_host (host arrays in the caller's order) give the device
+    calls' results bit for bit, on a mesh whose cells are listed in a random order."""
+    m = mg.permute_cells(mg.bump_channel(12, 6, 4, n_prism=2, n_pyr=2, jitter=0.05, seed=3, amp=0.05), seed=4)
+    S = cg.Solver()
+    S.set_mesh(m)
+    prim = np.array([1.0, 0.5, 0.0, 0.0, 1.0 / 1.4])
+    for tag in (mg.TAG_INLET, mg.TAG_OUTLET):
+        S.set_bc(tag, cg.BC_FARFIELD, prim)
+    for tag in (mg.TAG_WALL_BOTTOM, mg.TAG_WALL_TOP, mg.TAG_WALL_SIDE):
+        S.set_bc(tag, cg.BC_SLIP)
+    S.agglomerate()
+    x = mg.cell_node_mean(m)
+    W = mg.random_smooth_state(x, seed=6, amp=0.05)
+    G = np.zeros((15, m.n_cells))
+    al = np.ones(m.n_cells)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    R, Gn, an = S.residual(dev(W), dev(G), dev(al))
+    Rh, Gnh, anh = S.residual_host(W, G, al)
+    np.testing.assert_array_equal(Rh, R.cpu().numpy())
+    np.testing.assert_array_equal(Gnh, Gn.cpu().numpy())
+    np.testing.assert_array_equal(anh, an.cpu().numpy())
+    Wd, Gd, ad = dev(W), dev(G), dev(al)
+    h, _ = S.vcycle(Wd, Gd, ad, 5, 0.0)
+    Wh, Gh, ah = W.copy(), G.copy(), al.copy()
+    hh, _ = S.vcycle_host(Wh, Gh, ah, 5, 0.0)
+    np.testing.assert_array_equal(hh, h)
+    np.testing.assert_array_equal(Wh, Wd.cpu().numpy())
+    np.testing.assert_array_equal(Gh, Gd.cpu().numpy())
+    np.testing.assert_array_equal(ah, ad.cpu().numpy())
+
+
+def test_batch_rollback_equals_checked_loop(cg, torch):
+    """A state that turns non-physical a few cycles into a queued batch (a large CFL number on a
+    perturbed channel): the batch call reports CGKS_E_PHYS with the cycles run and the state left
+    bit-identical to a loop of single-cycle calls that stops at its first error (the batch restores
+    its starting state and re-runs cycle by cycle)."""
+    import ctypes as C
+    m = mg.bump_channel(16, 6, 4, n_prism=2, n_pyr=2, jitter=0.05, seed=7, amp=0.05)
+    S = cg.Solver()
+    S.set_mesh(m)
+    _channel_bcs(S, cg)
+    S.agglomerate()
+    x = mg.cell_node_mean(m)
+    W0 = mg.random_smooth_state(x, seed=8, amp=0.05)
+    G0 = np.zeros((15, m.n_cells))
+    a0 = np.ones(m.n_cells)
+    lib = cg.lib()
+    found = None
+    for cfl in (2.0, 3.0, 4.0, 6.0, 8.0, 12.0, 16.0):
+        S.set_params(cfl=cfl)
+        W, G, al = to_dev(torch, W0), to_dev(torch, G0), to_dev(torch, a0)
+        j = None
+        for k in range(16):
+            try:
+                S.vcycle(W, G, al, 1, 1e-10)
+            except cg.CgksError as e:
+                assert e.code == cg.E_PHYS
+                j = k
+                break
+        if j is not None and 2 <= j <= 14:
+            found = (cfl, j, W.clone(), G.clone(), al.clone())
+            break
+    assert found is not None, "no CFL number in the list fails inside the first batch"
+    cfl, j, Wc, Gc, ac = found
+    say(f"[gpu] rollback: CFL {cfl}, the checked loop fails in cycle {j + 1}")
+    S.set_params(cfl=cfl)
+    W, G, al = to_dev(torch, W0), to_dev(torch, G0), to_dev(torch, a0)
+    hist = np.zeros(16)
+    done = C.c_int32(-1)
+    code = lib.cgks_vcycle(S.h, C.c_void_p(W.data_ptr()), C.c_void_p(G.data_ptr()), C.c_void_p(al.data_ptr()), 16,
+                           1e-10, hist.ctypes.data_as(C.c_void_p), C.byref(done))
+    assert code == cg.E_PHYS
+    assert done.value == j
+    bits = lambda t: t.contiguous().view(torch.int64)
+    assert torch.equal(bits(W), bits(Wc)) and torch.equal(bits(G), bits(Gc)) and torch.equal(bits(al), bits(ac))
+    # the flag is cleared afterwards: a physical state runs again
+    S.set_params(cfl=0.5)
+    h, _ = S.vcycle(to_dev(torch, W0), to_dev(torch, G0), to_dev(torch, a0), 3, 0.0)
+    assert np.isfinite(h).all()
