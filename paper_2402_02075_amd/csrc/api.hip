@@ -447,6 +447,7 @@ cgks_status cgks_set_params(cgks_ctx *c, const cgks_params *p)
     if (c->has_mesh && (p->cell_order == 0) != (c->prm.cell_order == 0))
         throw Error{CGKS_E_ARG, "cell_order 0 against 1/2 is fixed by cgks_set_mesh: set the mesh again"};
     c->prm = *p;
+    if (c->prm.precision == 1) ensure_fp32_front(c);
     API_END(c)
 }
 
@@ -468,6 +469,9 @@ cgks_status cgks_set_mesh(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64
     for (Level *l : c->lev) delete l;
     c->lev.assign(1, nullptr);
     c->has_mesh = false;
+    c->opf.release();
+    c->lgeof.release();
+    c->coeff.release();
     c->permuted = false;
     c->perm_h.clear();
     if (n_cells <= 0 || n_nodes <= 0 || n_cells > INT32_MAX / 2 || n_nodes > INT32_MAX)
@@ -515,6 +519,7 @@ cgks_status cgks_set_mesh(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64
     c->n_params = 0;
     c->pdir_prim.clear();
     c->pdir_xyz.clear();
+    if (c->prm.precision == 1) ensure_fp32_front(c);
     API_END(c)
 }
 
@@ -605,10 +610,11 @@ cgks_status cgks_residual(cgks_ctx *c, const double *W, const double *G, const d
     need_bc(c);
     if (!W || !G || !R || (G_new == nullptr) != (alpha_new == nullptr))
         throw Error{CGKS_E_ARG, "W, G, R required; G_new and alpha_new both or neither"};
+    const bool fp32 = c->prm.precision == 1;
     launch_local_dt_recon(c, cells_in(c, W, 5, 0), cells_in(c, G, 15, 1), cells_in(c, alpha, 1, 2), c->dtc.p,
-                          c->coef.p);
+                          c->coef.p, nullptr, fp32 ? c->coeff.p : nullptr);
     const int mode = G_new ? MODE_RES : MODE_RESONLY;
-    launch_face(c, mode, c->coef.p, c->dtc.p, -1.0, c->prm.precision == 1);
+    launch_face(c, mode, c->coef.p, c->dtc.p, -1.0, fp32);
     launch_gather_res(c, cells_buf(c, R, 5, 3), cells_buf(c, G_new, 15, 4), cells_buf(c, alpha_new, 1, 5), mode);
     cells_out(c, R, 5, 3);
     cells_out(c, G_new, 15, 4);
@@ -659,8 +665,11 @@ cgks_status cgks_residual_noalloc(cgks_ctx *c, const double *W, const double *G,
         gn = G_new ? out + 5 * N : nullptr;
         an = alpha_new ? out + 20 * N : nullptr;
     }
-    launch_local_dt_recon(c, w, g, a, dtc, coef, bgq);
-    launch_face(c, mode, coef, dtc, -1.0, c->prm.precision == 1, rec);
+    // FP32 flux: FP32 coefficients in the same piece of the work array (50 N floats)
+    const bool fp32 = c->prm.precision == 1;
+    float *coef32 = fp32 ? reinterpret_cast<float *>(coef) : nullptr;
+    launch_local_dt_recon(c, w, g, a, dtc, coef, bgq, coef32);
+    launch_face(c, mode, coef, dtc, -1.0, fp32, rec, coef32);
     launch_gather_res(c, r, gn, an, mode, rec);
     if (moved) {
         cells_scatter(c, (const double *)out, R, 5);

@@ -1460,14 +1460,15 @@ void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flu
     const int nb = gather_blocks(c->N);
     c->partial.ensure(nb);
     const int npre = std::max(1, c->prm.nu_pre[0]);
+    float *c32 = fp32_flux ? c->coeff.p : nullptr;  // FP32 coefficients in the FP32 flux phase
     for (int s = 0; s < npre; ++s) {
-        launch_local_dt_recon(c, W, G, alpha, c->dtc.p, c->coef.p);
+        launch_local_dt_recon(c, W, G, alpha, c->dtc.p, c->coef.p, nullptr, c32);
         launch_face(c, MODE_RES, c->coef.p, c->dtc.p, -1.0, fp32_flux);
         launch_gather_fe(c, W, G, alpha, c->dtc.p, c->Rw.p, s == 0 ? c->partial.p : nullptr);
         if (s == 0) finish_norm(c, c->partial.p, nb, c->N, norm_out);
     }
     if (c->lev.size() > 1) {
-        launch_local_dt_recon(c, W, G, alpha, c->dtc.p, c->coef.p);
+        launch_local_dt_recon(c, W, G, alpha, c->dtc.p, c->coef.p, nullptr, c32);
         launch_face(c, MODE_RESONLY, c->coef.p, c->dtc.p, -1.0, fp32_flux);
         launch_gather_res(c, c->Rw.p, nullptr, nullptr, MODE_RESONLY);
         Level *L = c->lev[1];
@@ -1488,7 +1489,7 @@ void vcycle_once(cgks_ctx *c, double *W, double *G, double *alpha, bool fp32_flu
         }
     }
     for (int s = 0; s < c->prm.nu_post[0]; ++s) {
-        launch_local_dt_recon(c, W, G, alpha, c->dtc.p, c->coef.p);
+        launch_local_dt_recon(c, W, G, alpha, c->dtc.p, c->coef.p, nullptr, c32);
         launch_face(c, MODE_RES, c->coef.p, c->dtc.p, -1.0, fp32_flux);
         launch_gather_fe(c, W, G, alpha, c->dtc.p, c->Rw.p, nullptr);
     }

@@ -198,7 +198,8 @@ struct cgks_ctx {
     cgks::DBuf<cgks::BcTable> bc;
     // work buffers
     cgks::DBuf<double> coef, dtc, fout, Rw, Gw, aw, Ws, Gs, L1, Lt1, Gc1, partial, scal;
-    cgks::DBuf<float> coeff32;
+    // mixed precision: FP32 copies of op and lgeo, FP32 cell-major coefficients (ensure_fp32_front)
+    cgks::DBuf<float> opf, lgeof, coeff;
     cgks::DBuf<int32_t> bad;
     // multigrid hierarchy; lev[0] is a placeholder for the fine level
     std::vector<cgks::Level *> lev;
@@ -234,15 +235,21 @@ void launch_local_dt(cgks_ctx *c, const double *W, double *dt);
 // cell-major: coef[50 i + 10 c + k], else coef[(10 c + k) N + i]; ghosts_ready: the boundary
 // ghost states at W are already in bgq
 // bgq: where the boundary ghost states go (nullptr: the context's buffer)
+// coef32: write FP32 cell-major coefficients there instead, from the FP32 operator copy (the
+// mixed-precision flux phase; coef is then unused)
 void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef,
-                  bool cell_major = true, bool ghosts_ready = false, double *bgq = nullptr);
+                  bool cell_major = true, bool ghosts_ready = false, double *bgq = nullptr, float *coef32 = nullptr);
 // launch_local_dt + launch_recon (cell-major) with the ghost states formed in the local-step launch
 void launch_local_dt_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *dt,
-                           double *coef, double *bgq = nullptr);
+                           double *coef, double *bgq = nullptr, float *coef32 = nullptr);
 enum FaceMode { MODE_RES = 0, MODE_RESONLY = 1, MODE_S1 = 2, MODE_S2 = 3 };
 // out: face records (nullptr: the context's buffer; a launch with its own buffer is never timed)
+// fp32: the per-point evaluation in FP32 from coef32 (nullptr: the context's FP32 coefficients)
 void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cell, double dt_global, bool fp32,
-                 double *out = nullptr);
+                 double *out = nullptr, const float *coef32 = nullptr);
+// FP32 copies of the reconstruction operator and the lane geometry, and the FP32 coefficient
+// buffer, made once per mesh when the mixed precision is first selected
+void ensure_fp32_front(cgks_ctx *c);
 void launch_gather_res(cgks_ctx *c, double *R, double *Gn, double *an, int mode, const double *fout = nullptr);
 void launch_gather_fe(cgks_ctx *c, double *W, double *G, double *alpha, const double *dt, double *Rout, double *norm_part);
 void launch_gather_s2o4(cgks_ctx *c, int stage, double dt, double *W, double *G, double *alpha);

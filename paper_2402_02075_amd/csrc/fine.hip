@@ -124,9 +124,15 @@ __device__ __forceinline__ void recon_gg_boundary(const ReconArgs &A, int64_t i,
     }
 }
 
-template <bool CELL_MAJOR> __global__ __launch_bounds__(320) void k_recon(ReconArgs A)
+// TS: storage type of the operator entries and of the coefficients written (double, or float in
+// the mixed-precision flux phase, which halves the two largest streams); the arithmetic is FP64.
+template <class TS> __device__ __forceinline__ const TS *recon_op(const ReconArgs &A);
+template <> __device__ __forceinline__ const double *recon_op<double>(const ReconArgs &A) { return A.op; }
+template <> __device__ __forceinline__ const float *recon_op<float>(const ReconArgs &A) { return A.opf; }
+
+template <bool CELL_MAJOR, class TS = double> __global__ __launch_bounds__(320) void k_recon(ReconArgs A)
 {
-    __shared__ double sop[OP_PER_NB * OP_GROUP];
+    __shared__ TS sop[OP_PER_NB * OP_GROUP];
     const int lane = threadIdx.x & (OP_GROUP - 1);
     const int C = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform over a wave
     const int64_t N = A.N;
@@ -153,7 +159,7 @@ template <bool CELL_MAJOR> __global__ __launch_bounds__(320) void k_recon(ReconA
 #pragma unroll
     for (int k = 0; k < 9; ++k) a[k] = 0.0;
     const int gnb = A.gnb[blockIdx.x], gmax = A.gmax[blockIdx.x];
-    const double *gop = A.op + A.gbase[blockIdx.x];
+    const TS *gop = recon_op<TS>(A) + A.gbase[blockIdx.x];
     int nb_next = (live && nint > 0) ? A.inb[i] : 0;
     for (int m = 0; m < gmax; ++m) {
         const bool use = live && m < nint;
@@ -169,19 +175,23 @@ template <bool CELL_MAJOR> __global__ __launch_bounds__(320) void k_recon(ReconA
             gz = A.G[(3 * C + 2) * N + nb];
         }
         if (m < gnb) {
-            // 2,496 entries over 320 threads: all eight loads in flight before the stores
-            const double *src = gop + (int64_t)OP_GROUP * OP_PER_NB * m;
-            constexpr int NT = 5 * OP_GROUP, NE = OP_PER_NB * OP_GROUP, NR = (NE + NT - 1) / NT;
-            double v[NR];
+            // 2,496 entries over 320 threads in 8-byte units (one double or two floats; group
+            // bases are multiples of 64 entries): all loads in flight before the stores
+            using U = typename std::conditional<sizeof(TS) == 8, double, float2>::type;
+            const U *src = reinterpret_cast<const U *>(gop + (int64_t)OP_GROUP * OP_PER_NB * m);
+            U *dst = reinterpret_cast<U *>(sop);
+            constexpr int NT = 5 * OP_GROUP, NE = OP_PER_NB * OP_GROUP * (int)sizeof(TS) / 8,
+                          NR = (NE + NT - 1) / NT;
+            U v[NR];
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 const int t = threadIdx.x + r * NT;
-                v[r] = t < NE ? src[t] : 0.0;
+                v[r] = t < NE ? src[t] : U{};
             }
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 const int t = threadIdx.x + r * NT;
-                if (t < NE) sop[t] = v[r];
+                if (t < NE) dst[t] = v[r];
             }
         }
         __syncthreads();
@@ -191,13 +201,13 @@ template <bool CELL_MAJOR> __global__ __launch_bounds__(320) void k_recon(ReconA
         }
         if (p2) {
             const double e = qm - q0;
-            const double *o = sop + lane;
+            const TS *o = sop + lane;
 #pragma unroll
             for (int k = 0; k < 9; ++k)
-                a[k] += o[OP_GROUP * k] * e + o[OP_GROUP * (9 + 3 * k)] * gx + o[OP_GROUP * (10 + 3 * k)] * gy +
-                        o[OP_GROUP * (11 + 3 * k)] * gz;
+                a[k] += double(o[OP_GROUP * k]) * e + double(o[OP_GROUP * (9 + 3 * k)]) * gx +
+                        double(o[OP_GROUP * (10 + 3 * k)]) * gy + double(o[OP_GROUP * (11 + 3 * k)]) * gz;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) gl[d] += o[OP_GROUP * (36 + d)] * e;
+            for (int d = 0; d < 3; ++d) gl[d] += double(o[OP_GROUP * (36 + d)]) * e;
         }
         __syncthreads();
     }
@@ -256,10 +266,15 @@ template <bool CELL_MAJOR> __global__ __launch_bounds__(320) void k_recon(ReconA
 #pragma unroll
         for (int k = 3; k < 9; ++k) r[1 + k] = c2 * a[k];
     }
+    if constexpr (sizeof(TS) == 4) {
 #pragma unroll
-    for (int k = 0; k < 10; ++k) {
-        if (CELL_MAJOR) A.coef[i * 50 + 10 * C + k] = r[k];
-        else A.coef[(10 * C + k) * N + i] = r[k];
+        for (int k = 0; k < 10; ++k) A.coeff[i * 50 + 10 * C + k] = float(r[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            if (CELL_MAJOR) A.coef[i * 50 + 10 * C + k] = r[k];
+            else A.coef[(10 * C + k) * N + i] = r[k];
+        }
     }
 }
 
@@ -269,21 +284,23 @@ struct FaceArgs {
     GksCfg cfg;
     double dt_global;
     const double *coef, *dtc;
+    const float *coeff;  // FP32 coefficients (FP32 flux)
     const int4 *lidx;    // per lane {4 f + k, L, R, 8 tag + ngp}, f = -1 idle
     const double *lgeo;  // per lane dx_L, dx_R, n, w S ([10][NL])
+    const float *lgeof;  // the same in FP32 (FP32 flux)
     int64_t NL;
     const BcTable *bc;
     double *out;  // [F][nq], face-major
     int32_t *bad;
 };
 
-__device__ __forceinline__ void eval_poly(const double *__restrict__ coef, int64_t cell, const double dx[3],
-                                          double w[5], double g[15])
+template <class T>
+__device__ __forceinline__ void eval_poly(const T *__restrict__ coef, int64_t cell, const T dx[3], T w[5], T g[15])
 {
-    const double *cc = coef + cell * 50;  // cell-major: 10 coefficients per component
+    const T *cc = coef + cell * 50;  // cell-major: 10 coefficients per component
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-        double r[10];
+        T r[10];
 #pragma unroll
         for (int k = 0; k < 10; ++k) r[k] = cc[10 * c + k];
         poly_eval(r, dx, w[c], &g[3 * c]);
@@ -306,8 +323,14 @@ __device__ __forceinline__ double face_prod(double v, int ln, int ngp)
 // The work of one lane: its face's Gauss point k, given the lane's indices and geometry.
 // FOLD: 0 = moment vectors then combination (all modes), 1 = time coefficients folded into the
 // moment sums, inviscid, 2 = folded, viscous (steady modes only).
+// T is the type of the whole per-point evaluation: polynomials, rotations, flux and compression
+// factor (FP32 reads FP32 coefficients and lane geometry); the face sums are FP64.
+template <class T> __device__ __forceinline__ const T *face_coef(const FaceArgs &A);
+template <> __device__ __forceinline__ const double *face_coef<double>(const FaceArgs &A) { return A.coef; }
+template <> __device__ __forceinline__ const float *face_coef<float>(const FaceArgs &A) { return A.coeff; }
+
 template <class T, int MODE, bool VAL, int FOLD>
-__device__ __forceinline__ void face_lane(const FaceArgs &A, const int4 id, const double g[10], int ln)
+__device__ __forceinline__ void face_lane(const FaceArgs &A, const int4 id, const T g[10], int ln)
 {
     const int64_t N = A.N;
     const bool act = id.x >= 0;
@@ -321,24 +344,25 @@ __device__ __forceinline__ void face_lane(const FaceArgs &A, const int4 id, cons
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     double alpha_k = 1.0;
     if (act) {
-        const double n[3] = {g[6], g[7], g[8]};
+        const T n[3] = {g[6], g[7], g[8]};
         const double wS = g[9];
         double dtf = A.dt_global;
         if (dtf <= 0.0) dtf = R >= 0 ? fmin(A.dtc[L], A.dtc[R]) : A.dtc[L];
-        double WL[5], GL[15], WR[5], GR[15];
+        T WL[5], GL[15], WR[5], GR[15];
         {
-            const double dx[3] = {g[0], g[1], g[2]};
-            eval_poly(A.coef, L, dx, WL, GL);
+            const T dx[3] = {g[0], g[1], g[2]};
+            eval_poly<T>(face_coef<T>(A), L, dx, WL, GL);
         }
         if (R >= 0) {
-            const double dx[3] = {g[3], g[4], g[5]};
-            eval_poly(A.coef, R, dx, WR, GR);
+            const T dx[3] = {g[3], g[4], g[5]};
+            eval_poly<T>(face_coef<T>(A), R, dx, WR, GR);
         } else {
             const int tag = id.w >> 3;
-            ghost_state(*A.bc, tag, n, WL, A.cfg.gamma, WR);
-            ghost_grad(*A.bc, tag, n, GL, GR);
+            const double nd[3] = {n[0], n[1], n[2]};
+            ghost_state(*A.bc, tag, nd, WL, A.cfg.gamma, WR);
+            ghost_grad(*A.bc, tag, nd, GL, GR);
         }
-        double t1[3], t2[3];
+        T t1[3], t2[3];
         onb(n, t1, t2);
         T wl[5], wr[5], gl[3][5], gr[3][5];
         to_local(WL, GL, n, t1, t2, wl, gl);
@@ -350,19 +374,22 @@ __device__ __forceinline__ void face_lane(const FaceArgs &A, const int4 id, cons
                                                                 A.cfg, Fl, Wt, pl, pr)) {
                 atomicMin(A.bad, L);
             } else {
-                double Fg[5];
+                T Fg[5];
                 to_global(Fl, n, t1, t2, Fg);
                 const double s = wS / dtf;
 #pragma unroll
-                for (int q = 0; q < 5; ++q) acc[q] = s * Fg[q];
+                for (int q = 0; q < 5; ++q) acc[q] = s * double(Fg[q]);
                 if (MODE == MODE_RES) {
-                    double Wg[5];
+                    T Wg[5];
                     to_global(Wt, n, t1, t2, Wg);
 #pragma unroll
                     for (int q = 0; q < 5; ++q)
 #pragma unroll
-                        for (int d = 0; d < 3; ++d) acc[5 + 3 * q + d] = wS * Wg[q] * n[d];
-                    if (R >= 0) alpha_k = cf_factor(wl, wr, double(pl), double(pr), A.cfg.gamma);
+                        for (int d = 0; d < 3; ++d) acc[5 + 3 * q + d] = wS * double(Wg[q]) * double(n[d]);
+                    if (R >= 0) {
+                        if constexpr (sizeof(T) == 8) alpha_k = cf_factor(wl, wr, double(pl), double(pr), A.cfg.gamma);
+                        else alpha_k = double(cf_factor(wl, wr, pl, pr, T(A.cfg.gamma)));
+                    }
                 }
             }
         } else {
@@ -450,9 +477,14 @@ template <class T, int MODE, bool VAL, int FOLD> __device__ __forceinline__ void
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t NL = A.NL;
     const int4 id = A.lidx[gid];  // the grid covers the padded lane map exactly
-    double g[10];
+    T g[10];
+    if constexpr (sizeof(T) == 4) {
 #pragma unroll
-    for (int q = 0; q < 10; ++q) g[q] = A.lgeo[q * NL + gid];
+        for (int q = 0; q < 10; ++q) g[q] = A.lgeof[q * NL + gid];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 10; ++q) g[q] = A.lgeo[q * NL + gid];
+    }
     face_lane<T, MODE, VAL, FOLD>(A, id, g, (int)(threadIdx.x & 63));
 }
 
@@ -729,18 +761,37 @@ void launch_local_dt(cgks_ctx *c, const double *W, double *dt)
 }
 
 void launch_local_dt_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *dt,
-                           double *coef, double *bgq)
+                           double *coef, double *bgq, float *coef32)
 {
     const int64_t Fb = c->F - c->Fi;
     if (!bgq) bgq = c->bgq.p;
     hipLaunchKernelGGL(k_local_dt_ghost, dim3(blocks_for(c->N + Fb, 256)), dim3(256), 0, c->stream, c->N, c->F, c->Fi,
                        c->prm.gamma, c->prm.cfl, c->prm.mu, c->prm.viscous, W, c->cf_ptr.p, c->cf_face.p, c->favec.p,
                        c->farea.p, c->vol.p, dt, c->fl.p, c->ftag.p, c->bc.p, bgq);
-    launch_recon(c, W, G, alpha, coef, true, true, bgq);
+    launch_recon(c, W, G, alpha, coef, true, true, bgq, coef32);
+}
+
+__global__ void k_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = float(a[i]);
+}
+
+void ensure_fp32_front(cgks_ctx *c)
+{
+    if (!c->has_mesh || c->opf.p) return;
+    c->opf.alloc(c->op.n);
+    c->lgeof.alloc(10 * c->NL);
+    c->coeff.alloc(50 * c->N);
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(c->op.n, 256)), dim3(256), 0, c->stream, (int64_t)c->op.n, c->op.p,
+                       c->opf.p);
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(10 * c->NL, 256)), dim3(256), 0, c->stream, 10 * c->NL, c->lgeo.p,
+                       c->lgeof.p);
+    CGKS_HIP(hipGetLastError());
 }
 
 void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *alpha, double *coef, bool cell_major,
-                  bool ghosts_ready, double *bgq)
+                  bool ghosts_ready, double *bgq, float *coef32)
 {
     if (!bgq) bgq = c->bgq.p;
     ReconArgs A{};
@@ -761,6 +812,8 @@ void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *a
     A.op_off = c->op_off.p;
     A.bc = c->bc.p;
     A.coef = coef;
+    A.opf = c->opf.p;
+    A.coeff = coef32;
     A.gbase = c->op_gbase.p;
     A.gnb = c->op_gnb.p;
     A.gmax = c->op_gmax.p;
@@ -775,12 +828,18 @@ void launch_recon(cgks_ctx *c, const double *W, const double *G, const double *a
         hipLaunchKernelGGL(k_bnd_ghost, dim3(blocks_for(A.Fb, 256)), dim3(256), 0, c->stream, c->N, c->F, c->Fi, W,
                            c->fl.p, c->ftag.p, c->favec.p, c->bc.p, c->prm.gamma, bgq);
     const dim3 grid(blocks_for(c->N, OP_GROUP)), blk(5 * OP_GROUP);
-    if (cell_major) hipLaunchKernelGGL((k_recon<true>), grid, blk, 0, c->stream, A);
-    else hipLaunchKernelGGL((k_recon<false>), grid, blk, 0, c->stream, A);
+    if (coef32) {
+        if (!c->opf.p) throw Error{CGKS_E_STATE, "FP32 reconstruction without its operator copy"};
+        hipLaunchKernelGGL((k_recon<true, float>), grid, blk, 0, c->stream, A);
+    } else if (cell_major) {
+        hipLaunchKernelGGL((k_recon<true>), grid, blk, 0, c->stream, A);
+    } else {
+        hipLaunchKernelGGL((k_recon<false>), grid, blk, 0, c->stream, A);
+    }
 }
 
 void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cell, double dt_global, bool fp32,
-                 double *out)
+                 double *out, const float *coef32)
 {
     FaceArgs A;
     A.N = c->N;
@@ -791,6 +850,9 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
     A.dtc = dt_cell;
     A.lidx = c->lidx.p;
     A.lgeo = c->lgeo.p;
+    A.coeff = coef32 ? coef32 : c->coeff.p;
+    A.lgeof = c->lgeof.p;
+    if (fp32 && !c->lgeof.p) throw Error{CGKS_E_STATE, "FP32 flux without its lane geometry copy"};
     A.NL = c->NL;
     A.bc = c->bc.p;
     A.out = out ? out : c->fout.p;

@@ -30,6 +30,8 @@ struct ReconArgs {
     const double *bgq;      // [5][Fb] ghost states of the boundary faces at W (face ids Fi..F-1)
     int64_t Fi, Fb;
     double *coef;
+    const float *opf;  // FP32 copy of op (FP32 storage instantiation)
+    float *coeff;      // FP32 cell-major coefficients (FP32 storage instantiation)
 };
 
 // Operator entries of one interior neighbour m of a cell, 39 per neighbour: 9 multiply the

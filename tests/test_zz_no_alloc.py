@@ -3,7 +3,8 @@
 cgks_residual_noalloc runs the same kernels as cgks_residual with its work memory in the
 library's fixed device array instead of the context's buffers: its outputs must be bit-identical,
 on two calls in a row where the second has a smaller mesh (the array keeps the first call's
-contents), in both cell-order modes at the ABI and with and without the gradient update; a mesh
+contents), in both cell-order modes at the ABI, with and without the gradient update, and with the
+FP64 and the FP32 flux (whose FP32 coefficients share the array's coefficient piece); a mesh
 whose work memory exceeds the array is rejected before any work.
 """
 import numpy as np
@@ -30,8 +31,8 @@ def cg(torch):
     return cgks
 
 
-def _case(cg, torch, m, order, seed):
-    S = cg.Solver(cell_order=order)
+def _case(cg, torch, m, order, seed, precision=0):
+    S = cg.Solver(cell_order=order, precision=precision)
     S.set_mesh(m)
     channel_bcs(S.set_bc, cg.BC_FARFIELD, cg.BC_SLIP)
     x = mg.cell_node_mean(m)
@@ -42,13 +43,14 @@ def _case(cg, torch, m, order, seed):
     return S, to_dev(torch, W), to_dev(torch, G), to_dev(torch, al)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("order", [1, 2])
-def test_noalloc_residual_equals_residual(cg, torch, order):
+def test_noalloc_residual_equals_residual(cg, torch, order, precision):
     big = mg.bump_channel(20, 10, 6, n_prism=2, n_pyr=3, jitter=0.05, seed=2, amp=0.05)
     small = mg.bump_channel(12, 4, 2, n_prism=1, n_pyr=1, jitter=0.05, seed=3, amp=0.05)
     for m, seed in ((big, 1), (small, 2)):
-        say(f"[gpu] no-allocation residual, cell_order {order}, {m.n_cells} cells")
-        S, W, G, al = _case(cg, torch, m, order, seed)
+        say(f"[gpu] no-allocation residual, cell_order {order}, precision {precision}, {m.n_cells} cells")
+        S, W, G, al = _case(cg, torch, m, order, seed, precision)
         N = m.n_cells
         R, Gn, an = S.residual(W, G, al)
         R2, Gn2, an2 = S.residual_noalloc(W, G, al, Gn=S.empty(15, N), an=S.empty(N))
