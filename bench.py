@@ -450,17 +450,22 @@ def adjoint_check(torch, cg, mg):
     return out
 
 
-def long_run(torch, cg, mg, name, cycles, chunk=1000):
-    """FP64 then mixed V-cycles from the free stream on one sphere mesh, `cycles` each, with the drop,
-    minimum drop and drag every `chunk` cycles, then the mixed run's density-field and drag
-    differences from the FP64 run (a long convergence record, not part of the default run)."""
+def long_run(torch, cg, mg, name, cycles, compare="precision", chunk=1000):
+    """Two runs of V-cycles from the free stream on one sphere mesh, `cycles` each, with the drop,
+    minimum drop and drag every `chunk` cycles, then the second run's density-field and drag
+    differences from the first (a long convergence record, not part of the default run).
+    compare = "precision": FP64 then mixed; "smoother": explicit then implicit coarse sweeps
+    (Sec. 4.3), both FP64."""
     spec = {"sphere6M": (6, 33, 12), "sphere1p47M": (5, 32, 12)}[name]
     m, S, sizes, setup = sphere_solver(cg, mg, *spec)
     N = m.n_cells
-    out = {"long_run": name, "cells": N, "level_cells": [int(x) for x in sizes], "cycles": cycles}
+    out = {"long_run": name, "compare": compare, "cells": N, "level_cells": [int(x) for x in sizes],
+           "cycles": cycles}
     ref = None
-    for prec, key in ((0, "fp64"), (1, "mixed")):
-        S.set_params(precision=prec)
+    runs = ((dict(precision=0), "fp64"), (dict(precision=1), "mixed")) if compare == "precision" else \
+        ((dict(coarse_smoother=0), "explicit"), (dict(coarse_smoother=1), "implicit"))
+    for par, key in runs:
+        S.set_params(**par)
         W, G, al = free_stream(torch, mg, N, (0.2, 0.0, 0.0))
         hs, cps, done = [], [], 0
         torch.cuda.synchronize()
@@ -480,10 +485,150 @@ def long_run(torch, cg, mg, name, cycles, chunk=1000):
             ref = (W[0].clone(), cd)
         else:
             d = W[0] - ref[0]
-            out["mixed_vs_fp64"] = {"density_l2": float(torch.sqrt((d * d).mean())),
-                                    "density_max": float(d.abs().max()), "Cd_diff": cd - ref[1],
-                                    "Cd_rel": (cd - ref[1]) / ref[1]}
+            out[f"{key}_vs_{runs[0][1]}"] = {"density_l2": float(torch.sqrt((d * d).mean())),
+                                             "density_max": float(d.abs().max()), "Cd_diff": cd - ref[1],
+                                             "Cd_rel": (cd - ref[1]) / ref[1]}
         del W, G, al
+    S.close()
+    return out
+
+
+def _omp_threads(n):
+    import ctypes
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
+def _oracle_eval_s(M, par, W, G, al, samples=3):
+    ts = []
+    for k in range(samples):
+        t0 = time.perf_counter()
+        M.residual(par, W, G, al)
+        ts.append(time.perf_counter() - t0)
+        log(f"    oracle residual sample {k}: {ts[-1]:.2f} s")
+    return float(np.median(ts))
+
+
+def oracle_timing(torch, cg, mg, which):
+    """The CPU oracle as it stands, timed on this host: per-residual time on each configuration
+    mesh at a developed state (200 GPU V-cycles from the free stream, median of 3 evaluations,
+    all threads and, where it fits, one thread); the periodic density-wave configuration run
+    through on both sides; 100 oracle V-cycles against the GPU's on a ~24k-cell bump channel.
+    which = "small" (those) or "sphere6M" (the per-residual time on the 6.14M-cell sphere)."""
+    import oracle as om
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out = {"oracle_timing": which, "threads": threads, "host_cpus": os.cpu_count()}
+    visc = om.params(viscous=True, mu=2e-3, prandtl=0.72)
+    inv = om.params()
+
+    def developed(S, m, vel, cycles=200):
+        W, G, al = free_stream(torch, mg, m.n_cells, vel)
+        S.vcycle(W, G, al, cycles, 0.0)
+        return W.cpu().numpy(), G.cpu().numpy(), al.cpu().numpy()
+
+    def sphere_oracle(m):
+        M = om.Mesh(m)
+        M.set_bc(mg.TAG_SPHERE, om.BC_NOSLIP)
+        M.set_bc(mg.TAG_FARFIELD, om.BC_FARFIELD, np.array([1.0, 0.2, 0.0, 0.0, 1.0 / 1.4]))
+        return M
+
+    def channel_oracle(m):
+        M = om.Mesh(m)
+        prim = np.array([1.0, 0.5, 0.0, 0.0, 1.0 / 1.4])
+        for tag in (mg.TAG_INLET, mg.TAG_OUTLET):
+            M.set_bc(tag, om.BC_FARFIELD, prim)
+        for tag in (mg.TAG_WALL_BOTTOM, mg.TAG_WALL_TOP, mg.TAG_WALL_SIDE):
+            M.set_bc(tag, om.BC_SLIP)
+        return M
+
+    if which == "sphere6M":
+        m, S, _, _ = sphere_solver(cg, mg, 6, 33, 12, cell_order=1)
+        W, G, al = developed(S, m, (0.2, 0.0, 0.0))
+        S.close()
+        t0 = time.perf_counter()
+        M = sphere_oracle(m)
+        log(f"sphere6M oracle mesh set-up {time.perf_counter() - t0:.1f} s")
+        out["sphere6M"] = {"cells": m.n_cells, "residual_s_all_threads": _oracle_eval_s(M, visc, W, G, al)}
+        return out
+
+    # periodic density wave, 8^3 hexahedra: 100 two-stage fourth-order steps at CFL 0.5
+    n = 8
+    m = mg.periodic_hex_cube(n)
+    M = om.Mesh(m)
+    W0, G0 = mg.density_wave_averages(n)
+    al0 = np.ones(m.n_cells)
+    dt = float(M.local_dt(inv, W0).min())
+    W, G, al = W0.copy(), G0.copy(), al0.copy()
+    t0 = time.perf_counter()
+    for _ in range(100):
+        M.step_s2o4(inv, dt, W, G, al)
+    t_or = time.perf_counter() - t0
+    S = cg.Solver()
+    S.set_mesh(m)
+    Wd, Gd, ad = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (W0, G0, al0))
+    S.step(Wd, Gd, ad, dt)
+    Wd, Gd, ad = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (W0, G0, al0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(100):
+        S.step(Wd, Gd, ad, dt)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    We, _ = mg.density_wave_averages(n, T=100 * dt)
+    out["density_wave_8cube_100_steps"] = {
+        "oracle_s": t_or, "gpu_s": t_gpu, "oracle_L1_rho_error": float(np.abs(W[0] - We[0]).mean()),
+        "gpu_L1_rho_error": float(np.abs(Wd.cpu().numpy()[0] - We[0]).mean()),
+        "gpu_vs_oracle_max_state_diff": float(np.abs(Wd.cpu().numpy() - W).max())}
+    log(f"density wave: oracle {t_or:.2f} s, GPU {t_gpu:.3f} s")
+    S.close()
+    per = {"density_wave_8cube": {"cells": m.n_cells}}
+    per["density_wave_8cube"]["residual_s_all_threads"] = _oracle_eval_s(M, inv, W0, G0, al0)
+    _omp_threads(1)
+    per["density_wave_8cube"]["residual_s_one_thread"] = _oracle_eval_s(M, inv, W0, G0, al0)
+    _omp_threads(threads)
+    # bump channel (189k mixed cells), inviscid
+    m = mg.bump_channel()
+    S, _, _ = channel_solver(cg, mg, m, cell_order=1)
+    W, G, al = developed(S, m, (0.5, 0.0, 0.0))
+    S.close()
+    M = channel_oracle(m)
+    per["bump_channel_189k"] = {"cells": m.n_cells, "residual_s_all_threads": _oracle_eval_s(M, inv, W, G, al)}
+    _omp_threads(1)
+    per["bump_channel_189k"]["residual_s_one_thread"] = _oracle_eval_s(M, inv, W, G, al)
+    _omp_threads(threads)
+    del M
+    # sphere, 1.47M cells, viscous
+    m, S, _, _ = sphere_solver(cg, mg, 5, 32, 12, cell_order=1)
+    W, G, al = developed(S, m, (0.2, 0.0, 0.0))
+    S.close()
+    M = sphere_oracle(m)
+    per["sphere_1p47M"] = {"cells": m.n_cells, "residual_s_all_threads": _oracle_eval_s(M, visc, W, G, al)}
+    del M
+    out["per_residual"] = per
+    # a 24k-cell bump channel: 100 V-cycles from the free stream on both sides
+    m = mg.bump_channel(48, 16, 8, n_prism=2, n_pyr=4)
+    S, _, _ = channel_solver(cg, mg, m, cell_order=1)
+    M = channel_oracle(m)
+    H = om.Hierarchy(M, levels=3, passes=3, seed=1)
+    W0, G0 = mg.uniform_state(m.n_cells)
+    Wd, Gd, ad = free_stream(torch, mg, m.n_cells, (0.5, 0.0, 0.0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hg, _ = S.vcycle(Wd, Gd, ad, 100, 0.0)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    W, G, al = W0.copy(), G0.copy(), np.ones(m.n_cells)
+    ho = []
+    t0 = time.perf_counter()
+    for k in range(100):
+        ho.append(H.vcycle(inv, W, G, al))
+        if k % 25 == 24:
+            log(f"    oracle V-cycle {k + 1}: {time.perf_counter() - t0:.1f} s")
+    t_or = time.perf_counter() - t0
+    hg, ho = np.asarray(hg), np.asarray(ho)
+    out["bump_channel_24k_100_vcycles"] = {
+        "cells": m.n_cells, "oracle_s": t_or, "gpu_s": t_gpu, "oracle_drop": float(ho[-1] / ho[0]),
+        "gpu_drop": float(hg[-1] / hg[0]), "history_max_rel_diff": float(np.abs(hg / ho - 1.0).max()),
+        "state_max_rel_diff": float((np.abs(Wd.cpu().numpy() - W).max(1) / np.abs(W).max(1)).max())}
     S.close()
     return out
 
@@ -528,7 +673,11 @@ def main():
     ap.add_argument("--headline-only", action="store_true", help="only the headline workload (profiling)")
     ap.add_argument("--long-run", choices=("sphere6M", "sphere1p47M"),
                     help="instead of the benchmark: FP64 and mixed V-cycles from the free stream on that sphere")
-    ap.add_argument("--cycles", type=int, default=8000, help="V-cycles per precision of --long-run")
+    ap.add_argument("--cycles", type=int, default=8000, help="V-cycles per run of --long-run")
+    ap.add_argument("--compare", choices=("precision", "smoother"), default="precision",
+                    help="--long-run pair: FP64 and mixed, or explicit and implicit coarse sweeps")
+    ap.add_argument("--oracle-timing", choices=("small", "sphere6M"),
+                    help="instead of the benchmark: the CPU oracle timed on the configuration meshes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="a plain 1 GiB fill and copy first (known bytes for scaling the HBM counters)")
     args = ap.parse_args()
@@ -541,7 +690,10 @@ def main():
     from paper_2402_02075_amd import meshgen as mg
     torch.cuda.set_device(0)
     if args.long_run:
-        print(json.dumps(long_run(torch, cg, mg, args.long_run, args.cycles)))
+        print(json.dumps(long_run(torch, cg, mg, args.long_run, args.cycles, args.compare)))
+        return
+    if args.oracle_timing:
+        print(json.dumps(oracle_timing(torch, cg, mg, args.oracle_timing)))
         return
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
