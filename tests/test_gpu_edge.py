@@ -110,7 +110,7 @@ def test_nonphysical_state_is_reported_then_cleared(cg, torch):
 def test_ragged_group_tail_matches_oracle(oracle, cg, torch):
     """130 cells: two full 64-cell reconstruction groups and a two-cell tail group, lane-map waves
     partly idle; the residual agrees with the oracle as on the larger meshes."""
-    from gpu_common import assert_residual_close, cell_surface, flux_scale
+    from gpu_common import assert_residual_close, cell_flux_bound
     m = mg.bump_channel(13, 5, 2, n_prism=0, n_pyr=0)
     assert m.n_cells == 130
     say(f"[gpu] edge: ragged tail cells={m.n_cells}")
@@ -128,8 +128,7 @@ def test_ragged_group_tail_matches_oracle(oracle, cg, torch):
     R, Gn, an = (t.cpu().numpy() for t in S.residual(to_dev(torch, W), to_dev(torch, G), to_dev(torch, al)))
     S.check()
     oR, oGn, oan, _ = M.residual(oracle.params(), W, G, al)
-    F = M.faces()
-    assert_residual_close(R, oR, cell_surface(F, m.n_cells), flux_scale(W), what="R ragged")
+    assert_residual_close(R, oR, cell_flux_bound(W, M.faces(), m.n_cells), what="R ragged")
     np.testing.assert_allclose(an, oan, rtol=1e-10, atol=1e-14)
 
 

@@ -11,7 +11,7 @@ import pytest
 
 from paper_2402_02075_amd import meshgen as mg
 
-from gpu_common import assert_residual_close, cell_surface, channel_bcs, flux_scale, say, to_dev
+from gpu_common import assert_residual_close, cell_flux_bound, cell_surface, channel_bcs, flux_scale, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -125,12 +125,12 @@ def test_residual(oracle, cg, torch, name, wall, par):
     oR, oGn, oan, _ = M.residual(opar, W, G, alpha)
     F = M.faces()
     surf = cell_surface(F, M.n_cells)
-    fs = flux_scale(W)
-    assert_residual_close(R, oR, surf, fs, what="R")
+    bnd = cell_flux_bound(W, F, M.n_cells)
+    assert_residual_close(R, oR, bnd, what="R")
     # the residual-only kernels (no interface values, no compression factor) give the same R
     R1, _, _ = S.residual(to_dev(torch, W), to_dev(torch, G), to_dev(torch, alpha), grad=False)
     S.check()
-    assert_residual_close(R1.cpu().numpy(), oR, surf, fs, what="R (residual only)")
+    assert_residual_close(R1.cpu().numpy(), oR, bnd, what="R (residual only)")
     vol = M.cells()[0]
     # gradients: sum of interface values times n S over |Omega|; bound by |W| S / V
     wscale = np.abs(W).max(axis=1)
@@ -142,7 +142,7 @@ def test_residual(oracle, cg, torch, name, wall, par):
     np.testing.assert_allclose(an, oan, rtol=1e-10, atol=1e-14)
     # residual-only call (a separately compiled kernel variant) gives the same R to rounding
     R2, _, _ = S.residual(to_dev(torch, W), to_dev(torch, G), to_dev(torch, alpha), grad=False)
-    assert_residual_close(R2.cpu().numpy(), R, surf, fs, tol=1e-13, what="R residual-only")
+    assert_residual_close(R2.cpu().numpy(), R, bnd, tol=1e-13, what="R residual-only")
 
 
 def test_free_stream(cg, torch):
@@ -246,9 +246,8 @@ def test_full_size_bump_sampled(oracle, cg, torch):
     rng = np.random.default_rng(0)
     sub = np.unique(np.concatenate([rng.choice(m.n_cells, 48, replace=False), np.arange(8), [m.n_cells - 1]]))
     oR, oGn, oan, _ = M.residual(oracle.params(), W, G, alpha, sub=sub)
-    F = M.faces()
-    surf = cell_surface(F, M.n_cells)
-    assert_residual_close(R.cpu().numpy()[:, sub], oR[:, sub], surf[sub], flux_scale(W), what="R sampled")
+    bnd = cell_flux_bound(W, M.faces(), M.n_cells)
+    assert_residual_close(R.cpu().numpy()[:, sub], oR[:, sub], bnd[:, sub], what="R sampled")
     np.testing.assert_allclose(an.cpu().numpy()[sub], oan[sub], rtol=1e-10, atol=1e-14)
 
 
@@ -274,11 +273,9 @@ def test_full_size_sphere_sampled(oracle, cg, torch, level, layers, prisms):
     sub = np.unique(np.concatenate([rng.choice(m.n_cells, 40, replace=False), np.arange(12), [m.n_cells - 1]]))
     opar = oracle.params(viscous=1, mu=2e-3, prandtl=0.72)
     oR, oGn, oan, _ = M.residual(opar, W, G, alpha, sub=sub)
-    F = M.faces()
-    surf = cell_surface(F, M.n_cells)
-    fs = flux_scale(W)
-    assert_residual_close(R.cpu().numpy()[:, sub], oR[:, sub], surf[sub], fs, what="R sampled")
-    r32 = assert_residual_close(R32.cpu().numpy()[:, sub], oR[:, sub], surf[sub], fs, tol=1e-5, what="R fp32")
+    bnd = cell_flux_bound(W, M.faces(), M.n_cells)
+    assert_residual_close(R.cpu().numpy()[:, sub], oR[:, sub], bnd[:, sub], what="R sampled")
+    r32 = assert_residual_close(R32.cpu().numpy()[:, sub], oR[:, sub], bnd[:, sub], tol=1e-5, what="R fp32")
     np.testing.assert_allclose(an.cpu().numpy()[sub], oan[sub], rtol=1e-10, atol=1e-14)
     say(f"    FP32 flux sampled error {r32 * 1e-5:.2e} of the flux scale")
 

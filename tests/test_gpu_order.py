@@ -17,7 +17,7 @@ import pytest
 
 from paper_2402_02075_amd import meshgen as mg
 
-from gpu_common import assert_residual_close, cell_surface, channel_bcs, flux_scale, say, to_dev
+from gpu_common import assert_residual_close, cell_flux_bound, cell_surface, channel_bcs, flux_scale, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -71,8 +71,7 @@ def test_shuffled_residual_matches_oracle(oracle, cg, torch, shuffled):
     S.check()
     oR, oGn, oan, _ = M.residual(oracle.params(), W, G, al)
     surf = cell_surface(M.faces(), m.n_cells)
-    fs = flux_scale(W)
-    assert_residual_close(R.cpu().numpy(), oR, surf, fs)
+    assert_residual_close(R.cpu().numpy(), oR, cell_flux_bound(W, M.faces(), m.n_cells))
     np.testing.assert_allclose(an.cpu().numpy(), oan, rtol=1e-10)
     vol = M.cells()[0]
     gscale = np.abs(W).max(1).repeat(3)[:, None] * (surf / vol)[None, :]

@@ -11,7 +11,7 @@ import pytest
 
 from paper_2402_02075_amd import meshgen as mg
 
-from gpu_common import assert_residual_close, cell_surface, flux_scale, say, to_dev
+from gpu_common import assert_residual_close, cell_flux_bound, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -61,11 +61,9 @@ def test_bow_shock_residual_matches_oracle(oracle, cg, torch):
                                     rng.choice(m.n_cells, 60, replace=False)]))
     opar = oracle.params(viscous=1, mu=MACH / RE, prandtl=0.72)
     oR, oGn, oan, _ = M.residual(opar, W, G, alpha, sub=sub)
-    F = M.faces()
-    surf = cell_surface(F, M.n_cells)
-    fs = flux_scale(W)
-    assert_residual_close(R[:, sub], oR[:, sub], surf[sub], fs, what="R bow shock")
-    r32 = assert_residual_close(R32[:, sub], oR[:, sub], surf[sub], fs, tol=1e-5, what="R bow shock fp32")
+    bnd = cell_flux_bound(W, M.faces(), M.n_cells)
+    assert_residual_close(R[:, sub], oR[:, sub], bnd[:, sub], what="R bow shock")
+    r32 = assert_residual_close(R32[:, sub], oR[:, sub], bnd[:, sub], tol=1e-5, what="R bow shock fp32")
     gscale = np.abs(oGn[:, sub]).max(axis=1, keepdims=True)
     np.testing.assert_allclose(Gn[:, sub] / gscale, oGn[:, sub] / gscale, rtol=0, atol=1e-11)
     np.testing.assert_allclose(an[sub], oan[sub], rtol=1e-10, atol=1e-14)
