@@ -283,3 +283,34 @@ def test_adjoint_gradients_vs_converged_fd(torch, ad):
         rel = abs(gr[key] - fd[name]) / abs(fd[name])
         say(f"    {key}: adjoint {gr[key]:.12e} fd {fd[name]:.12e} rel {rel:.2e}")
         assert rel < 1e-6
+
+
+def test_adjoint_gradients_vs_oracle_fd(torch, ad):
+    """dJ/dMach and dJ/dA from the library's adjoint solve on the 12 x 4 x 2 hexahedral bump
+    channel against the oracle's own central differences (step 1e-6) of J at converged
+    perturbed states, within 1e-6 relative.  The oracle values are in
+    tests/golden/adjoint_oracle_fd.json, written by tests/golden/make_adjoint_oracle_fd.py, which
+    calls only the oracle and the input generators."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_oracle_fd.json")) as f:
+        gold = json.load(f)
+    for run in gold["runs"]:  # the oracle's four states converged to round-off
+        assert run["min_norm"] / run["first_norm"] < 1e-12, run
+
+    def mesh_fn(a):
+        return mg.bump_channel(12, 4, 2, n_prism=0, n_pyr=0, amp=a)
+
+    amp, mach = 0.05, 0.5
+    m = mesh_fn(amp)
+    say(f"[gpu] adjoint gradients vs oracle differences cells={m.n_cells}")
+    S = ad.channel_solver(m, mach)
+    W, G, al, hist, _ = ad.converge(S, m, cycles=40000, tol=1e-14)
+    say(f"    primal {len(hist)} cycles drop {hist[-1] / hist[0]:.2e}")
+    assert hist[-1] / hist[0] < 1e-12
+    gr = ad.gradients(S, mesh_fn, amp, mach, W, G, al, max_iter=40000, tol=1e-12)
+    say(f"    adjoint {gr['adjoint_iterations']} iterations, last change {gr['adjoint_final_change']:.2e}")
+    for key in ("dJ_dMach", "dJ_dA"):
+        rel = abs(gr[key] - gold[key]) / abs(gold[key])
+        say(f"    {key}: library adjoint {gr[key]:.12e} oracle differences {gold[key]:.12e} rel {rel:.2e}")
+        assert rel < 1e-6
