@@ -123,6 +123,8 @@ template <int K> struct Fp<Dual<K>> {
         const double s = ::sqrt(x.v);
         return chain(x, s, s > 0.0 ? 0.5 / s : 0.0);
     }
+    CGKS_HD static Dual<K> div_(const Dual<K> &a, const Dual<K> &b) { return a / b; }
+    CGKS_HD static Dual<K> rsqrt_(const Dual<K> &x) { return Dual<K>(1.0) / sqrt_(x); }
 };
 
 // x^e for a constant exponent

@@ -46,6 +46,8 @@ template <> struct Fp<Cnt> {
     static Cnt exp_(Cnt x) { ++g.trans; return Cnt(::exp(x.v)); }
     static Cnt expm1_(Cnt x) { ++g.trans; return Cnt(::expm1(x.v)); }
     static Cnt sqrt_(Cnt x) { ++g.trans; return Cnt(::sqrt(x.v)); }
+    static Cnt div_(Cnt a, Cnt b) { return a / b; }
+    static Cnt rsqrt_(Cnt x) { return Cnt(1.0) / sqrt_(x); }
 };
 }  // namespace cgks
 

@@ -27,17 +27,29 @@
 namespace cgks {
 
 template <class T> struct Fp;
+// div_ and rsqrt_: correctly rounded in FP64; in FP32 the hardware reciprocal and reciprocal square
+// root (1 ulp, one instruction each, against about ten for an IEEE division), well inside the
+// FP32 flux's error budget.
 template <> struct Fp<double> {
     CGKS_HD static double erfc_(double x) { return ::erfc(x); }
     CGKS_HD static double exp_(double x) { return ::exp(x); }
     CGKS_HD static double expm1_(double x) { return ::expm1(x); }
     CGKS_HD static double sqrt_(double x) { return ::sqrt(x); }
+    CGKS_HD static double div_(double a, double b) { return a / b; }
+    CGKS_HD static double rsqrt_(double x) { return 1.0 / ::sqrt(x); }
 };
 template <> struct Fp<float> {
     CGKS_HD static float erfc_(float x) { return ::erfcf(x); }
     CGKS_HD static float exp_(float x) { return ::expf(x); }
     CGKS_HD static float expm1_(float x) { return ::expm1f(x); }
     CGKS_HD static float sqrt_(float x) { return ::sqrtf(x); }
+#ifdef __HIP_DEVICE_COMPILE__
+    CGKS_HD static float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    CGKS_HD static float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+#else
+    CGKS_HD static float div_(float a, float b) { return a / b; }
+    CGKS_HD static float rsqrt_(float x) { return 1.0f / ::sqrtf(x); }
+#endif
 };
 
 CGKS_HD double abs_(double x) { return fabs(x); }
@@ -64,7 +76,7 @@ template <class T> CGKS_HD Side<T> side_of(const T w[5], T gam)
     Side<T> s;
     s.rho = w[0];
     const T rp = (gam - T(1)) * (w[4] * w[0] - T(0.5) * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]));
-    const T d = T(1) / (w[0] * rp);
+    const T d = Fp<T>::div_(T(1), w[0] * rp);
     s.ir = rp * d;
     s.U = w[1] * s.ir;
     s.V = w[2] * s.ir;
@@ -437,7 +449,7 @@ template <class T> struct TimeCoef {
 
 template <class T> CGKS_HD TimeCoef<T> coef_integrated(T Tt, T tau, T taun)
 {
-    const T x = Tt / taun;
+    const T x = Fp<T>::div_(Tt, taun);
     const T E = Fp<T>::exp_(-x);
     const T omE = -Fp<T>::expm1_(-x);
     TimeCoef<T> c;
@@ -454,7 +466,7 @@ template <class T> CGKS_HD TimeCoef<T> coef_integrated(T Tt, T tau, T taun)
 
 template <class T> CGKS_HD TimeCoef<T> coef_at(T t, T tau, T taun)
 {
-    const T x = t / taun;
+    const T x = Fp<T>::div_(t, taun);
     const T e = Fp<T>::exp_(-x);
     TimeCoef<T> c;
     c.c1 = -Fp<T>::expm1_(-x);
@@ -593,7 +605,7 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
     if (!(sl.rho > T(0) && sr.rho > T(0) && sl.lam > T(0) && sr.lam > T(0))) return false;
     pl = sl.p;
     pr = sr.p;
-    const T jump = abs_((pl - pr) / (pl + pr));
+    const T jump = abs_(Fp<T>::div_(pl - pr, pl + pr));
     T Wc[5] = {T(0), T(0), T(0), T(0), T(0)};
     T tau = T(0), taun;
     if (VISC) {
@@ -611,7 +623,7 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
         }
         const Side<T> s0 = side_of(Wc, gam);
         if (!(s0.rho > T(0) && s0.lam > T(0))) return false;
-        tau = T(cfg.mu) / s0.p;
+        tau = Fp<T>::div_(T(cfg.mu), s0.p);
         taun = tau + T(cfg.c_tau) * jump * dt;
     } else {
         taun = T(cfg.eps_tau) * dt + T(cfg.c_tau) * jump * dt;
@@ -619,7 +631,7 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
     const TimeCoef<T> cf = coef_integrated(dt, tau, taun);
     TimeCoef<T> cw;
     if (VAL) cw = coef_at(dt, tau, taun);
-    const T iK3 = T(1) / (K + T(3));
+    const T iK3 = Fp<T>::div_(T(1), K + T(3));
     T dWc[3][5];
 #pragma unroll
     for (int j = 0; j < 3; ++j)
@@ -742,7 +754,7 @@ CGKS_HD bool gks_flux_folded(const T wl[5], const T gl[3][5], const T wr[5], con
     }
     if (VISC && cfg.prandtl != 1.0) {
         const T Uc[3] = {sc.U, sc.V, sc.W};
-        F[4] += (T(1) / T(cfg.prandtl) - T(1)) * heat_flux(F, Q, Uc);
+        F[4] += (Fp<T>::div_(T(1), T(cfg.prandtl)) - T(1)) * heat_flux(F, Q, Uc);
     }
     return true;
 }
@@ -771,7 +783,7 @@ template <class T> CGKS_HD void kfvs_local(const T wl[5], const T wr[5], T gam, 
 template <class T> CGKS_HD void onb(const T n[3], T t1[3], T t2[3])
 {
     const T s = sign_(n[2]);
-    const T a = T(-1) / (s + n[2]);
+    const T a = Fp<T>::div_(T(-1), s + n[2]);
     const T b = n[0] * n[1] * a;
     t1[0] = T(1) + s * n[0] * n[0] * a;
     t1[1] = s * b;
@@ -831,12 +843,12 @@ template <class T, class S>
 CGKS_HD S cf_factor(const T wl[5], const T wr[5], S pl, S pr, S gam)
 {
     // a Mach number is |m|/(rho c) with rho c = sqrt(gamma p rho); |dp|/p_l + |dp|/p_r = |dp| (p_l + p_r)/(p_l p_r)
-    const S il = S(1) / Fp<S>::sqrt_(gam * pl * S(wl[0])), ir = S(1) / Fp<S>::sqrt_(gam * pr * S(wr[0]));
+    const S il = Fp<S>::rsqrt_(gam * pl * S(wl[0])), ir = Fp<S>::rsqrt_(gam * pr * S(wr[0]));
     const S mtl = Fp<S>::sqrt_(S(wl[2]) * S(wl[2]) + S(wl[3]) * S(wl[3]));
     const S mtr = Fp<S>::sqrt_(S(wr[2]) * S(wr[2]) + S(wr[3]) * S(wr[3]));
     const S dmn = S(wl[1]) * il - S(wr[1]) * ir, dmt = mtl * il - mtr * ir;
-    const S A = abs_(pl - pr) * (pl + pr) / (pl * pr) + dmn * dmn + dmt * dmt;
-    return S(1) / (S(1) + A * A);
+    const S A = Fp<S>::div_(abs_(pl - pr) * (pl + pr), pl * pr) + dmn * dmn + dmt * dmt;
+    return Fp<S>::div_(S(1), S(1) + A * A);
 }
 
 }  // namespace cgks
