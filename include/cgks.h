@@ -69,7 +69,9 @@ typedef struct {
     int32_t viscous;     /* 0 inviscid, 1 Navier-Stokes */
     int32_t levels;      /* multigrid levels including the fine one (3) */
     int32_t passes;      /* agglomeration passes per coarse level (3) */
-    int32_t precision;   /* 0 FP64 everywhere, 1 mixed (FP32 coarse levels, transfers and flux evaluation) */
+    int32_t precision;   /* 0 FP64 everywhere, 1 mixed (FP32 coarse levels, transfers and flux evaluation;
+                            the first selection with a mesh set allocates FP32 copies of the
+                            reconstruction operator and the lane geometry, about 0.9 KB per cell) */
     int32_t nu_pre[8];   /* pre-smoothing sweeps per level (1) */
     int32_t nu_post[8];  /* post-smoothing sweeps per level (0) */
     double mixed_switch; /* mixed precision: FP64 flux once the residual drop is below this (1e-6) */
@@ -166,7 +168,9 @@ cgks_status cgks_reconstruct(cgks_ctx *ctx, const double *W, const double *G, co
  *   alpha_new[N]  = product over interior-face Gauss points of 1/(1 + A^2).
  * Inputs W, G, alpha (alpha of the previous update, scales the Green-Gauss p^1).
  * G_new and alpha_new may be NULL (residual only).  All device.  With precision 1 the
- * Gauss-point flux is evaluated in FP32 (sums, update and outputs stay FP64).
+ * flux is evaluated in FP32: FP32 reconstruction coefficients (FP64 arithmetic), FP32 polynomial
+ * evaluation, frame rotations, BGK solution and compression factor; face sums, gathers and
+ * outputs stay FP64.
  */
 cgks_status cgks_residual(cgks_ctx *ctx, const double *W, const double *G, const double *alpha, double *R,
                           double *G_new, double *alpha_new);
@@ -194,7 +198,9 @@ cgks_status cgks_check(cgks_ctx *ctx);
  * one fixed device array of 32 Mi doubles (256 MiB) per GPU, kept until the process ends, instead
  * of the context's buffers.  It needs N + 50 N + 5 Fb + 21 F doubles (5 F without G_new), plus
  * 42 N with cell_order 1, each rounded up to 32; a mesh that needs more returns CGKS_E_ARG before
- * any work (about 230k mixed cells with cell_order 1, 330k with 0 or 2).  Nothing in the array
+ * any work (about 230k mixed cells with cell_order 1, 330k with 0 or 2).  With precision 1 the
+ * FP32 coefficients take the coefficient piece (the FP32 operator and lane-geometry copies are
+ * the context's, made when precision 1 was selected).  Nothing in the array
  * needs clearing: every call writes all it reads.  All calls on one GPU share the array, from every
  * context: calls that overlap on one GPU (other streams, other host threads) race and must be
  * ordered by the caller.  The context's device must be the current device (CGKS_E_DEVICE).
