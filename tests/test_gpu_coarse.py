@@ -226,3 +226,30 @@ def test_vcycle_converges_faster_than_explicit(cg, torch, hier):
         res[mode] = hist[-1] / hist[0]
     say(f"[gpu] drop after 60: {res}")
     assert res["vcycle"] < res["explicit"]
+
+
+def test_converged_state_equals_the_oracle_fixed_point(cg, torch):
+    """On the 12 x 4 x 2 hexahedral channel the library's V-cycle, run from the free stream to a
+    1e-14 drop, ends at the state the oracle's V-cycle converged to (a stored oracle run,
+    tests/golden/vcycle_fixed_point.json), within 1e-11 of each component's size: the two solve
+    the same discrete equations, and the fixed point does not depend on the path to it."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "vcycle_fixed_point.json")) as f:
+        gold = json.load(f)
+    m = mg.bump_channel(12, 4, 2, n_prism=0, n_pyr=0, amp=0.05)
+    S = cg.Solver()
+    S.set_mesh(m)
+    for tag, kind, prim in _bcs():
+        S.set_bc(tag, kind, prim)
+    S.agglomerate()
+    W0, G0 = mg.uniform_state(m.n_cells)
+    W, G = to_dev(torch, W0), to_dev(torch, G0)
+    al = torch.ones(m.n_cells, dtype=torch.float64, device="cuda")
+    h, ok = S.vcycle(W, G, al, 40000, 1e-14)
+    say(f"[gpu] converged state vs oracle fixed point: {len(h)} cycles, drop {h[-1] / h[0]:.2e}")
+    assert ok
+    Wo = np.array(gold["W"])
+    d = np.abs(W.cpu().numpy() - Wo).max(axis=1) / np.abs(Wo).max(axis=1)
+    say("    max difference per component: " + " ".join(f"{x:.2e}" for x in d))
+    assert d.max() < 1e-11

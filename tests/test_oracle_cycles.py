@@ -6,6 +6,10 @@ W-cycle visits each coarser level twice per visit of its parent).
   the results are bit-identical.
 * The free stream is a fixed point of every cycle variant (W-cycle, four levels, post-sweeps,
   implicit coarse smoother).
+* The state the V-cycle converges to on a small hexahedral channel (a stored oracle run) is a zero
+  of the fine residual, so it is also the fixed point of the single-level explicit scheme: one
+  forward-Euler step and one more V-cycle leave it unchanged (the coarse correction of the FAS
+  cycle, Sec. 4.2, vanishes with the fine residual).
 """
 import numpy as np
 import pytest
@@ -55,3 +59,30 @@ def test_free_stream_is_a_fixed_point_of_every_cycle(oracle, variant):
     W0 = W.copy()
     H.vcycle(par, W, G, al, nu_pre=[1] * 8, nu_post=post)
     np.testing.assert_allclose(W, W0, rtol=0, atol=1e-13)
+
+
+def test_converged_vcycle_state_is_the_explicit_fixed_point(oracle):
+    """The oracle V-cycle's converged state on the 12 x 4 x 2 hexahedral channel
+    (tests/golden/vcycle_fixed_point.json, written by make_vcycle_fixed_point.py from oracle calls
+    only) has a fine residual at round-off, and neither an explicit step nor a V-cycle moves it."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "vcycle_fixed_point.json")) as f:
+        gold = json.load(f)
+    assert gold["min_norm"] / gold["first_norm"] < 1e-12
+    m, M = _channel(oracle, 12, 4, 2)
+    W, G, al = (np.array(gold[k], dtype=np.float64) for k in ("W", "G", "alpha"))
+    par = oracle.params()
+    # the fine residual at the converged state, against its size at the free stream
+    W0, G0 = mg.uniform_state(m.n_cells)
+    r0 = M.residual_norm(M.residual(par, W0, G0, np.ones(m.n_cells))[0])
+    r = M.residual_norm(M.residual(par, W, G, al)[0])
+    assert r0 > 0.0 and r / r0 < 1e-12, (r, r0)
+    scale = np.abs(W).max(axis=1, keepdims=True)
+    We, Ge, ae = W.copy(), G.copy(), al.copy()
+    M.step_fe(par, We, Ge, ae)  # single-level explicit step
+    assert (np.abs(We - W) / scale).max() < 1e-13
+    H = oracle.Hierarchy(M, levels=3, passes=3, seed=1)
+    Wv, Gv, av = W.copy(), G.copy(), al.copy()
+    H.vcycle(par, Wv, Gv, av)
+    assert (np.abs(Wv - W) / scale).max() < 1e-13
