@@ -446,8 +446,16 @@ cgks_status cgks_set_params(cgks_ctx *c, const cgks_params *p)
     check_params(p);
     if (c->has_mesh && (p->cell_order == 0) != (c->prm.cell_order == 0))
         throw Error{CGKS_E_ARG, "cell_order 0 against 1/2 is fixed by cgks_set_mesh: set the mesh again"};
+    const cgks_params prev = c->prm;
     c->prm = *p;
-    if (c->prm.precision == 1) ensure_fp32_front(c);
+    if (c->prm.precision == 1) {
+        try {
+            ensure_fp32_front(c);
+        } catch (...) {  // the previous parameters stay in force
+            c->prm = prev;
+            throw;
+        }
+    }
     API_END(c)
 }
 

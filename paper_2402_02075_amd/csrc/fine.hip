@@ -779,10 +779,17 @@ __global__ void k_to_f32(int64_t n, const double *__restrict__ a, float *__restr
 
 void ensure_fp32_front(cgks_ctx *c)
 {
-    if (!c->has_mesh || c->opf.p) return;
-    c->opf.alloc(c->op.n);
-    c->lgeof.alloc(10 * c->NL);
-    c->coeff.alloc(50 * c->N);
+    if (!c->has_mesh || (c->opf.p && c->lgeof.p && c->coeff.p)) return;
+    try {
+        c->opf.alloc(c->op.n);
+        c->lgeof.alloc(10 * c->NL);
+        c->coeff.alloc(50 * c->N);
+    } catch (...) {  // all three or none
+        c->opf.release();
+        c->lgeof.release();
+        c->coeff.release();
+        throw;
+    }
     hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(c->op.n, 256)), dim3(256), 0, c->stream, (int64_t)c->op.n, c->op.p,
                        c->opf.p);
     hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(10 * c->NL, 256)), dim3(256), 0, c->stream, 10 * c->NL, c->lgeo.p,
@@ -852,7 +859,7 @@ void launch_face(cgks_ctx *c, int mode, const double *coef, const double *dt_cel
     A.lgeo = c->lgeo.p;
     A.coeff = coef32 ? coef32 : c->coeff.p;
     A.lgeof = c->lgeof.p;
-    if (fp32 && !c->lgeof.p) throw Error{CGKS_E_STATE, "FP32 flux without its lane geometry copy"};
+    if (fp32 && (!c->lgeof.p || !A.coeff)) throw Error{CGKS_E_STATE, "FP32 flux without its FP32 buffers"};
     A.NL = c->NL;
     A.bc = c->bc.p;
     A.out = out ? out : c->fout.p;
