@@ -35,8 +35,20 @@ template <> struct Fp<double> {
     CGKS_HD static double exp_(double x) { return ::exp(x); }
     CGKS_HD static double expm1_(double x) { return ::expm1(x); }
     CGKS_HD static double sqrt_(double x) { return ::sqrt(x); }
+#ifdef __HIP_DEVICE_COMPILE__
+    // hardware reciprocal, two Newton steps and one residual correction of the quotient
+    CGKS_HD static double div_(double a, double b)
+    {
+        double r = __builtin_amdgcn_rcp(b);
+        r = fma(fma(-b, r, 1.0), r, r);
+        r = fma(fma(-b, r, 1.0), r, r);
+        const double q = a * r;
+        return fma(fma(-b, q, a), r, q);
+    }
+#else
     CGKS_HD static double div_(double a, double b) { return a / b; }
-    CGKS_HD static double rsqrt_(double x) { return 1.0 / ::sqrt(x); }
+#endif
+    CGKS_HD static double rsqrt_(double x) { return div_(1.0, ::sqrt(x)); }
 };
 template <> struct Fp<float> {
     CGKS_HD static float erfc_(float x) { return ::erfcf(x); }
