@@ -92,6 +92,8 @@ typedef struct {
                                 2  the same locality order, and cell arrays at this ABI are exchanged
                                    in it (no gather or scatter; cgks_cell_order gives the order).
                                 Switching between 0 and 1/2 needs a new cgks_set_mesh. */
+    int32_t mixed_stall;     /* mixed precision: FP64 flux also once the residual norm has not
+                                reached a new minimum for this many cycles (300; >= 1) */
 } cgks_params;
 
 /* Fill *p with the defaults above. */

@@ -69,6 +69,7 @@ static void check_params(const cgks_params *p)
     if (p->coarse_smoother == 1 && !(p->cfl_implicit > 0.0)) throw Error{CGKS_E_ARG, "cfl_implicit must be positive"};
     if (p->cycle_gamma < 1 || p->cycle_gamma > 3) throw Error{CGKS_E_ARG, "cycle_gamma must be in 1..3"};
     if (p->cell_order < 0 || p->cell_order > 2) throw Error{CGKS_E_ARG, "cell_order must be 0, 1 or 2"};
+    if (p->mixed_stall < 1) throw Error{CGKS_E_ARG, "mixed_stall must be at least 1"};
 }
 
 static void check_bad(cgks_ctx *c)
@@ -268,7 +269,7 @@ static cgks_status vcycle_impl(cgks_ctx *c, double *W, double *G, double *alpha,
         if (r < best) best = r, best_at = k;
         const double drop = r / r0;
         if (drop <= tol_drop) return 1;
-        if (mixed && (drop <= c->prm.mixed_switch || k - best_at >= 20)) return 2;
+        if (mixed && (drop <= c->prm.mixed_switch || k - best_at >= c->prm.mixed_stall)) return 2;
         return 0;
     };
     // Cycles run in batches queued without a host wait, each cycle writing its norm into a
@@ -391,6 +392,7 @@ cgks_status cgks_default_params(cgks_params *p)
     p->cfl_implicit = 0.25;
     p->cycle_gamma = 1;
     p->cell_order = 1;
+    p->mixed_stall = 300;
     return CGKS_OK;
 }
 

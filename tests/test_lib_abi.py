@@ -32,3 +32,15 @@ def test_default_params_without_gpu():
     assert p.gamma == 1.4 and p.levels == 3 and p.passes == 3 and p.seed == 1
     assert p.nu_pre[0] == 1 and p.nu_post[0] == 0
     assert abs(p.skew_sin - 0.17364817766693033) < 1e-15
+    assert p.cell_order == 1 and p.mixed_stall == 300
+
+
+def test_params_struct_size_matches_the_header():
+    """cgks_default_params writes exactly the binding's copy of cgks_params: a buffer with guard
+    bytes past the binding's size keeps them (a field added on one side only would overrun)."""
+    from paper_2402_02075_amd import cgks
+    n = ctypes.sizeof(cgks.Params)
+    buf = (ctypes.c_uint8 * (n + 64))(*([0xA5] * (n + 64)))
+    cgks.lib().cgks_default_params(ctypes.cast(buf, ctypes.c_void_p))
+    assert bytes(buf[n:]) == bytes([0xA5] * 64)
+    assert any(b != 0xA5 for b in buf[n - 8:n])  # the last field was written
