@@ -141,3 +141,40 @@ def test_mixed_switch_inside_a_batch(torch, ad):
     np.testing.assert_array_equal(hA, np.concatenate([hB1, hB2]))
     for a, b in ((WA, WB), (GA, GB), (aA, aB)):
         np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_mixed_switch_by_the_stall_window(torch, ad):
+    """The switch to the FP64 flux after `mixed_stall` cycles without a new minimum of the residual
+    norm, decided inside a batch of queued cycles: the run equals one that stops the mixed cycle
+    at that cycle and continues in FP64 (states bit for bit, same norms).  The switch cycle is read
+    off the mixed run's own history (the first k with k - argmin(h[:k+1]) = mixed_stall)."""
+    m = mg.bump_channel(24, 8, 4, n_prism=2, n_pyr=2, jitter=0.05, seed=3)
+    W0, G0 = mg.uniform_state(m.n_cells)
+    al0 = np.ones(m.n_cells)
+
+    def dev():
+        return (torch.from_numpy(W0.copy()).cuda(), torch.from_numpy(G0.copy()).cuda(),
+                torch.from_numpy(al0.copy()).cuda())
+
+    n, stall = 300, 5
+    SA = ad.channel_solver(m, 0.5, precision=1, mixed_switch=0.0, mixed_stall=stall)
+    WA, GA, aA = dev()
+    hA, _ = SA.vcycle(WA, GA, aA, n, 1e-300)
+    # the first cycle k at which the mixed run has gone `stall` cycles without a new minimum
+    best, best_at, s = np.inf, 0, None
+    for k, r in enumerate(hA):
+        if r < best:
+            best, best_at = r, k
+        if k - best_at >= stall:
+            s = k
+            break
+    say(f"[gpu] mixed switch by the stall window at cycle {s}")
+    assert s is not None and 0 < s < n - 1
+    SB = ad.channel_solver(m, 0.5, precision=1, mixed_switch=0.0, mixed_stall=10 ** 6)
+    WB, GB, aB = dev()
+    hB1, _ = SB.vcycle(WB, GB, aB, s + 1, 1e-300)
+    SB.set_params(precision=0)
+    hB2, _ = SB.vcycle(WB, GB, aB, n - s - 1, 1e-300)
+    np.testing.assert_array_equal(hA, np.concatenate([hB1, hB2]))
+    for a, b in ((WA, WB), (GA, GB), (aA, aB)):
+        np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
