@@ -361,6 +361,9 @@ cgks_status cgks_prolong(cgks_ctx *ctx, int32_t level, const double *dWc, double
  * a batch's start is kept (21 N doubles of device memory), so that a stop, a precision switch or a
  * non-physical state before the batch's end is reproduced by re-running from it: the results are
  * those of a loop that checks after every cycle (the kernels are deterministic).
+ * With params.precision 1 every call starts with the FP32 flux and FP32 coarse levels and
+ * switches to FP64 for the rest of the call once the drop reaches params.mixed_switch or the norm
+ * has gone params.mixed_stall cycles without a new minimum.
  * Returns CGKS_E_NOCONV if the drop was not reached (state and history valid).
  */
 cgks_status cgks_vcycle(cgks_ctx *ctx, double *W, double *G, double *alpha, int32_t max_cycles, double tol_drop,
