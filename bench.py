@@ -407,7 +407,8 @@ def explicit_vs_vcycle(torch, cg, mg, cap):
 def adjoint_check(torch, cg, mg):
     """Adjoint gradients of the lower-wall x-force on a converged hexahedral channel (768 cells)
     against central differences (step 1e-6) of the converged objective, and the cost of one
-    linearisation, one fine VJP and one adjoint iteration on the 189k-cell channel."""
+    linearisation, one fine VJP and one adjoint iteration on the 189k-cell channel, with the
+    Jacobians stored in FP64 and in FP32, and the device memory each tape holds."""
     from paper_2402_02075_amd import adjoint as ad
     out = {}
 
@@ -448,26 +449,90 @@ def adjoint_check(torch, cg, mg):
     N = m.n_cells
     W, G, al = free_stream(torch, mg, N, (0.5, 0.0, 0.0))
     S.vcycle(W, G, al, 100, 0.0)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    w = [torch.randn(*sh, dtype=torch.float64, device="cuda", generator=g) for sh in ((5, N), (15, N), (N,))]
     torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for tape in (0, 1):  # Jacobians stored in FP64, then in FP32 (params.adjoint_tape)
+        S.set_params(adjoint_tape=tape)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.linearize(W, G, al)
+        torch.cuda.synchronize()
+        t_lin = time.perf_counter() - t0
+        S.vjp_residual(*w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            S.vjp_residual(*w)
+        torch.cuda.synchronize()
+        t_vjp = (time.perf_counter() - t0) / 20 * 1e3
+        t0 = time.perf_counter()
+        r = S.adjoint_solve(mg.TAG_WALL_BOTTOM, max_iter=20, tol=0.0)
+        t_it = (time.perf_counter() - t0) / max(r["iterations"], 1) * 1e3
+        torch.cuda.synchronize()
+        # device memory the tape and the adjoint's work buffers hold (hipMemGetInfo difference)
+        used = free0 - torch.cuda.mem_get_info()[0]
+        if tape == 0:
+            out["linearize_s_189k"] = t_lin
+            out["vjp_residual_ms_189k"] = t_vjp
+            out["adjoint_iteration_ms_189k"] = t_it
+            out["tape_bytes_per_cell_189k"] = used / N
+        else:
+            out["fp32_tape_189k"] = {"linearize_s": t_lin, "vjp_residual_ms": t_vjp, "adjoint_iteration_ms": t_it,
+                                     "tape_bytes_per_cell": used / N}
+    S.close()
+    log(f"adjoint: gradient rel err {out['gradient_check']['dJ_dMach']['rel_err']:.2e} "
+        f"{out['gradient_check']['dJ_dA']['rel_err']:.2e}; tape {out['tape_bytes_per_cell_189k']:.0f} B/cell, "
+        f"FP32 tape {out['fp32_tape_189k']['tape_bytes_per_cell']:.0f} B/cell")
+    return out
+
+
+def adjoint_sphere(torch, cg, mg, develop=200):
+    """Linearisation, fine VJP and adjoint iterations on the 6.14M-cell sphere with the Jacobians
+    stored in FP32 (params.adjoint_tape = 1), and the device memory the context and the tape hold
+    (hipMemGetInfo differences).  The state is the developed flow after `develop` V-cycles, not a
+    converged one: the figures are costs, the adjoint iterates are not a gradient."""
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    m, S, sizes, setup = sphere_solver(cg, mg, 6, 33, 12)
+    N = m.n_cells
+    W, G, al = free_stream(torch, mg, N, (0.2, 0.0, 0.0))
+    S.vcycle(W, G, al, develop, 0.0)
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    log(f"adjoint sphere: {N} cells, context and state {(free0 - free1) / 2**30:.1f} GiB")
+    S.set_params(adjoint_tape=1)
     t0 = time.perf_counter()
     S.linearize(W, G, al)
     torch.cuda.synchronize()
-    out["linearize_s_189k"] = time.perf_counter() - t0
+    t_lin = time.perf_counter() - t0
+    free2 = torch.cuda.mem_get_info()[0]
+    log(f"adjoint sphere: linearised in {t_lin:.2f} s, tape {(free1 - free2) / 2**30:.1f} GiB")
     g = torch.Generator(device="cuda").manual_seed(1)
     w = [torch.randn(*sh, dtype=torch.float64, device="cuda", generator=g) for sh in ((5, N), (15, N), (N,))]
     S.vjp_residual(*w)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(20):
+    for _ in range(10):
         S.vjp_residual(*w)
     torch.cuda.synchronize()
-    out["vjp_residual_ms_189k"] = (time.perf_counter() - t0) / 20 * 1e3
+    t_vjp = (time.perf_counter() - t0) / 10 * 1e3
+    del w
+    S.adjoint_solve(mg.TAG_SPHERE, max_iter=2, tol=0.0)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = S.adjoint_solve(mg.TAG_WALL_BOTTOM, max_iter=20, tol=0.0)
-    out["adjoint_iteration_ms_189k"] = (time.perf_counter() - t0) / max(r["iterations"], 1) * 1e3
+    r = S.adjoint_solve(mg.TAG_SPHERE, max_iter=10, tol=0.0)
+    torch.cuda.synchronize()
+    t_it = (time.perf_counter() - t0) / max(r["iterations"], 1) * 1e3
+    free3 = torch.cuda.mem_get_info()[0]
+    out = {"workload": "viscous sphere 6.14M cells, developed state (200 V-cycles), Jacobians in FP32",
+           "cells": N, "linearize_s": t_lin, "vjp_residual_ms": t_vjp, "adjoint_iteration_ms": t_it,
+           "context_and_state_GiB": (free0 - free1) / 2**30, "tape_GiB": (free1 - free2) / 2**30,
+           "tape_and_adjoint_work_bytes_per_cell": (free1 - free3) / N,
+           "device_total_used_GiB": (free0 - free3) / 2**30}
+    log(f"adjoint sphere: vjp {t_vjp:.2f} ms, iteration {t_it:.2f} ms, total {(free0 - free3) / 2**30:.1f} GiB")
     S.close()
-    log(f"adjoint: gradient rel err {out['gradient_check']['dJ_dMach']['rel_err']:.2e} "
-        f"{out['gradient_check']['dJ_dA']['rel_err']:.2e}")
     return out
 
 
@@ -700,6 +765,8 @@ def main():
                     help="--long-run pair: FP64 and mixed, or explicit and implicit coarse sweeps")
     ap.add_argument("--oracle-timing", choices=("small", "sphere6M"),
                     help="instead of the benchmark: the CPU oracle timed on the configuration meshes")
+    ap.add_argument("--adjoint-sphere", action="store_true",
+                    help="only the adjoint's costs on the 6.14M-cell sphere with the FP32 tape")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="a plain 1 GiB fill and copy first (known bytes for scaling the HBM counters)")
     args = ap.parse_args()
@@ -720,6 +787,9 @@ def main():
         return
     if args.oracle_timing:
         print(json.dumps(oracle_timing(torch, cg, mg, args.oracle_timing)))
+        return
+    if args.adjoint_sphere:
+        print(json.dumps({"adjoint_sphere": adjoint_sphere(torch, cg, mg)}))
         return
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")

@@ -94,6 +94,9 @@ typedef struct {
                                 Switching between 0 and 1/2 needs a new cgks_set_mesh. */
     int32_t mixed_stall;     /* mixed precision: FP64 flux also once the residual norm has not
                                 reached a new minimum for this many cycles (300; >= 1) */
+    int32_t adjoint_tape;    /* storage of the Jacobians cgks_linearize records: 0 FP64 (default),
+                                1 FP32 (half the memory; every product still accumulates in FP64,
+                                so only the stored entries are rounded, to 2^-24 relative) */
 } cgks_params;
 
 /* Fill *p with the defaults above. */
@@ -230,8 +233,10 @@ cgks_status cgks_wall_force(cgks_ctx *ctx, const double *W, const double *G, con
  * Sec. 3.3) with respect to the two reconstructed states, their gradients and
  * the face step; per cell and component those of the HWENO coefficients (Sec. 3)
  * with respect to the stencil data; per cell that of the local time step.
- * Device memory kept: about (451 x 4F + 1650 N) doubles, released with the
- * context.  CGKS_E_PHYS if a Gauss-point state is non-physical.  Any later
+ * Device memory kept: the Jacobians, 451 NGP + 1500 N values (NGP = Gauss points of all
+ * faces, cgks_mesh_info[4]; FP64, or FP32 with params.adjoint_tape = 1), and about
+ * 300 N + 150 F doubles of state and work buffers (some 100 N more once cgks_adjoint_solve
+ * has run), released with the context.  CGKS_E_PHYS if a Gauss-point state is non-physical.  Any later
  * cgks_set_mesh, cgks_set_bc, cgks_set_params or cgks_agglomerate invalidates it.
  */
 cgks_status cgks_linearize(cgks_ctx *ctx, const double *W, const double *G, const double *alpha);

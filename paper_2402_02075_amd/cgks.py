@@ -35,7 +35,8 @@ class Params(C.Structure):
                 ("passes", C.c_int32), ("precision", C.c_int32), ("nu_pre", C.c_int32 * 8),
                 ("nu_post", C.c_int32 * 8), ("mixed_switch", C.c_double), ("seed", C.c_uint64),
                 ("coarse_smoother", C.c_int32), ("relax_sweeps", C.c_int32), ("cfl_implicit", C.c_double),
-                ("cycle_gamma", C.c_int32), ("cell_order", C.c_int32), ("mixed_stall", C.c_int32)]
+                ("cycle_gamma", C.c_int32), ("cell_order", C.c_int32), ("mixed_stall", C.c_int32),
+                ("adjoint_tape", C.c_int32)]
 
 
 class CgksError(RuntimeError):

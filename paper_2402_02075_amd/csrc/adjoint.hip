@@ -119,13 +119,14 @@ __global__ void k_rev_slots(int64_t N, int64_t Fi, const int32_t *cf_ptr, const 
 
 // ---------------------------------------------------------------- Gauss-point outputs
 struct GpArgs {
-    int64_t N, F, NS;
+    int64_t N, F, NGP;
     GksCfg cfg;
     const double *coef, *dt, *cen, *gpx, *gpw, *gpn, *fshift;
     const uint8_t *dtL;
-    const int32_t *fl, *fr, *ftag, *fngp;
+    const int32_t *fl, *fr, *ftag, *fngp, *gpoff;
     const BcTable *bc;
-    double *Jf, *agp;
+    double *Jf, *agp;  // Jf [11*41][NGP] in FP64, or
+    float *Jf32;       // the same in FP32 (when not null)
     int32_t *bad;
 };
 
@@ -181,14 +182,16 @@ __device__ inline void eval_cell(const double *coef, int64_t cell, const double 
     }
 }
 
-// One lane per Gauss-point slot; pass p differentiates along inputs [pK, pK + K).
+// One lane per Gauss-point slot (4 per face); pass p differentiates along inputs [pK, pK + K).
+// Jacobian columns are the compact Gauss-point numbers gpoff[f] + k (3 per triangle, 4 per quad).
 template <int K> __global__ __launch_bounds__(64) void k_face_jac(GpArgs A, int pass)
 {
     const int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t f = gp >> 2;
     const int k = (int)(gp & 3);
     if (f >= A.F || k >= A.fngp[f]) return;
-    const int64_t F = A.F, N = A.N, NS = A.NS;
+    const int64_t F = A.F, N = A.N, NGP = A.NGP;
+    const int64_t col = (int64_t)A.gpoff[f] + k;
     const int L = A.fl[f], R = A.fr[f];
     const double x[3] = {A.gpx[(3 * k) * F + f], A.gpx[(3 * k + 1) * F + f], A.gpx[(3 * k + 2) * F + f]};
     const double n[3] = {A.gpn[(3 * k) * F + f], A.gpn[(3 * k + 1) * F + f], A.gpn[(3 * k + 2) * F + f]};
@@ -224,16 +227,21 @@ template <int K> __global__ __launch_bounds__(64) void k_face_jac(GpArgs A, int 
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int q = pass * K + j;
-            if (q < GP_IN) A.Jf[(int64_t)(o * GP_IN + q) * NS + gp] = ok ? out[o].d[j] : 0.0;
+            if (q < GP_IN) {
+                const double v = ok ? out[o].d[j] : 0.0;
+                const int64_t at = (int64_t)(o * GP_IN + q) * NGP + col;
+                if (A.Jf32) A.Jf32[at] = (float)v;
+                else A.Jf[at] = v;
+            }
         }
     if (pass == 0) A.agp[gp] = ok ? out[10].v : 1.0;
 }
 
 // ---------------------------------------------------------------- face VJP
 struct FvArgs {
-    int64_t N, F, NS;
-    const double *cen, *gpx, *gpw, *gpn, *fshift, *Jf, *agp, *brec;
-    const int32_t *fl, *fr, *fngp;
+    int64_t N, F, NGP;
+    const double *cen, *gpx, *gpw, *gpn, *fshift, *agp, *brec;
+    const int32_t *fl, *fr, *fngp, *gpoff;
     double *bface;  // [F][101]: coefficient cotangents of L (50) and R (50), face step (1)
 };
 
@@ -260,13 +268,14 @@ __device__ __forceinline__ void poly_vjp(const double dx[3], double bw, const do
     b[9] += bw * x * z + z * bg[0] + x * bg[2];
 }
 
-__global__ __launch_bounds__(256) void k_face_vjp(FvArgs A)
+// TJ: the Jacobians' storage type (double or float); the products accumulate in FP64
+template <class TJ> __global__ __launch_bounds__(256) void k_face_vjp(FvArgs A, const TJ *Jf)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t f = gid >> 2;
     const int k = (int)(gid & 3);
     if (f >= A.F) return;  // whole groups of four leave together
-    const int64_t F = A.F, N = A.N, NS = A.NS;
+    const int64_t F = A.F, N = A.N, NGP = A.NGP;
     const bool act = k < A.fngp[f];
     const int L = A.fl[f], R = A.fr[f];
     const double *br = A.brec + f * 21;
@@ -291,12 +300,12 @@ __global__ __launch_bounds__(256) void k_face_vjp(FvArgs A)
         // half an output row at a time: about 20 loads in flight, not all 451 (keeps the wave count up)
 #pragma unroll
         for (int o = 0; o < GP_OUT; ++o) {
-            const double *J = A.Jf + (int64_t)o * GP_IN * NS + gid;
+            const TJ *J = Jf + (int64_t)o * GP_IN * NGP + A.gpoff[f] + k;
 #pragma unroll
-            for (int q = 0; q < 21; ++q) bi[q] += J[(int64_t)q * NS] * bo[o];
+            for (int q = 0; q < 21; ++q) bi[q] += (double)J[(int64_t)q * NGP] * bo[o];
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int q = 21; q < GP_IN; ++q) bi[q] += J[(int64_t)q * NS] * bo[o];
+            for (int q = 21; q < GP_IN; ++q) bi[q] += (double)J[(int64_t)q * NGP] * bo[o];
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
@@ -359,7 +368,7 @@ __global__ __launch_bounds__(256) void k_coef_gather(int64_t N, const int32_t *c
 }
 
 // ---------------------------------------------------------------- reconstruction Jacobian and VJP
-template <int K, int C> __device__ __forceinline__ void recon_jac_comp(const ReconArgs &A, int64_t i, int pass, double *Jr)
+template <int K, int C, class TJ> __device__ __forceinline__ void recon_jac_comp(const ReconArgs &A, int64_t i, int pass, TJ *Jr)
 {
     const int64_t N = A.N;
     using D = Dual<K>;
@@ -396,25 +405,26 @@ template <int K, int C> __device__ __forceinline__ void recon_jac_comp(const Rec
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int q = pass * K + j;
-            if (q < RECON_IN) Jr[(int64_t)(o * RECON_IN + q) * 5 * N + C * N + i] = r[o].d[j];
+            if (q < RECON_IN) Jr[(int64_t)(o * RECON_IN + q) * 5 * N + C * N + i] = (TJ)r[o].d[j];
         }
 }
 
-template <int K> __global__ __launch_bounds__(320) void k_recon_jac(ReconArgs A, int pass, double *Jr)
+template <int K, class TJ> __global__ __launch_bounds__(320) void k_recon_jac(ReconArgs A, int pass, TJ *Jr)
 {
     const int64_t i = (int64_t)blockIdx.x * OP_GROUP + (threadIdx.x & (OP_GROUP - 1));
     if (i >= A.N) return;
     switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
-    case 0: recon_jac_comp<K, 0>(A, i, pass, Jr); break;
-    case 1: recon_jac_comp<K, 1>(A, i, pass, Jr); break;
-    case 2: recon_jac_comp<K, 2>(A, i, pass, Jr); break;
-    case 3: recon_jac_comp<K, 3>(A, i, pass, Jr); break;
-    default: recon_jac_comp<K, 4>(A, i, pass, Jr); break;
+    case 0: recon_jac_comp<K, 0, TJ>(A, i, pass, Jr); break;
+    case 1: recon_jac_comp<K, 1, TJ>(A, i, pass, Jr); break;
+    case 2: recon_jac_comp<K, 2, TJ>(A, i, pass, Jr); break;
+    case 3: recon_jac_comp<K, 3, TJ>(A, i, pass, Jr); break;
+    default: recon_jac_comp<K, 4, TJ>(A, i, pass, Jr); break;
     }
 }
 
 // per (component, cell): input cotangents = Jr^T (coefficient cotangents)
-__global__ __launch_bounds__(256) void k_recon_vjp(int64_t N, const double *Jr, const double *bcoef, double *bown,
+template <class TJ>
+__global__ __launch_bounds__(256) void k_recon_vjp(int64_t N, const TJ *Jr, const double *bcoef, double *bown,
                                                    double *bslot)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -428,7 +438,7 @@ __global__ __launch_bounds__(256) void k_recon_vjp(int64_t N, const double *Jr, 
     for (int q = 0; q < RECON_IN; ++q) {
         double s = 0.0;
 #pragma unroll
-        for (int o = 0; o < 10; ++o) s += Jr[(int64_t)(o * RECON_IN + q) * 5 * N + t] * br[o];
+        for (int o = 0; o < 10; ++o) s += (double)Jr[(int64_t)(o * RECON_IN + q) * 5 * N + t] * br[o];
         if (q < 6) bown[(C * 6 + q) * N + i] = s;
         else bslot[((int64_t)(C * 6 + (q - 6) / 4) * 4 + (q - 6) % 4) * N + i] = s;
     }
@@ -748,7 +758,7 @@ void adj_linearize(cgks_ctx *c, const double *W, const double *G, const double *
     AdjTape &T = *c->adj;
     T.ready = false;
     hipStream_t st = c->stream;
-    const int64_t N = c->N, F = c->F, NS = 4 * F;
+    const int64_t N = c->N, F = c->F, NS = 4 * F, NGP = c->NGP;
     T.W.ensure(5 * N);
     T.G.ensure(15 * N);
     T.al.ensure(N);
@@ -775,13 +785,24 @@ void adj_linearize(cgks_ctx *c, const double *W, const double *G, const double *
     c->Rw.ensure(5 * N);
     launch_gather_res(c, c->Rw.p, T.Sgv.p, T.Anew.p, MODE_RES);
     hipLaunchKernelGGL(k_div, B1(15 * N), dim3(256), 0, st, N, T.Sgv.p, T.Anew.p, (int64_t)15, T.Sgv.p);
-    // Gauss-point Jacobians
-    T.Jf.ensure((size_t)GP_OUT * GP_IN * NS);
+    // Gauss-point Jacobians, in the precision params.adjoint_tape asks for (the other copy released)
+    T.fp32 = c->prm.adjoint_tape == 1;
+    if (T.fp32) {
+        T.Jf.release();
+        T.Jr.release();
+        T.Jf32.ensure((size_t)GP_OUT * GP_IN * NGP);
+        T.Jr32.ensure((size_t)10 * RECON_IN * 5 * N);
+    } else {
+        T.Jf32.release();
+        T.Jr32.release();
+        T.Jf.ensure((size_t)GP_OUT * GP_IN * NGP);
+        T.Jr.ensure((size_t)10 * RECON_IN * 5 * N);
+    }
     T.agp.ensure(NS);
     GpArgs A;
     A.N = N;
     A.F = F;
-    A.NS = NS;
+    A.NGP = NGP;
     A.cfg = cfg_of(c);
     A.coef = T.coef.p;
     A.dt = T.dt.p;
@@ -795,18 +816,24 @@ void adj_linearize(cgks_ctx *c, const double *W, const double *G, const double *
     A.fr = c->fr.p;
     A.ftag = c->ftag.p;
     A.fngp = c->fngp.p;
+    A.gpoff = c->gpoff.p;
     A.bc = c->bc.p;
     A.Jf = T.Jf.p;
+    A.Jf32 = T.fp32 ? T.Jf32.p : nullptr;
     A.agp = T.agp.p;
     A.bad = c->bad.p;
     for (int p = 0; p * K_FACE < GP_IN; ++p)
         hipLaunchKernelGGL(k_face_jac<K_FACE>, B1(NS, 64), dim3(64), 0, st, A, p);
     // reconstruction Jacobians
-    T.Jr.ensure((size_t)10 * RECON_IN * 5 * N);
     const ReconArgs RA = recon_args(c, T.W.p, T.G.p, T.al.p);
-    for (int p = 0; p * K_RECON < RECON_IN; ++p)
-        hipLaunchKernelGGL(k_recon_jac<K_RECON>, dim3(blocks_for(N, OP_GROUP)), dim3(5 * OP_GROUP), 0, st, RA, p,
-                           T.Jr.p);
+    for (int p = 0; p * K_RECON < RECON_IN; ++p) {
+        if (T.fp32)
+            hipLaunchKernelGGL((k_recon_jac<K_RECON, float>), dim3(blocks_for(N, OP_GROUP)), dim3(5 * OP_GROUP), 0,
+                               st, RA, p, T.Jr32.p);
+        else
+            hipLaunchKernelGGL((k_recon_jac<K_RECON, double>), dim3(blocks_for(N, OP_GROUP)), dim3(5 * OP_GROUP), 0,
+                               st, RA, p, T.Jr.p);
+    }
     T.rev.ensure(6 * N);
     hipLaunchKernelGGL(k_rev_slots, B1(N), dim3(256), 0, st, N, c->Fi, c->cf_ptr.p, c->cf_face.p, c->fl.p, c->fr.p,
                        T.rev.p);
@@ -855,23 +882,25 @@ static void vjp_from_records(cgks_ctx *c, double *oW, double *oG, double *oA, bo
     FvArgs A;
     A.N = N;
     A.F = F;
-    A.NS = 4 * F;
+    A.NGP = c->NGP;
     A.cen = c->cen.p;
     A.gpx = c->gpx.p;
     A.gpw = c->gpw.p;
     A.gpn = c->gpn.p;
     A.fshift = c->fshift.p;
-    A.Jf = T.Jf.p;
     A.agp = T.agp.p;
     A.brec = T.brec.p;
     A.fl = c->fl.p;
     A.fr = c->fr.p;
     A.fngp = c->fngp.p;
+    A.gpoff = c->gpoff.p;
     A.bface = T.bface.p;
-    hipLaunchKernelGGL(k_face_vjp, B1(4 * F), dim3(256), 0, st, A);
+    if (T.fp32) hipLaunchKernelGGL(k_face_vjp<float>, B1(4 * F), dim3(256), 0, st, A, T.Jf32.p);
+    else hipLaunchKernelGGL(k_face_vjp<double>, B1(4 * F), dim3(256), 0, st, A, T.Jf.p);
     hipLaunchKernelGGL(k_coef_gather, B1(5 * N), dim3(256), 0, st, N, c->cf_ptr.p, c->cf_face.p, c->fr.p, T.dtL.p,
                        T.bface.p, T.bcoef.p, T.bdt.p);
-    hipLaunchKernelGGL(k_recon_vjp, B1(5 * N), dim3(256), 0, st, N, T.Jr.p, T.bcoef.p, T.bown.p, T.bslot.p);
+    if (T.fp32) hipLaunchKernelGGL(k_recon_vjp<float>, B1(5 * N), dim3(256), 0, st, N, T.Jr32.p, T.bcoef.p, T.bown.p, T.bslot.p);
+    else hipLaunchKernelGGL(k_recon_vjp<double>, B1(5 * N), dim3(256), 0, st, N, T.Jr.p, T.bcoef.p, T.bown.p, T.bslot.p);
     hipLaunchKernelGGL(k_recon_gather, B1(N), dim3(256), 0, st, N, c->slot_nb.p, T.rev.p, T.bown.p, T.bslot.p,
                        T.bdt.p, T.ddt.p, oW, oG, oA, acc ? 1 : 0);
 }
@@ -1117,7 +1146,7 @@ __global__ __launch_bounds__(64) void k_face_jvp(GpArgs A, const double *ct, con
     const int64_t f = gp >> 2;
     const int k = (int)(gp & 3);
     if (f >= A.F || k >= A.fngp[f]) return;
-    const int64_t F = A.F, N = A.N, NS = A.NS;
+    const int64_t F = A.F, N = A.N, NS = 4 * A.F;
     const int L = A.fl[f], R = A.fr[f];
     const double x[3] = {A.gpx[(3 * k) * F + f], A.gpx[(3 * k + 1) * F + f], A.gpx[(3 * k + 2) * F + f]};
     const double n[3] = {A.gpn[(3 * k) * F + f], A.gpn[(3 * k + 1) * F + f], A.gpn[(3 * k + 2) * F + f]};
@@ -1219,7 +1248,7 @@ void jvp_residual(cgks_ctx *c, const double *W, const double *G, const double *a
     GpArgs A;
     A.N = N;
     A.F = F;
-    A.NS = NS;
+    A.NGP = c->NGP;
     A.cfg = cfg_of(c);
     A.coef = cv.p;
     A.dt = dtv.p;
@@ -1233,8 +1262,10 @@ void jvp_residual(cgks_ctx *c, const double *W, const double *G, const double *a
     A.fr = c->fr.p;
     A.ftag = c->ftag.p;
     A.fngp = c->fngp.p;
+    A.gpoff = c->gpoff.p;
     A.bc = c->bc.p;
     A.Jf = nullptr;
+    A.Jf32 = nullptr;
     A.agp = nullptr;
     A.bad = c->bad.p;
     hipLaunchKernelGGL(k_face_jvp, B1(NS, 64), dim3(64), 0, st, A, ct.p, dtt.p, sv.p);

@@ -70,6 +70,7 @@ static void check_params(const cgks_params *p)
     if (p->cycle_gamma < 1 || p->cycle_gamma > 3) throw Error{CGKS_E_ARG, "cycle_gamma must be in 1..3"};
     if (p->cell_order < 0 || p->cell_order > 2) throw Error{CGKS_E_ARG, "cell_order must be 0, 1 or 2"};
     if (p->mixed_stall < 1) throw Error{CGKS_E_ARG, "mixed_stall must be at least 1"};
+    if (p->adjoint_tape != 0 && p->adjoint_tape != 1) throw Error{CGKS_E_ARG, "adjoint_tape must be 0 or 1"};
 }
 
 static void check_bad(cgks_ctx *c)
@@ -393,6 +394,7 @@ cgks_status cgks_default_params(cgks_params *p)
     p->cycle_gamma = 1;
     p->cell_order = 1;
     p->mixed_stall = 300;
+    p->adjoint_tape = 0;
     return CGKS_OK;
 }
 

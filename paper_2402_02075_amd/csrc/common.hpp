@@ -105,8 +105,10 @@ struct AdjTape {
     DBuf<double> rec;          // face records of the full mode (21F)
     DBuf<double> Anew, Sgv;    // CF product per cell (N), sum w S W n / |Omega| (15N)
     DBuf<double> agp;          // CF factor per Gauss-point slot (NS)
-    DBuf<double> Jf;           // [11*41][NS] Gauss-point Jacobians, output-major
+    bool fp32 = false;         // Jacobians stored in FP32 (params.adjoint_tape_fp32)
+    DBuf<double> Jf;           // [11*41][NGP] Gauss-point Jacobians, output-major, compact slots
     DBuf<double> Jr;           // [10*30][5N] reconstruction Jacobians per (component, cell)
+    DBuf<float> Jf32, Jr32;    // the same in FP32
     DBuf<int8_t> rev;          // [6][N] slot of the same face in the neighbour's list
     // cotangent work buffers
     DBuf<double> brec, bface, bcoef, bdt, bown, bslot, bat;
@@ -173,6 +175,7 @@ struct cgks_ctx {
     cgks::DBuf<double> vol, cen, mom2;  // [N], [3][N], [6][N]
     cgks::DBuf<int32_t> fl, fr, ftag;   // [F]
     cgks::DBuf<int32_t> fngp;           // [F] 3 or 4
+    cgks::DBuf<int32_t> gpoff;          // [F] first Gauss point of the face in a compact numbering (NGP)
     cgks::DBuf<int32_t> lmap;           // [NL] face-kernel lane -> 4 face + Gauss point, -1 idle
     int64_t NL = 0;                     // lanes of the face kernel (multiple of 256)
     cgks::DBuf<int4> lidx;              // [NL] {4 f + k, L, R, 8 tag + ngp}, f = -1 idle

@@ -526,6 +526,7 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
     std::vector<int32_t> hfl(F), hfr(F), htag(F), fnode(4 * F), fshn(2 * F, -1);
     std::vector<int32_t> deg(N + 1, 0);
     int64_t ngp = 0;
+    std::vector<int32_t> gpoff(F);  // first Gauss point of each face in a compact numbering
     std::vector<int32_t> lmap;  // face-kernel lanes: 4 f + k, or -1 for an idle lane
     lmap.reserve(4 * F + 256);
     for (int64_t f = 0; f < F; ++f) {
@@ -535,6 +536,7 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
         htag[f] = r.tag;
         const int *lf = face_of(ctype[r.L], r.lfL);
         const int nn = lf[3] < 0 ? 3 : 4;
+        gpoff[f] = (int32_t)ngp;
         ngp += nn;
         // pack faces into 64-lane waves, nn lanes each, never splitting a face across waves
         if ((int64_t)(lmap.size() % 64) + nn > 64)
@@ -621,6 +623,7 @@ void mesh_build(cgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t N, cons
     while (lmap.size() % 256) lmap.push_back(-1);
     c->NL = (int64_t)lmap.size();
     c->lmap.upload(lmap, s);
+    c->gpoff.upload(gpoff, s);
     DBuf<double> dxyz;
     DBuf<int32_t> dhexn, dfnode, dfsh;
     dxyz.upload(xyz, 3 * n_nodes, s);

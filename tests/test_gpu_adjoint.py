@@ -6,11 +6,13 @@
 * VJP of the fine operator against a forward-mode dual-number JVP that uses no recorded
   Jacobian (dot products equal to 1e-12).
 * VJP of the coarse KFVS operator and of the wall force, likewise.
+* The same VJP with the Jacobians stored in FP32, against the JVP and the FP64 tape.
 * torch.autograd path through ResidualFunction.
 * Gradients of the lower-wall x-force with respect to the inflow Mach number and
   the bump amplitude returned by the library's adjoint solve, against central
   differences (step 1e-6) of the converged objective, on a small hexahedral bump
-  channel that converges to the round-off floor.
+  channel that converges to the round-off floor; and against the oracle's own differences on a
+  smaller channel, with the FP64 and the FP32 tape.
 Inputs come from the seeded generators; no expected value comes from the library.
 """
 import numpy as np
@@ -157,6 +159,45 @@ def test_vjp_residual_vs_oracle(torch, ad, oracle):
     rel = abs(lhs - rhs) / abs(rhs)
     say(f"    vjp {lhs:.12e} oracle fd {rhs:.12e} rel {rel:.2e}")
     assert rel < 1e-6
+
+
+def test_fp32_tape(torch, ad):
+    """Jacobians stored in FP32 (params.adjoint_tape = 1) on the mixed channel (tetrahedra, pyramids,
+    prisms, hexahedra: triangular and quadrilateral faces).  Every stored entry is rounded to
+    2^-24 relative and the products still accumulate in FP64, so <J^T u, v> stays within 2^-24 of
+    the summed magnitudes of the dual-number JVP's <u, J v>, and each cotangent within 1e-6 of the
+    largest of its kind from the FP64 tape (measured: 2e-10 and 1e-7)."""
+    m = MESHES["mixed"]()
+    say(f"[gpu] fp32 tape mixed cells={m.n_cells}")
+    S = ad.channel_solver(m, 0.5, agglomerate=False)
+    W, G, al = _smooth(torch, m, seed=17)
+    N = m.n_cells
+    g = torch.Generator(device="cuda").manual_seed(9)
+    u = (_randn(torch, g, 5, N), _randn(torch, g, 15, N), _randn(torch, g, N))
+    v = (_randn(torch, g, 5, N) * W.abs().mean(1, keepdim=True), _randn(torch, g, 15, N) * 0.1,
+         _randn(torch, g, N) * 0.1)
+    dR, dG, dA = S.jvp_residual(W, G, al, *v)
+    lhs = float((u[0] * dR).sum() + (u[1] * dG).sum() + (u[2] * dA).sum())
+    S.linearize(W, G, al)
+    b64 = S.vjp_residual(*u)
+    S.set_params(adjoint_tape=1)
+    S.linearize(W, G, al)
+    b32 = S.vjp_residual(*u)
+    rhs = float(sum((b * x).sum() for b, x in zip(b32, v)))
+    scale = float(sum(t.abs().sum() for t in (u[0] * dR, u[1] * dG, u[2] * dA))
+                  + sum((b * x).abs().sum() for b, x in zip(b32, v)))
+    say(f"    <u, Jv> {lhs:.15e} <J^T u, v> (FP32 tape) {rhs:.15e} diff/scale {abs(lhs - rhs) / scale:.2e}")
+    assert abs(lhs - rhs) <= 2.0 ** -24 * scale
+    for name, x32, x64 in zip(("W", "G", "alpha"), b32, b64):
+        d = float((x32 - x64).abs().max()) / float(x64.abs().max())
+        say(f"    bar{name}: max |FP32 - FP64 tape| / max |FP64 tape| {d:.2e}")
+        assert 0.0 < d <= 1e-6  # > 0: the FP32 copy is the one in use
+    # back to the FP64 tape: the same cotangents as before, bit for bit
+    S.set_params(adjoint_tape=0)
+    S.linearize(W, G, al)
+    for x, y in zip(S.vjp_residual(*u), b64):
+        assert torch.equal(x, y)
+    S.close()
 
 
 def test_vjp_kfvs_dot(torch, ad):
@@ -313,4 +354,11 @@ def test_adjoint_gradients_vs_oracle_fd(torch, ad):
     for key in ("dJ_dMach", "dJ_dA"):
         rel = abs(gr[key] - gold[key]) / abs(gold[key])
         say(f"    {key}: library adjoint {gr[key]:.12e} oracle differences {gold[key]:.12e} rel {rel:.2e}")
+        assert rel < 1e-6
+    # the same with the Jacobians stored in FP32
+    S.set_params(adjoint_tape=1)
+    gr = ad.gradients(S, mesh_fn, amp, mach, W, G, al, max_iter=40000, tol=1e-12)
+    for key in ("dJ_dMach", "dJ_dA"):
+        rel = abs(gr[key] - gold[key]) / abs(gold[key])
+        say(f"    {key}: FP32 tape {gr[key]:.12e} rel {rel:.2e}")
         assert rel < 1e-6

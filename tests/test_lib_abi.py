@@ -32,7 +32,7 @@ def test_default_params_without_gpu():
     assert p.gamma == 1.4 and p.levels == 3 and p.passes == 3 and p.seed == 1
     assert p.nu_pre[0] == 1 and p.nu_post[0] == 0
     assert abs(p.skew_sin - 0.17364817766693033) < 1e-15
-    assert p.cell_order == 1 and p.mixed_stall == 300
+    assert p.cell_order == 1 and p.mixed_stall == 300 and p.adjoint_tape == 0
 
 
 def test_params_struct_size_matches_the_header():
