@@ -19,7 +19,8 @@ levels), plus isolated residual evaluations, the face-flux kernel's roofline, an
 free stream in FP64 and mixed precision within a budget (drop, drag coefficient, density-field and
 drag differences between the two).  Extra workloads (each optional): the 1.47M-cell sphere at the
 same conditions, the inviscid bump channel (about 189k mixed cells), the hexahedral channel that
-converges to round-off, the explicit-against-V-cycle comparison, the adjoint, and the CPU oracle
+converges to round-off, the explicit-against-V-cycle comparison, the adjoint (its gradient check,
+and its costs and tape size on the headline mesh with the Jacobians in FP32), and the CPU oracle
 on a bounded sample of the headline mesh.
 """
 from __future__ import annotations
@@ -488,27 +489,21 @@ def adjoint_check(torch, cg, mg):
     return out
 
 
-def adjoint_sphere(torch, cg, mg, develop=200):
-    """Linearisation, fine VJP and adjoint iterations on the 6.14M-cell sphere with the Jacobians
-    stored in FP32 (params.adjoint_tape = 1), and the device memory the context and the tape hold
-    (hipMemGetInfo differences).  The state is the developed flow after `develop` V-cycles, not a
-    converged one: the figures are costs, the adjoint iterates are not a gradient."""
-    torch.cuda.synchronize()
-    free0 = torch.cuda.mem_get_info()[0]
-    m, S, sizes, setup = sphere_solver(cg, mg, 6, 33, 12)
-    N = m.n_cells
-    W, G, al = free_stream(torch, mg, N, (0.2, 0.0, 0.0))
-    S.vcycle(W, G, al, develop, 0.0)
+def adjoint_costs(torch, mg, S, W, G, al, label):
+    """Linearisation with the Jacobians stored in FP32 (params.adjoint_tape = 1), fine VJP and
+    adjoint iterations at (W, G, al) on the sphere solver S, and the device memory the tape holds
+    (hipMemGetInfo differences).  The state is a developed flow, not a converged one: the figures
+    are costs, the adjoint iterates are not a gradient."""
+    N = S.n_cells
     torch.cuda.synchronize()
     free1 = torch.cuda.mem_get_info()[0]
-    log(f"adjoint sphere: {N} cells, context and state {(free0 - free1) / 2**30:.1f} GiB")
     S.set_params(adjoint_tape=1)
     t0 = time.perf_counter()
     S.linearize(W, G, al)
     torch.cuda.synchronize()
     t_lin = time.perf_counter() - t0
     free2 = torch.cuda.mem_get_info()[0]
-    log(f"adjoint sphere: linearised in {t_lin:.2f} s, tape {(free1 - free2) / 2**30:.1f} GiB")
+    log(f"adjoint {label}: linearised in {t_lin:.2f} s, FP32 tape {(free1 - free2) / 2**30:.1f} GiB")
     g = torch.Generator(device="cuda").manual_seed(1)
     w = [torch.randn(*sh, dtype=torch.float64, device="cuda", generator=g) for sh in ((5, N), (15, N), (N,))]
     S.vjp_residual(*w)
@@ -526,12 +521,28 @@ def adjoint_sphere(torch, cg, mg, develop=200):
     torch.cuda.synchronize()
     t_it = (time.perf_counter() - t0) / max(r["iterations"], 1) * 1e3
     free3 = torch.cuda.mem_get_info()[0]
-    out = {"workload": "viscous sphere 6.14M cells, developed state (200 V-cycles), Jacobians in FP32",
-           "cells": N, "linearize_s": t_lin, "vjp_residual_ms": t_vjp, "adjoint_iteration_ms": t_it,
-           "context_and_state_GiB": (free0 - free1) / 2**30, "tape_GiB": (free1 - free2) / 2**30,
-           "tape_and_adjoint_work_bytes_per_cell": (free1 - free3) / N,
-           "device_total_used_GiB": (free0 - free3) / 2**30}
-    log(f"adjoint sphere: vjp {t_vjp:.2f} ms, iteration {t_it:.2f} ms, total {(free0 - free3) / 2**30:.1f} GiB")
+    S.set_params(adjoint_tape=0)
+    log(f"adjoint {label}: vjp {t_vjp:.2f} ms, iteration {t_it:.2f} ms")
+    return {"workload": f"{label}, developed state, Jacobians in FP32", "cells": N, "linearize_s": t_lin,
+            "vjp_residual_ms": t_vjp, "adjoint_iteration_ms": t_it, "tape_GiB": (free1 - free2) / 2**30,
+            "tape_and_adjoint_work_bytes_per_cell": (free1 - free3) / N}
+
+
+def adjoint_sphere(torch, cg, mg, develop=200):
+    """adjoint_costs on the 6.14M-cell sphere after `develop` V-cycles, with the context's own
+    device memory beside it."""
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    m, S, sizes, setup = sphere_solver(cg, mg, 6, 33, 12)
+    W, G, al = free_stream(torch, mg, m.n_cells, (0.2, 0.0, 0.0))
+    S.vcycle(W, G, al, develop, 0.0)
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    out = adjoint_costs(torch, mg, S, W, G, al, "viscous sphere 6.14M cells")
+    out["context_and_state_GiB"] = (free0 - free1) / 2**30
+    out["device_total_used_GiB"] = (free0 - torch.cuda.mem_get_info()[0]) / 2**30
+    log(f"adjoint sphere: context and state {out['context_and_state_GiB']:.1f} GiB, "
+        f"total {out['device_total_used_GiB']:.1f} GiB")
     S.close()
     return out
 
@@ -835,6 +846,8 @@ def main():
     log(f"headline: V-cycle {out['median_event_ms_per_step']:.2f} ms FP64, {out['mixed']['median_event_ms_per_step']:.2f} "
         f"ms mixed; face kernel {h['face_ms']:.3f} ms = {achieved:.1f} TFLOP/s")
     W, G, al = h.pop("state")
+    if not args.no_adjoint and not args.headline_only:
+        out["adjoint_sphere"] = adjoint_costs(torch, mg, S, W, G, al, "viscous sphere 6.14M cells")
     del W, G, al
     if args.converge and not args.headline_only:
         out["headline_convergence"] = sphere_convergence(torch, mg, S, N, args.converge)
