@@ -43,6 +43,18 @@
 namespace cgks {
 
 constexpr int GP_IN = 41, GP_OUT = 11;
+
+// The Gauss-point Jacobians are stored in tiles of 64 columns: entry r of column s at
+// ((s / 64) R + r) 64 + s % 64 for R entries per column, so the lanes of a wave that handle
+// consecutive columns read each entry with one coalesced load and stream through one contiguous
+// tile (R x 64 values) instead of R rows far apart (their columns are the compact Gauss points,
+// 48 to 64 per wave, which would leave short unaligned pieces of each row).  The reconstruction
+// Jacobians stay row-major: a wave there covers 64 consecutive columns exactly.
+__host__ __device__ constexpr int64_t tiled_at(int64_t s, int64_t r, int64_t R)
+{
+    return ((s >> 6) * R + r) * 64 + (s & 63);
+}
+__host__ __device__ constexpr size_t tiled_size(int64_t n, int64_t R) { return (size_t)((n + 63) >> 6) * 64 * R; }
 constexpr int K_FACE = 4;   // tangent directions per pass of the Gauss-point Jacobian
 constexpr int K_RECON = 6;  // tangent directions per pass of the reconstruction Jacobian
 
@@ -125,7 +137,7 @@ struct GpArgs {
     const uint8_t *dtL;
     const int32_t *fl, *fr, *ftag, *fngp, *gpoff;
     const BcTable *bc;
-    double *Jf, *agp;  // Jf [11*41][NGP] in FP64, or
+    double *Jf, *agp;  // Jf: 11*41 per compact Gauss point (tiled_at) in FP64, or
     float *Jf32;       // the same in FP32 (when not null)
     int32_t *bad;
 };
@@ -229,7 +241,7 @@ template <int K> __global__ __launch_bounds__(64) void k_face_jac(GpArgs A, int 
             const int q = pass * K + j;
             if (q < GP_IN) {
                 const double v = ok ? out[o].d[j] : 0.0;
-                const int64_t at = (int64_t)(o * GP_IN + q) * NGP + col;
+                const int64_t at = tiled_at(col, o * GP_IN + q, GP_OUT * GP_IN);
                 if (A.Jf32) A.Jf32[at] = (float)v;
                 else A.Jf[at] = v;
             }
@@ -297,15 +309,16 @@ template <class TJ> __global__ __launch_bounds__(256) void k_face_vjp(FvArgs A, 
             bo[5 + q] = wS * (n[0] * br[5 + 3 * q] + n[1] * br[6 + 3 * q] + n[2] * br[7 + 3 * q]);
         }
         bo[10] = br[20] * others;
-        // half an output row at a time: about 20 loads in flight, not all 451 (keeps the wave count up)
+        // half an output row at a time: about 20 loads in flight, not all 451 (keeps the wave count
+        // up; a whole row per step with FP32 entries measured the same)
 #pragma unroll
         for (int o = 0; o < GP_OUT; ++o) {
-            const TJ *J = Jf + (int64_t)o * GP_IN * NGP + A.gpoff[f] + k;
+            const TJ *J = Jf + tiled_at((int64_t)A.gpoff[f] + k, o * GP_IN, GP_OUT * GP_IN);
 #pragma unroll
-            for (int q = 0; q < 21; ++q) bi[q] += (double)J[(int64_t)q * NGP] * bo[o];
+            for (int q = 0; q < 21; ++q) bi[q] += (double)J[q * 64] * bo[o];
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int q = 21; q < GP_IN; ++q) bi[q] += (double)J[(int64_t)q * NGP] * bo[o];
+            for (int q = 21; q < GP_IN; ++q) bi[q] += (double)J[q * 64] * bo[o];
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
@@ -790,12 +803,12 @@ void adj_linearize(cgks_ctx *c, const double *W, const double *G, const double *
     if (T.fp32) {
         T.Jf.release();
         T.Jr.release();
-        T.Jf32.ensure((size_t)GP_OUT * GP_IN * NGP);
+        T.Jf32.ensure(tiled_size(NGP, GP_OUT * GP_IN));
         T.Jr32.ensure((size_t)10 * RECON_IN * 5 * N);
     } else {
         T.Jf32.release();
         T.Jr32.release();
-        T.Jf.ensure((size_t)GP_OUT * GP_IN * NGP);
+        T.Jf.ensure(tiled_size(NGP, GP_OUT * GP_IN));
         T.Jr.ensure((size_t)10 * RECON_IN * 5 * N);
     }
     T.agp.ensure(NS);

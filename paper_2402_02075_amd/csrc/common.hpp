@@ -105,8 +105,8 @@ struct AdjTape {
     DBuf<double> rec;          // face records of the full mode (21F)
     DBuf<double> Anew, Sgv;    // CF product per cell (N), sum w S W n / |Omega| (15N)
     DBuf<double> agp;          // CF factor per Gauss-point slot (NS)
-    bool fp32 = false;         // Jacobians stored in FP32 (params.adjoint_tape_fp32)
-    DBuf<double> Jf;           // [11*41][NGP] Gauss-point Jacobians, output-major, compact slots
+    bool fp32 = false;         // Jacobians stored in FP32 (params.adjoint_tape = 1)
+    DBuf<double> Jf;           // Gauss-point Jacobians, 11*41 per compact Gauss point, 64-column tiles
     DBuf<double> Jr;           // [10*30][5N] reconstruction Jacobians per (component, cell)
     DBuf<float> Jf32, Jr32;    // the same in FP32
     DBuf<int8_t> rev;          // [6][N] slot of the same face in the neighbour's list
