@@ -234,7 +234,8 @@ cgks_status cgks_wall_force(cgks_ctx *ctx, const double *W, const double *G, con
  * the face step; per cell and component those of the HWENO coefficients (Sec. 3)
  * with respect to the stencil data; per cell that of the local time step.
  * Device memory kept: the Jacobians, 451 NGP + 1500 N values (NGP = Gauss points of all
- * faces, cgks_mesh_info[4]; FP64, or FP32 with params.adjoint_tape = 1), and about
+ * faces, cgks_mesh_info[4], rounded up to a multiple of 64; FP64, or FP32 with
+ * params.adjoint_tape = 1), and about
  * 300 N + 150 F doubles of state and work buffers (some 100 N more once cgks_adjoint_solve
  * has run), released with the context.  CGKS_E_PHYS if a Gauss-point state is non-physical.  Any later
  * cgks_set_mesh, cgks_set_bc, cgks_set_params or cgks_agglomerate invalidates it.
