@@ -277,8 +277,8 @@ cgks_status cgks_vjp_wall_force(cgks_ctx *ctx, int32_t tag, const double *e, dou
 cgks_status cgks_vjp_kfvs(cgks_ctx *ctx, int32_t level, const double *Wc, const double *barRc, double *barWc);
 
 /*
- * Parameter directions for the gradients of cgks_adjoint_solve (the inflow Mach number and a shape
- * parameter of the spec adjoint workload, or any other scalar parameters).  Parameter k
+ * Parameter directions for the gradients of cgks_adjoint_solve (for instance the inflow Mach number
+ * and the bump amplitude of the bump channel's drag sensitivities, or any other scalar parameters).  Parameter k
  * moves, per unit, the far-field primitives (rho, u, v, w, p) of boundary tag t by
  * dprim[(k * 64 + t) * 5 + q] (host, nullable = no change) and node j of the mesh (caller's node
  * numbering) by dxyz[k * 3 n_nodes + 3 j + d] (host, nullable = no node moves); n_params <= 8.
