@@ -44,3 +44,29 @@ def test_params_struct_size_matches_the_header():
     cgks.lib().cgks_default_params(ctypes.cast(buf, ctypes.c_void_p))
     assert bytes(buf[n:]) == bytes([0xA5] * 64)
     assert any(b != 0xA5 for b in buf[n - 8:n])  # the last field was written
+
+
+def test_invalid_params_rejected_before_any_device_work():
+    """cgks_create checks the parameters before it touches the device: each out-of-range field
+    returns CGKS_E_ARG and no context (so this runs without a GPU), and the defaults pass the
+    check (their create then fails only for the missing device, or succeeds on a GPU machine)."""
+    from paper_2402_02075_amd import cgks
+    bad = [("gamma", 1.0), ("gamma", 1.7), ("cfl", 0.0), ("prandtl", 0.0), ("gamma_lin", 1.0),
+           ("levels", 0), ("levels", 9), ("passes", 17), ("precision", 2), ("coarse_smoother", 2),
+           ("relax_sweeps", 65), ("cycle_gamma", 4), ("cell_order", 3), ("mixed_stall", 0),
+           ("adjoint_tape", 2)]
+    for field, value in bad:
+        p = cgks.default_params()
+        setattr(p, field, value)
+        h = ctypes.c_void_p()
+        code = cgks.lib().cgks_create(ctypes.byref(p), ctypes.byref(h))
+        assert code == cgks.E_ARG and not h.value, (field, value, code)
+    p = cgks.default_params()
+    p.viscous, p.mu = 1, 0.0  # viscous flow needs a viscosity
+    h = ctypes.c_void_p()
+    assert cgks.lib().cgks_create(ctypes.byref(p), ctypes.byref(h)) == cgks.E_ARG and not h.value
+    p = cgks.default_params()
+    code = cgks.lib().cgks_create(ctypes.byref(p), ctypes.byref(h))
+    assert code in (cgks.OK, cgks.E_DEVICE), code
+    if code == cgks.OK:
+        cgks.lib().cgks_destroy(h)
