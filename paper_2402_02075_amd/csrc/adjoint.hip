@@ -800,16 +800,28 @@ void adj_linearize(cgks_ctx *c, const double *W, const double *G, const double *
     hipLaunchKernelGGL(k_div, B1(15 * N), dim3(256), 0, st, N, T.Sgv.p, T.Anew.p, (int64_t)15, T.Sgv.p);
     // Gauss-point Jacobians, in the precision params.adjoint_tape asks for (the other copy released)
     T.fp32 = c->prm.adjoint_tape == 1;
-    if (T.fp32) {
+    const size_t nJf = tiled_size(NGP, GP_OUT * GP_IN), nJr = (size_t)10 * RECON_IN * 5 * N;
+    try {
+        if (T.fp32) {
+            T.Jf.release();
+            T.Jr.release();
+            T.Jf32.ensure(nJf);
+            T.Jr32.ensure(nJr);
+        } else {
+            T.Jf32.release();
+            T.Jr32.release();
+            T.Jf.ensure(nJf);
+            T.Jr.ensure(nJr);
+        }
+    } catch (const Error &e) {
+        // out of device memory: hold none of the Jacobians, and say what they need
         T.Jf.release();
         T.Jr.release();
-        T.Jf32.ensure(tiled_size(NGP, GP_OUT * GP_IN));
-        T.Jr32.ensure((size_t)10 * RECON_IN * 5 * N);
-    } else {
         T.Jf32.release();
         T.Jr32.release();
-        T.Jf.ensure(tiled_size(NGP, GP_OUT * GP_IN));
-        T.Jr.ensure((size_t)10 * RECON_IN * 5 * N);
+        const double gb = double(nJf + nJr) * (T.fp32 ? 4.0 : 8.0) / 1e9;
+        throw Error{e.code, e.msg + " (the recorded Jacobians need " + std::to_string(gb) + " GB" +
+                                (T.fp32 ? ")" : "; params.adjoint_tape = 1 stores them in FP32, in half of that)")};
     }
     T.agp.ensure(NS);
     GpArgs A;

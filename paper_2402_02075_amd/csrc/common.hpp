@@ -29,8 +29,15 @@ template <class T> struct DBuf {
     void alloc(size_t count)
     {
         release();
+        if (!count) return;
+        const hipError_t e = hipMalloc(&p, sizeof(T) * count);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();  // a refused allocation must not surface again at a later check
+            throw ::cgks::Error{CGKS_E_DEVICE, "hipMalloc of " + std::to_string(sizeof(T) * count) +
+                                                   " bytes: " + hipGetErrorString(e)};
+        }
         n = count;
-        if (count) CGKS_HIP(hipMalloc(&p, sizeof(T) * count));
     }
     void release()
     {
