@@ -233,9 +233,9 @@ cgks_status cgks_wall_force(cgks_ctx *ctx, const double *W, const double *G, con
  * Sec. 3.3) with respect to the two reconstructed states, their gradients and
  * the face step; per cell and component those of the HWENO coefficients (Sec. 3)
  * with respect to the stencil data; per cell that of the local time step.
- * Device memory kept: the Jacobians, 451 NGP + 1500 N values (NGP = Gauss points of all
- * faces, cgks_mesh_info[4], rounded up to a multiple of 64; FP64, or FP32 with
- * params.adjoint_tape = 1), and about
+ * Device memory kept: the Jacobians, 452 NGP + 1500 N values (NGP = Gauss points of all
+ * faces, cgks_mesh_info[4], rounded up to a multiple of 64; 451 values per Gauss point padded to
+ * 452; FP64, or FP32 with params.adjoint_tape = 1), and about
  * 300 N + 150 F doubles of state and work buffers (some 100 N more once cgks_adjoint_solve
  * has run), released with the context.  Its dual-number kernels also need about 12 KB of
  * scratch memory per GPU lane in flight (a few GB), which the HIP runtime allocates at launch:

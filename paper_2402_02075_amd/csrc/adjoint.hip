@@ -44,17 +44,31 @@ namespace cgks {
 
 constexpr int GP_IN = 41, GP_OUT = 11;
 
-// The Gauss-point Jacobians are stored in tiles of 64 columns: entry r of column s at
-// ((s / 64) R + r) 64 + s % 64 for R entries per column, so the lanes of a wave that handle
-// consecutive columns read each entry with one coalesced load and stream through one contiguous
-// tile (R x 64 values) instead of R rows far apart (their columns are the compact Gauss points,
-// 48 to 64 per wave, which would leave short unaligned pieces of each row).  The reconstruction
-// Jacobians stay row-major: a wave there covers 64 consecutive columns exactly.
-__host__ __device__ constexpr int64_t tiled_at(int64_t s, int64_t r, int64_t R)
+// The Gauss-point Jacobians are stored in tiles of 64 columns (the compact Gauss points), and
+// within a tile in runs of JG = 16 / (entry size) consecutive entries of one column: entry r of
+// column s at ((s / 64) JRP + (r / JG) JG) 64 + (s % 64) JG + r % JG, with the 451 entries of a
+// column padded to JRP = 452.  The lanes of a wave, which handle consecutive columns, then read
+// 16 bytes each per load and stream through one contiguous tile (JRP x 64 entries) instead of 451
+// rows far apart (48 to 64 columns per wave would leave short unaligned pieces of each row).  The
+// reconstruction Jacobians stay row-major: a wave there covers 64 consecutive columns exactly.
+constexpr int JRP = 452;
+template <int JG> __host__ __device__ constexpr int64_t jf_at(int64_t s, int64_t r)
 {
-    return ((s >> 6) * R + r) * 64 + (s & 63);
+    return ((s >> 6) * JRP + (r / JG) * JG) * 64 + (s & 63) * JG + (r % JG);
 }
-__host__ __device__ constexpr size_t tiled_size(int64_t n, int64_t R) { return (size_t)((n + 63) >> 6) * 64 * R; }
+__host__ __device__ constexpr size_t jf_size(int64_t n) { return (size_t)((n + 63) >> 6) * 64 * JRP; }
+__device__ __forceinline__ void unpack(const float4 &v, float e[4])
+{
+    e[0] = v.x;
+    e[1] = v.y;
+    e[2] = v.z;
+    e[3] = v.w;
+}
+__device__ __forceinline__ void unpack(const double2 &v, double e[2])
+{
+    e[0] = v.x;
+    e[1] = v.y;
+}
 constexpr int K_FACE = 4;   // tangent directions per pass of the Gauss-point Jacobian
 constexpr int K_RECON = 6;  // tangent directions per pass of the reconstruction Jacobian
 
@@ -137,8 +151,8 @@ struct GpArgs {
     const uint8_t *dtL;
     const int32_t *fl, *fr, *ftag, *fngp, *gpoff;
     const BcTable *bc;
-    double *Jf, *agp;  // Jf: 11*41 per compact Gauss point (tiled_at) in FP64, or
-    float *Jf32;       // the same in FP32 (when not null)
+    double *Jf, *agp;  // Jf: 11*41 per compact Gauss point (jf_at<2>) in FP64, or
+    float *Jf32;       // the same in FP32 (jf_at<4>; when not null)
     int32_t *bad;
 };
 
@@ -241,9 +255,9 @@ template <int K> __global__ __launch_bounds__(64) void k_face_jac(GpArgs A, int 
             const int q = pass * K + j;
             if (q < GP_IN) {
                 const double v = ok ? out[o].d[j] : 0.0;
-                const int64_t at = tiled_at(col, o * GP_IN + q, GP_OUT * GP_IN);
-                if (A.Jf32) A.Jf32[at] = (float)v;
-                else A.Jf[at] = v;
+                const int r = o * GP_IN + q;
+                if (A.Jf32) A.Jf32[jf_at<4>(col, r)] = (float)v;
+                else A.Jf[jf_at<2>(col, r)] = v;
             }
         }
     if (pass == 0) A.agp[gp] = ok ? out[10].v : 1.0;
@@ -309,16 +323,24 @@ template <class TJ> __global__ __launch_bounds__(256) void k_face_vjp(FvArgs A, 
             bo[5 + q] = wS * (n[0] * br[5 + 3 * q] + n[1] * br[6 + 3 * q] + n[2] * br[7 + 3 * q]);
         }
         bo[10] = br[20] * others;
-        // half an output row at a time: about 20 loads in flight, not all 451 (keeps the wave count
-        // up; a whole row per step with FP32 entries measured the same)
+        // the column's entries in memory order, 16 bytes per load, about 20 entries in flight at a
+        // time, not all 451 (keeps the wave count up); each bi[q] still sums over o in order
+        constexpr int JG = 16 / sizeof(TJ);
+        using V = typename std::conditional<sizeof(TJ) == 4, float4, double2>::type;
+        const V *J = reinterpret_cast<const V *>(Jf + jf_at<JG>((int64_t)A.gpoff[f] + k, 0));
+        constexpr int NG = (GP_OUT * GP_IN + JG - 1) / JG, BATCH = 20 / JG;
 #pragma unroll
-        for (int o = 0; o < GP_OUT; ++o) {
-            const TJ *J = Jf + tiled_at((int64_t)A.gpoff[f] + k, o * GP_IN, GP_OUT * GP_IN);
+        for (int g0 = 0; g0 < NG; g0 += BATCH) {
 #pragma unroll
-            for (int q = 0; q < 21; ++q) bi[q] += (double)J[q * 64] * bo[o];
-            __builtin_amdgcn_sched_barrier(0);
+            for (int g = g0; g < g0 + BATCH && g < NG; ++g) {
+                TJ e[JG];
+                unpack(J[g * 64], e);
 #pragma unroll
-            for (int q = 21; q < GP_IN; ++q) bi[q] += (double)J[q * 64] * bo[o];
+                for (int t = 0; t < JG; ++t) {
+                    const int r = g * JG + t;
+                    if (r < GP_OUT * GP_IN) bi[r % GP_IN] += (double)e[t] * bo[r / GP_IN];
+                }
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
@@ -800,7 +822,7 @@ void adj_linearize(cgks_ctx *c, const double *W, const double *G, const double *
     hipLaunchKernelGGL(k_div, B1(15 * N), dim3(256), 0, st, N, T.Sgv.p, T.Anew.p, (int64_t)15, T.Sgv.p);
     // Gauss-point Jacobians, in the precision params.adjoint_tape asks for (the other copy released)
     T.fp32 = c->prm.adjoint_tape == 1;
-    const size_t nJf = tiled_size(NGP, GP_OUT * GP_IN), nJr = (size_t)10 * RECON_IN * 5 * N;
+    const size_t nJf = jf_size(NGP), nJr = (size_t)10 * RECON_IN * 5 * N;
     try {
         if (T.fp32) {
             T.Jf.release();
