@@ -50,13 +50,21 @@ constexpr int GP_IN = 41, GP_OUT = 11;
 // column padded to JRP = 452.  The lanes of a wave, which handle consecutive columns, then read
 // 16 bytes each per load and stream through one contiguous tile (JRP x 64 entries) instead of 451
 // rows far apart (48 to 64 columns per wave would leave short unaligned pieces of each row).  The
-// reconstruction Jacobians stay row-major: a wave there covers 64 consecutive columns exactly.
+// reconstruction Jacobians need no tiles (a wave there covers 64 consecutive columns exactly):
+// jr_at below keeps them row-major over the columns, in the same 16-byte runs.
 constexpr int JRP = 452;
 template <int JG> __host__ __device__ constexpr int64_t jf_at(int64_t s, int64_t r)
 {
     return ((s >> 6) * JRP + (r / JG) * JG) * 64 + (s & 63) * JG + (r % JG);
 }
 __host__ __device__ constexpr size_t jf_size(int64_t n) { return (size_t)((n + 63) >> 6) * 64 * JRP; }
+// The reconstruction Jacobians: entry r = 30 o + q of column t = c N + i (component c, cell i) at
+// ((r / JG) 5N + t) JG + r % JG: row-major over the columns, so that the 64 consecutive columns of
+// a wave read one contiguous kilobyte per load, in runs of JG = 16 / (entry size) entries.
+template <int JG> __host__ __device__ constexpr int64_t jr_at(int64_t t, int64_t r, int64_t N5)
+{
+    return ((r / JG) * N5 + t) * JG + (r % JG);
+}
 __device__ __forceinline__ void unpack(const float4 &v, float e[4])
 {
     e[0] = v.x;
@@ -440,7 +448,7 @@ template <int K, int C, class TJ> __device__ __forceinline__ void recon_jac_comp
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int q = pass * K + j;
-            if (q < RECON_IN) Jr[(int64_t)(o * RECON_IN + q) * 5 * N + C * N + i] = (TJ)r[o].d[j];
+            if (q < RECON_IN) Jr[jr_at<16 / sizeof(TJ)>(C * N + i, o * RECON_IN + q, 5 * N)] = (TJ)r[o].d[j];
         }
 }
 
@@ -469,13 +477,32 @@ __global__ __launch_bounds__(256) void k_recon_vjp(int64_t N, const TJ *Jr, cons
     double br[10];
 #pragma unroll
     for (int o = 0; o < 10; ++o) br[o] = bcoef[i * 50 + 10 * C + o];
+    // the column's entries in memory order, 16 bytes per load, in batches; each s[q] still sums
+    // over o in order
+    constexpr int JG = 16 / sizeof(TJ), NG = 10 * RECON_IN / JG, BATCH = 32 / JG;
+    using V = typename std::conditional<sizeof(TJ) == 4, float4, double2>::type;
+    const V *Jv = reinterpret_cast<const V *>(Jr) + t;  // run g at Jv[g 5N]
+    double s[RECON_IN];
+#pragma unroll
+    for (int q = 0; q < RECON_IN; ++q) s[q] = 0.0;
+#pragma unroll
+    for (int g0 = 0; g0 < NG; g0 += BATCH) {
+#pragma unroll
+        for (int g = g0; g < g0 + BATCH && g < NG; ++g) {
+            TJ e[JG];
+            unpack(Jv[(int64_t)g * 5 * N], e);
+#pragma unroll
+            for (int u = 0; u < JG; ++u) {
+                const int r = g * JG + u;
+                s[r % RECON_IN] += (double)e[u] * br[r / RECON_IN];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int q = 0; q < RECON_IN; ++q) {
-        double s = 0.0;
-#pragma unroll
-        for (int o = 0; o < 10; ++o) s += (double)Jr[(int64_t)(o * RECON_IN + q) * 5 * N + t] * br[o];
-        if (q < 6) bown[(C * 6 + q) * N + i] = s;
-        else bslot[((int64_t)(C * 6 + (q - 6) / 4) * 4 + (q - 6) % 4) * N + i] = s;
+        if (q < 6) bown[(C * 6 + q) * N + i] = s[q];
+        else bslot[((int64_t)(C * 6 + (q - 6) / 4) * 4 + (q - 6) % 4) * N + i] = s[q];
     }
 }
 
