@@ -237,8 +237,8 @@ cgks_status cgks_wall_force(cgks_ctx *ctx, const double *W, const double *G, con
  * faces, cgks_mesh_info[4], rounded up to a multiple of 64; 451 values per Gauss point padded to
  * 452; FP64, or FP32 with params.adjoint_tape = 1), and about
  * 300 N + 150 F doubles of state and work buffers (some 100 N more once cgks_adjoint_solve
- * has run), released with the context.  Its dual-number kernels also need about 12 KB of
- * scratch memory per GPU lane in flight (a few GB), which the HIP runtime allocates at launch:
+ * has run), released with the context.  Its dual-number kernels also need about 2.3 KB of
+ * scratch memory per GPU lane in flight (up to a few GB), which the HIP runtime allocates at launch:
  * leave that much device memory free beyond the tape (the runtime aborts the queue, rather
  * than return an error, when it cannot get it).  If the tape itself does not fit, CGKS_E_DEVICE
  * says how much it needs.  CGKS_E_PHYS if a Gauss-point state is non-physical.  Any later

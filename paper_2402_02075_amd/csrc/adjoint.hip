@@ -77,7 +77,10 @@ __device__ __forceinline__ void unpack(const double2 &v, double e[2])
     e[0] = v.x;
     e[1] = v.y;
 }
-constexpr int K_FACE = 4;   // tangent directions per pass of the Gauss-point Jacobian
+// tangent directions per pass of the Gauss-point Jacobian: one (41 passes) keeps each lane's
+// dual numbers to twice the flux's own registers, so a pass spills 2.3 KB per lane; four tangents
+// spill 12 KB and eight 18.5 KB, and the whole linearisation takes 2.7 and 4.3 times as long
+constexpr int K_FACE = 1;
 constexpr int K_RECON = 6;  // tangent directions per pass of the reconstruction Jacobian
 
 static inline dim3 B1(int64_t n, int bs = 256) { return dim3(blocks_for(n > 0 ? n : 1, bs)); }
