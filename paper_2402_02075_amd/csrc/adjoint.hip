@@ -58,9 +58,10 @@ template <int JG> __host__ __device__ constexpr int64_t jf_at(int64_t s, int64_t
     return ((s >> 6) * JRP + (r / JG) * JG) * 64 + (s & 63) * JG + (r % JG);
 }
 __host__ __device__ constexpr size_t jf_size(int64_t n) { return (size_t)((n + 63) >> 6) * 64 * JRP; }
-// The reconstruction Jacobians: entry r = 30 o + q of column t = c N + i (component c, cell i) at
+// The reconstruction Jacobians: entry r = 30 o + q of column t = 5 i + c (cell i, component c) at
 // ((r / JG) 5N + t) JG + r % JG: row-major over the columns, so that the 64 consecutive columns of
-// a wave read one contiguous kilobyte per load, in runs of JG = 16 / (entry size) entries.
+// a wave read one contiguous kilobyte per load, in runs of JG = 16 / (entry size) entries; the
+// columns are cell-major, so that the cotangents they produce are cell-major too.
 template <int JG> __host__ __device__ constexpr int64_t jr_at(int64_t t, int64_t r, int64_t N5)
 {
     return ((r / JG) * N5 + t) * JG + (r % JG);
@@ -451,7 +452,7 @@ template <int K, int C, class TJ> __device__ __forceinline__ void recon_jac_comp
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int q = pass * K + j;
-            if (q < RECON_IN) Jr[jr_at<16 / sizeof(TJ)>(C * N + i, o * RECON_IN + q, 5 * N)] = (TJ)r[o].d[j];
+            if (q < RECON_IN) Jr[jr_at<16 / sizeof(TJ)>(5 * i + C, o * RECON_IN + q, 5 * N)] = (TJ)r[o].d[j];
         }
 }
 
@@ -468,15 +469,17 @@ template <int K, class TJ> __global__ __launch_bounds__(320) void k_recon_jac(Re
     }
 }
 
-// per (component, cell): input cotangents = Jr^T (coefficient cotangents)
+// per (cell, component): input cotangents = Jr^T (coefficient cotangents).  Outputs cell-major:
+// bown[30 i + 6 c + q] (own state, compression factor), bslot[120 i + 20 s + 4 c + d] (value and
+// gradient of the neighbour in slot s), so that a cell's 20 values for one slot are contiguous
 template <class TJ>
 __global__ __launch_bounds__(256) void k_recon_vjp(int64_t N, const TJ *Jr, const double *bcoef, double *bown,
                                                    double *bslot)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 5 * N) return;
-    const int C = (int)(t / N);
-    const int64_t i = t - C * N;
+    const int64_t i = t / 5;  // the five component threads of a cell are neighbouring lanes
+    const int C = (int)(t - 5 * i);
     double br[10];
 #pragma unroll
     for (int o = 0; o < 10; ++o) br[o] = bcoef[i * 50 + 10 * C + o];
@@ -504,8 +507,8 @@ __global__ __launch_bounds__(256) void k_recon_vjp(int64_t N, const TJ *Jr, cons
     }
 #pragma unroll
     for (int q = 0; q < RECON_IN; ++q) {
-        if (q < 6) bown[(C * 6 + q) * N + i] = s[q];
-        else bslot[((int64_t)(C * 6 + (q - 6) / 4) * 4 + (q - 6) % 4) * N + i] = s[q];
+        if (q < 6) bown[i * 30 + C * 6 + q] = s[q];
+        else bslot[i * 120 + ((q - 6) / 4) * 20 + C * 4 + (q - 6) % 4] = s[q];
     }
 }
 
@@ -523,11 +526,11 @@ __global__ __launch_bounds__(256) void k_recon_gather(int64_t N, const int32_t *
     for (int c = 0; c < 5; ++c) {
         double s = 0.0;
 #pragma unroll
-        for (int C = 0; C < 5; ++C) s += bown[(C * 6 + c) * N + j];
+        for (int C = 0; C < 5; ++C) s += bown[j * 30 + C * 6 + c];
         bw[c] = s + t * ddt[c * N + j];
     }
 #pragma unroll
-    for (int C = 0; C < 5; ++C) ba += bown[(C * 6 + 5) * N + j];
+    for (int C = 0; C < 5; ++C) ba += bown[j * 30 + C * 6 + 5];
 #pragma unroll
     for (int q = 0; q < 15; ++q) bg[q] = 0.0;
     for (int s = 0; s < 6; ++s) {
@@ -538,10 +541,10 @@ __global__ __launch_bounds__(256) void k_recon_gather(int64_t N, const int32_t *
         if (rs < 0) continue;
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            const double *b = bslot + ((int64_t)(c * 6 + rs) * 4) * N + nbv;
+            const double *b = bslot + (int64_t)nbv * 120 + rs * 20 + c * 4;
             bw[c] += b[0];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) bg[3 * c + d] += b[(1 + d) * N];
+            for (int d = 0; d < 3; ++d) bg[3 * c + d] += b[1 + d];
         }
     }
 #pragma unroll
