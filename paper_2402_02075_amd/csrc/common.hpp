@@ -114,7 +114,7 @@ struct AdjTape {
     DBuf<double> agp;          // CF factor per Gauss-point slot (NS)
     bool fp32 = false;         // Jacobians stored in FP32 (params.adjoint_tape = 1)
     DBuf<double> Jf;           // Gauss-point Jacobians, 11*41 per compact Gauss point, 64-column tiles
-    DBuf<double> Jr;           // reconstruction Jacobians, 10*30 per (component, cell) column (jr_at)
+    DBuf<double> Jr;           // reconstruction Jacobians, 10*30 per (cell, component) column (jr_at)
     DBuf<float> Jf32, Jr32;    // the same in FP32
     DBuf<int8_t> rev;          // [6][N] slot of the same face in the neighbour's list
     // cotangent work buffers
